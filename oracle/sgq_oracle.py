@@ -1,0 +1,533 @@
+"""Plain FP64 CPU oracle for the spectral Gauss-quadrature electron density.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import, call or run
+this module; only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline``
+leg of ``bench.py`` use it.  It shares no code with the HIP library: the only
+common module is the seeded input generator ``paper_1907_02604_amd.synth``, which
+holds no quadrature arithmetic.
+
+What it computes (paper: Sec. "Density Functional Theory"):
+
+* the Fermi-Dirac density matrix gamma = g(H; mu), g = 1/(1+exp((lam-mu)/kT))
+  (Eq. eq:dm);
+* for every node p the K-point Gauss rule (lambda_k, w_k) of the spectral measure
+  of H contracted with the FD basis function eta_p (Eq. eq:9), obtained by a
+  K-step Lanczos iteration started from eta_p (paragraph after Eq.
+  Eqn:LSSGQ:Electron_density:GQ) and the eigen-decomposition of the Lanczos
+  tridiagonal (nodes = eigenvalues, weights = squared first eigenvector
+  components);
+* rho_p = 2 h^-3 sum_k w_k g(lambda_k) (Eq. Eqn:LSSGQ:Electron_density:GQ);
+* the per-node band / free-energy term e_p = 2 sum_k w_k F(lambda_k) (the first and
+  last terms of Eq. eq:tot) and the weighted sum Omega = sum_q n_q e_q
+  (Eq. eq:free_cg);
+* the exact-arithmetic adjoint of Omega with respect to the local potential,
+  the projector energies and the atom positions (reverse mode through the
+  Lanczos three-term recurrence and the Daleckii-Krein derivative of F(T)).
+
+Everything is float64 and written for readability, not speed: one node at a
+time, numpy array ops for the stencil, a library tridiagonal eigensolver.
+
+Readings where the paper is silent (each is listed in the design notes):
+* H = -1/2 Lap_6 + V_loc + V_nl on the grid, where Lap_6 is the sixth-order
+  central finite-difference Laplacian applied axis by axis (no cross terms);
+* node truncation: H_q = P_q H P_q on a cube of side 2R+1 centred at the node,
+  indices wrapping periodically into the global grid, zero outside the cube;
+  R = -1 means the untruncated periodic Hamiltonian;
+* start vector = unit vector at the node (the orthonormal FD basis function);
+* full classical Gram-Schmidt reorthogonalisation each step, repeated once when
+  the norm drops by more than 1/sqrt(2); breakdown when beta <= tau * scale with
+  scale = 9.0667/h^2 + max|V|, after which the rule has K_eff < K nodes and is exact;
+* integrands F: BAND F = lam*g; FREE (Mermin) F = lam*g + kT[g ln g + (1-g) ln(1-g)]
+  = mu*g - kT*softplus(-(lam-mu)/kT); GRAND F = -kT*softplus(-(lam-mu)/kT).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import scipy.integrate
+import scipy.linalg
+import scipy.sparse
+
+BAND, FREE, GRAND = 0, 1, 2
+
+# Sixth-order central weights of d^2/dx^2 for offsets 0, +-1, +-2, +-3 (times 1/h^2).
+FD2_WEIGHTS = (-49.0 / 18.0, 3.0 / 2.0, -3.0 / 20.0, 1.0 / 90.0)
+
+TAU_FP64 = 1e-12
+
+
+# --------------------------------------------------------------------------------------
+# Fermi-Dirac occupation and integrands (Eq. eq:dm, Eq. eq:tot)
+# --------------------------------------------------------------------------------------
+def fermi(lam, mu, kT):
+    """g(lam) = 1/(1 + exp((lam - mu)/kT)), evaluated without overflow."""
+    x = (np.asarray(lam, dtype=np.float64) - mu) / kT
+    out = np.empty_like(x)
+    pos = x > 0
+    e = np.exp(-x[pos])
+    out[pos] = e / (1.0 + e)
+    out[~pos] = 1.0 / (1.0 + np.exp(x[~pos]))
+    return out
+
+
+def softplus(x):
+    """ln(1 + exp(x)) without overflow."""
+    x = np.asarray(x, dtype=np.float64)
+    return np.maximum(x, 0.0) + np.log1p(np.exp(-np.abs(x)))
+
+
+def integrand(lam, mu, kT, kind):
+    """F(lam) for the per-node energy e = 2 sum_k w_k F(lam_k)."""
+    lam = np.asarray(lam, dtype=np.float64)
+    g = fermi(lam, mu, kT)
+    if kind == BAND:
+        return lam * g
+    sp = kT * softplus(-(lam - mu) / kT)
+    if kind == FREE:
+        return mu * g - sp
+    if kind == GRAND:
+        return -sp
+    raise ValueError(kind)
+
+
+def integrand_deriv(lam, mu, kT, kind):
+    """dF/dlam."""
+    lam = np.asarray(lam, dtype=np.float64)
+    g = fermi(lam, mu, kT)
+    dg = -g * (1.0 - g) / kT
+    if kind == BAND:
+        return g + lam * dg
+    if kind == FREE:
+        return g + mu * dg
+    if kind == GRAND:
+        return g
+    raise ValueError(kind)
+
+
+def divided_differences(theta, mu, kT, kind):
+    """D[k, l] = (F(theta_k) - F(theta_l)) / (theta_k - theta_l), F'(midpoint) when the
+    two nodes are closer than 1e-6*max(kT, |theta|)."""
+    theta = np.asarray(theta, dtype=np.float64)
+    F = integrand(theta, mu, kT, kind)
+    a = theta[:, None]
+    b = theta[None, :]
+    diff = a - b
+    close = np.abs(diff) <= 1e-6 * np.maximum(kT, np.maximum(np.abs(a), np.abs(b)))
+    safe = np.where(close, 1.0, diff)
+    D = (F[:, None] - F[None, :]) / safe
+    mid = integrand_deriv(0.5 * (a + b), mu, kT, kind)
+    return np.where(close, mid, D)
+
+
+# --------------------------------------------------------------------------------------
+# Kleinman-Bylander projectors (s, px, py, pz Gaussians with a smooth cutoff)
+# --------------------------------------------------------------------------------------
+def projector_norms(rg, rc):
+    """Continuum normalisation constants (N_s, N_p) so that the integral of chi^2
+    over R^3 is one for every channel."""
+    def cut(r):
+        return (1.0 - (r / rc) ** 2) ** 3
+
+    def gs(r):
+        return math.exp(-r * r / (2.0 * rg * rg)) * cut(r)
+
+    i_s = scipy.integrate.quad(lambda r: 4.0 * math.pi * r * r * gs(r) ** 2, 0.0, rc,
+                               epsabs=0, epsrel=1e-13, limit=200)[0]
+    # p_x = (x/rg) g c; angular average of x^2 is r^2/3
+    i_p = scipy.integrate.quad(lambda r: 4.0 * math.pi * r * r * (r * r / (3.0 * rg * rg)) * gs(r) ** 2,
+                               0.0, rc, epsabs=0, epsrel=1e-13, limit=200)[0]
+    return 1.0 / math.sqrt(i_s), 1.0 / math.sqrt(i_p)
+
+
+def projector_values(d, rg, rc, norms):
+    """chi_l(d) for displacement d = x - R_J (..., 3) bohr -> (..., 4): s, px, py, pz."""
+    Ns, Np = norms
+    d = np.asarray(d, dtype=np.float64)
+    r2 = np.sum(d * d, axis=-1)
+    inside = r2 < rc * rc
+    g = np.exp(-r2 / (2.0 * rg * rg)) * np.where(inside, (1.0 - r2 / (rc * rc)) ** 3, 0.0)
+    out = np.empty(d.shape[:-1] + (4,))
+    out[..., 0] = Ns * g
+    for a in range(3):
+        out[..., 1 + a] = Np * (d[..., a] / rg) * g
+    return out
+
+
+def projector_gradients(d, rg, rc, norms):
+    """d chi_l / d d_a for displacement d (..., 3) -> (..., 4, 3).  (d chi/d R = -this.)"""
+    Ns, Np = norms
+    d = np.asarray(d, dtype=np.float64)
+    r2 = np.sum(d * d, axis=-1)
+    inside = r2 < rc * rc
+    e = np.exp(-r2 / (2.0 * rg * rg))
+    t = np.where(inside, 1.0 - r2 / (rc * rc), 0.0)
+    g = e * t ** 3
+    # d g / d d_a = d_a * e * [ -t^3 / rg^2 - 6 t^2 / rc^2 ]
+    dg_over_d = e * (-(t ** 3) / (rg * rg) - 6.0 * t * t / (rc * rc))
+    out = np.empty(d.shape[:-1] + (4, 3))
+    for a in range(3):
+        out[..., 0, a] = Ns * dg_over_d * d[..., a]
+    for l in range(3):
+        for a in range(3):
+            val = Np / rg * d[..., l] * dg_over_d * d[..., a]
+            if l == a:
+                val = val + Np / rg * g
+            out[..., 1 + l, a] = val
+    return out
+
+
+# --------------------------------------------------------------------------------------
+# The node Hamiltonian H_q (Eq. Eqn:Hamiltonian discretised on the FD grid)
+# --------------------------------------------------------------------------------------
+def kinetic_apply(v, h, periodic):
+    """-1/2 Lap_6 v on a (z, y, x) array; zero outside the box unless periodic."""
+    out = 3.0 * FD2_WEIGHTS[0] * v
+    for axis in range(3):
+        for d in (1, 2, 3):
+            wgt = FD2_WEIGHTS[d]
+            if periodic:
+                out = out + wgt * (np.roll(v, d, axis=axis) + np.roll(v, -d, axis=axis))
+            else:
+                fwd = np.zeros_like(v)
+                bwd = np.zeros_like(v)
+                src = [slice(None)] * 3
+                dst = [slice(None)] * 3
+                src[axis] = slice(0, v.shape[axis] - d)
+                dst[axis] = slice(d, v.shape[axis])
+                fwd[tuple(dst)] = v[tuple(src)]      # fwd[i] = v[i - d]
+                bwd[tuple(src)] = v[tuple(dst)]      # bwd[i] = v[i + d]
+                out = out + wgt * (fwd + bwd)
+    return (-0.5 / (h * h)) * out
+
+
+def kinetic_gershgorin(h):
+    """Gershgorin bound of -1/2 Lap_6: 3 * 1/2 * (49/18 + 2*(3/2 + 3/20 + 1/90)) / h^2."""
+    return 1.5 * (abs(FD2_WEIGHTS[0]) + 2.0 * sum(abs(w) for w in FD2_WEIGHTS[1:])) / (h * h)
+
+
+class NodeHamiltonian:
+    """H_q for one node of a problem (a ``synth.Problem``).
+
+    Periodic mode (half_width < 0): the whole grid, periodic stencil, the start
+    vector at the node.  Truncated mode: the cube of side s = 2R+1 around the node,
+    grid indices wrapping periodically, Dirichlet zero outside; requires
+    s <= n_a - 6 on every axis so that no coupling of H wraps around the cube."""
+
+    def __init__(self, prob, node, v_loc=None, atoms=None, proj_E=None):
+        self.h = float(prob.h)
+        nx, ny, nz = prob.n
+        v_loc = prob.v_loc if v_loc is None else v_loc
+        self.atoms = prob.atoms if atoms is None else atoms
+        self.proj_E = prob.proj_E if proj_E is None else proj_E
+        self.n_proj = int(prob.n_proj)
+        c = int(prob.centers[node])
+        cx, cy, cz = c % nx, (c // nx) % ny, c // (nx * ny)
+        R = int(prob.half_width[node])
+        self.periodic = R < 0
+        if self.periodic:
+            self.shape = (nz, ny, nx)
+            self.origin = (0, 0, 0)
+            self.start = (cz, cy, cx)
+            self.gz = np.arange(nz)
+            self.gy = np.arange(ny)
+            self.gx = np.arange(nx)
+        else:
+            s = 2 * R + 1
+            if s > min(nx, ny, nz) - 6:
+                raise ValueError("cube side exceeds grid size - 6")
+            self.shape = (s, s, s)
+            self.origin = (cz - R, cy - R, cx - R)
+            self.start = (R, R, R)
+            self.gz = np.mod(cz - R + np.arange(s), nz)
+            self.gy = np.mod(cy - R + np.arange(s), ny)
+            self.gx = np.mod(cx - R + np.arange(s), nx)
+        self.grid_n = (nz, ny, nx)
+        self.v = v_loc[np.ix_(self.gz, self.gy, self.gx)]
+        self.scale = kinetic_gershgorin(self.h) + float(np.max(np.abs(v_loc)))
+        self._build_projectors()
+
+    # -- projector columns restricted to the cube -----------------------------------
+    def _local_index(self, gz, gy, gx):
+        """Flat local index of global points, or -1 when outside the cube."""
+        nz, ny, nx = self.grid_n
+        if self.periodic:
+            return (np.mod(gz, nz) * ny + np.mod(gy, ny)) * nx + np.mod(gx, nx)
+        s = self.shape[0]
+        lz = np.mod(gz - self.origin[0], nz)
+        ly = np.mod(gy - self.origin[1], ny)
+        lx = np.mod(gx - self.origin[2], nx)
+        ok = (lz < s) & (ly < s) & (lx < s)
+        return np.where(ok, (lz * s + ly) * s + lx, -1)
+
+    def _build_projectors(self):
+        self.proj_atoms = []
+        self.chi = None
+        if self.n_proj == 0 or self.atoms.shape[0] == 0:
+            return
+        h = self.h
+        self.norms = projector_norms(0.5, 1.5)
+        # grid points within rc of R lie within ceil(rc/h + 1/2) of the nearest grid point
+        m = int(math.ceil(1.5 / h + 0.5))
+        offs = np.arange(-m, m + 1)
+        oz, oy, ox = np.meshgrid(offs, offs, offs, indexing="ij")
+        rows, cols, vals, dvals = [], [], [], []
+        col = 0
+        npts = int(np.prod(self.shape))
+        for J in range(self.atoms.shape[0]):
+            RJ = self.atoms[J]
+            g0 = np.rint(RJ / h).astype(np.int64)
+            px = (g0[0] + ox).ravel()
+            py = (g0[1] + oy).ravel()
+            pz = (g0[2] + oz).ravel()
+            disp = np.stack([px * h - RJ[0], py * h - RJ[1], pz * h - RJ[2]], axis=-1)
+            chi = projector_values(disp, 0.5, 1.5, self.norms)          # (box, 4)
+            dchi = projector_gradients(disp, 0.5, 1.5, self.norms)      # (box, 4, 3)
+            li = self._local_index(pz, py, px)
+            keep = (li >= 0) & np.any(chi != 0.0, axis=1)
+            if not np.any(keep):
+                continue
+            self.proj_atoms.append(J)
+            for l in range(4):
+                rows.append(li[keep])
+                cols.append(np.full(int(keep.sum()), col + l))
+                vals.append(chi[keep, l])
+                dvals.append(dchi[keep, l, :])
+            col += 4
+        r = np.concatenate(rows)
+        cidx = np.concatenate(cols)
+        # duplicates (several images of one atom on a tiny periodic grid) are summed
+        self.chi = scipy.sparse.csr_matrix((np.concatenate(vals), (r, cidx)), shape=(npts, col))
+        dv = np.concatenate(dvals)
+        self.dchi = [scipy.sparse.csr_matrix((dv[:, a], (r, cidx)), shape=(npts, col))
+                     for a in range(3)]
+        self.E_cols = np.concatenate([self.proj_E[J] for J in self.proj_atoms])
+
+    # -- matvec -------------------------------------------------------------------
+    def apply(self, vec):
+        """H_q vec for a flat vector over the cube points."""
+        v3 = vec.reshape(self.shape)
+        out = kinetic_apply(v3, self.h, self.periodic) + self.v * v3
+        out = out.ravel()
+        if self.chi is not None:
+            h3 = self.h ** 3
+            coef = h3 * (self.chi.T @ vec)
+            out = out + self.chi @ (self.E_cols * coef)
+        return out
+
+    def start_vector(self):
+        e = np.zeros(self.shape)
+        e[self.start] = 1.0
+        return e.ravel()
+
+    def dense(self):
+        n = int(np.prod(self.shape))
+        I = np.eye(n)
+        return np.stack([self.apply(I[:, i]) for i in range(n)], axis=1)
+
+
+# --------------------------------------------------------------------------------------
+# Lanczos iteration and the Gauss rule (paragraph after Eq. Eqn:LSSGQ:Electron_density:GQ)
+# --------------------------------------------------------------------------------------
+def lanczos(apply_H, start, K, scale, tau=TAU_FP64):
+    """K-step Lanczos from a unit start vector with full CGS reorthogonalisation.
+
+    Returns (alpha[K_eff], beta[K_eff - 1], Q[K_eff, n], beta_last) where T_K has
+    diagonal alpha and off-diagonal beta, and q_1..q_K_eff are the Lanczos vectors."""
+    n = start.size
+    Q = np.zeros((K, n))
+    alpha = np.zeros(K)
+    beta = np.zeros(K)
+    q = start.astype(np.float64).copy()
+    q_prev = np.zeros(n)
+    b_prev = 0.0
+    k_eff = K
+    for j in range(K):
+        Q[j] = q
+        u = apply_H(q)
+        a = float(q @ u)
+        w = u - a * q - b_prev * q_prev
+        for _ in range(2):
+            before = np.linalg.norm(w)
+            coef = Q[:j + 1] @ w
+            w = w - Q[:j + 1].T @ coef
+            if np.linalg.norm(w) >= before / math.sqrt(2.0):
+                break
+        b = float(np.linalg.norm(w))
+        alpha[j] = a
+        beta[j] = b
+        if j == K - 1:
+            break
+        if b <= tau * scale:
+            k_eff = j + 1
+            break
+        q_prev, q, b_prev = q, w / b, b
+    return alpha[:k_eff], beta[:k_eff - 1], Q[:k_eff], beta[k_eff - 1]
+
+
+def gauss_rule(alpha, beta, vectors=False):
+    """Nodes theta_k (eigenvalues of T) and weights w_k = (first eigenvector component)^2."""
+    if alpha.size == 1:
+        theta = alpha.copy()
+        S = np.ones((1, 1))
+    else:
+        theta, S = scipy.linalg.eigh_tridiagonal(alpha, beta)
+    w = S[0, :] ** 2
+    if vectors:
+        return theta, w, S
+    return theta, w
+
+
+def node_rule(prob, node, **overrides):
+    """(theta, w, K_eff) of one node."""
+    H = NodeHamiltonian(prob, node, **overrides)
+    K = int(prob.depth[node])
+    alpha, beta, _, _ = lanczos(H.apply, H.start_vector(), K, H.scale)
+    theta, w = gauss_rule(alpha, beta)
+    return theta, w, alpha.size
+
+
+def rho_quadrature(prob, nodes=None, mu=None, kT=None):
+    """rho_q = 2 h^-3 sum_k w_k g(theta_k) for every node (or the listed ones).
+    Returns (rho, k_eff)."""
+    mu = prob.mu if mu is None else mu
+    kT = prob.kT if kT is None else kT
+    nodes = range(prob.n_nodes) if nodes is None else nodes
+    rho, keff = [], []
+    for q in nodes:
+        theta, w, k = node_rule(prob, q)
+        rho.append(2.0 / prob.h ** 3 * float(np.sum(w * fermi(theta, mu, kT))))
+        keff.append(k)
+    return np.array(rho), np.array(keff, dtype=np.int32)
+
+
+def band_energy(prob, kind=FREE, nodes=None, mu=None, kT=None, **overrides):
+    """Per-node e_q = 2 sum_k w_k F(theta_k) and Omega = sum_q n_q e_q."""
+    mu = prob.mu if mu is None else mu
+    kT = prob.kT if kT is None else kT
+    nodes = list(range(prob.n_nodes)) if nodes is None else list(nodes)
+    e = []
+    for q in nodes:
+        theta, w, _ = node_rule(prob, q, **overrides)
+        e.append(2.0 * float(np.sum(w * integrand(theta, mu, kT, kind))))
+    e = np.array(e)
+    return e, float(np.sum(prob.weight[nodes] * e))
+
+
+# --------------------------------------------------------------------------------------
+# Adjoint of Omega (reverse mode through the exact-arithmetic Lanczos recurrence)
+# --------------------------------------------------------------------------------------
+def tbar_from_rule(theta, S, mu, kT, kind):
+    """Adjoint of e = 2 e_1^T F(T) e_1 with respect to a symmetric T:
+    Tbar = 2 S (D o s1 s1^T) S^T (Daleckii-Krein), D the divided differences of F."""
+    s1 = S[0, :]
+    D = divided_differences(theta, mu, kT, kind)
+    return 2.0 * S @ (D * np.outer(s1, s1)) @ S.T
+
+
+def node_backward(prob, node, kind, scale, **overrides):
+    """Gradient of scale * e_node.  Returns (H, vbar over cube points, Ebar per
+    projector column, Rbar_nl per projector atom (n_atoms_local, 3))."""
+    H = NodeHamiltonian(prob, node, **overrides)
+    K = int(prob.depth[node])
+    alpha, beta, Q, _ = lanczos(H.apply, H.start_vector(), K, H.scale)
+    Ke = alpha.size
+    theta, w, S = gauss_rule(alpha, beta, vectors=True)
+    Tb = scale * tbar_from_rule(theta, S, prob.mu, prob.kT, kind)
+    abar = np.diag(Tb).copy()
+    bbar = np.array([2.0 * Tb[j, j + 1] for j in range(Ke - 1)])
+    n = Q.shape[1]
+    qbar = np.zeros((Ke, n))
+    vbar = np.zeros(n)
+    pairs = []                       # (u_bar_j, q_j) for the projector adjoints
+    for j in range(Ke - 1, -1, -1):
+        qj = Q[j]
+        uj = H.apply(qj)
+        if j < Ke - 1:
+            qn = Q[j + 1]
+            bb = bbar[j] - float(qbar[j + 1] @ qn) / beta[j]
+            rbar = qbar[j + 1] / beta[j] + bb * qn
+        else:
+            rbar = np.zeros(n)
+        ahat = abar[j] - float(rbar @ qj)
+        ubar = rbar + ahat * qj
+        qbar[j] += -alpha[j] * rbar + ahat * uj + H.apply(ubar)
+        if j > 0:
+            qbar[j - 1] += -beta[j - 1] * rbar
+            bbar[j - 1] -= float(rbar @ Q[j - 1])
+        vbar += ubar * qj
+        pairs.append((ubar, qj))
+    Ebar = None
+    Rbar = None
+    if H.chi is not None:
+        h3 = H.h ** 3
+        ncol = H.chi.shape[1]
+        Ebar = np.zeros(ncol)
+        Rbar = np.zeros((len(H.proj_atoms), 3))
+        for ub, qj in pairs:
+            cu = H.chi.T @ ub
+            cq = H.chi.T @ qj
+            Ebar += h3 * cu * cq
+            for a in range(3):
+                du = H.dchi[a].T @ ub
+                dq = H.dchi[a].T @ qj
+                # d chi / d R = - d chi / d d
+                contrib = -h3 * H.E_cols * (du * cq + cu * dq)
+                Rbar[:, a] += contrib.reshape(-1, 4).sum(axis=1)
+    return H, vbar, Ebar, Rbar
+
+
+def band_energy_backward(prob, kind=FREE, grad_omega=1.0, nodes=None):
+    """dOmega/dV on the global grid (z, y, x), dOmega/dE (M, 4) and the nonlocal
+    part of dOmega/dR (M, 3)."""
+    nodes = list(range(prob.n_nodes)) if nodes is None else list(nodes)
+    nz, ny, nx = prob.n[2], prob.n[1], prob.n[0]
+    dV = np.zeros((nz, ny, nx))
+    M = prob.atoms.shape[0]
+    dE = np.zeros((M, 4))
+    dR = np.zeros((M, 3))
+    for q in nodes:
+        H, vbar, Ebar, Rbar = node_backward(prob, q, kind, grad_omega * prob.weight[q])
+        cube = vbar.reshape(H.shape)
+        dV[np.ix_(H.gz, H.gy, H.gx)] += cube
+        if Ebar is not None:
+            for i, J in enumerate(H.proj_atoms):
+                dE[J] += Ebar[4 * i:4 * i + 4]
+                dR[J] += Rbar[i]
+    return dV, dE, dR
+
+
+def vloc_position_gradient(dV, n, h, atoms, depth, sigma, cutoff):
+    """sum_x dV(x) dV_loc(x)/dR_J for the Gaussian local potential
+    V(x) = depth sum_J sum_images exp(-|x - R_J - L m|^2 / (2 sigma^2)) (terms with
+    distance <= cutoff*sigma), so dV/dR_J = depth exp(..) (x - R_J - L m)/sigma^2."""
+    nx, ny, nz = n
+    rcut = cutoff * sigma
+    wdt = int(math.ceil(rcut / h)) + 1
+    offs = np.arange(-wdt, wdt + 1)
+    out = np.zeros((atoms.shape[0], 3))
+    for J in range(atoms.shape[0]):
+        g = np.floor(atoms[J] / h).astype(np.int64)
+        ix, iy, iz = g[0] + offs, g[1] + offs, g[2] + offs
+        dx = (ix * h - atoms[J, 0])[None, None, :]
+        dy = (iy * h - atoms[J, 1])[None, :, None]
+        dz = (iz * h - atoms[J, 2])[:, None, None]
+        r2 = dx * dx + dy * dy + dz * dz
+        e = np.where(r2 <= rcut * rcut, np.exp(-r2 / (2.0 * sigma * sigma)), 0.0)
+        sub = dV[np.ix_(np.mod(iz, nz), np.mod(iy, ny), np.mod(ix, nx))]
+        base = depth * e * sub / (sigma * sigma)
+        out[J, 0] = np.sum(base * dx)
+        out[J, 1] = np.sum(base * dy)
+        out[J, 2] = np.sum(base * dz)
+    return out
+
+
+# --------------------------------------------------------------------------------------
+# Error metrics
+# --------------------------------------------------------------------------------------
+def normwise_rel_err(got, ref):
+    """||got - ref||_inf / ||ref||_inf."""
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    den = np.max(np.abs(ref))
+    return float(np.max(np.abs(got - ref)) / den) if den > 0 else float(np.max(np.abs(got - ref)))
