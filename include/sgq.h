@@ -1,0 +1,155 @@
+/*
+ * sgq.h - C ABI of the MI355X spectral Gauss-quadrature density library (libsgq.so).
+ *
+ * What the library computes (paper: Sec. "Density Functional Theory"):
+ *   For every node p of a uniform periodic finite-difference grid, the K-point Gauss
+ *   rule (lambda_k, w_k) of the spectral measure of the Kohn-Sham Hamiltonian H
+ *   contracted with the orthonormal FD basis function eta_p (Eq. eq:9), obtained by
+ *   a K-step Lanczos iteration started from eta_p; from it the density
+ *   rho_p = 2 h^-3 sum_k w_k g(lambda_k) (Eq. Eqn:LSSGQ:Electron_density:GQ) with the
+ *   Fermi-Dirac occupation g of Eq. eq:dm, the per-node energy term
+ *   e_p = 2 sum_k w_k F(lambda_k) (band and entropy terms of Eq. eq:tot) and the
+ *   node-weighted sum Omega = sum_q n_q e_q (Eq. eq:free_cg), plus the adjoint of
+ *   Omega with respect to the local potential, projector energies and atom positions.
+ *
+ *   H = -1/2 Lap_6 + V_loc + V_nl, Lap_6 the sixth-order central FD Laplacian (axis
+ *   stencil), V_loc a grid potential, V_nl = sum_J sum_l |chi_Jl> E_Jl <chi_Jl| with
+ *   <chi|v> = h^3 sum_x chi(x) v(x) and four Gaussian projectors per atom
+ *   (s, px, py, pz) of width proj_rg and smooth cutoff proj_rc (bohr).
+ *   Node truncation: H_q is H restricted to the cube of side 2R+1 around the node
+ *   (grid indices wrap periodically, Dirichlet zero outside); R = -1 keeps the whole
+ *   periodic grid.
+ *
+ * Conventions
+ *   - Grid arrays are [z][y][x] with x fastest: linear index ix + nx*(iy + ny*iz).
+ *   - Every array argument of a compute call is a DEVICE pointer owned by the caller,
+ *     contiguous, of the stated type and length.  Host arrays are passed only to
+ *     sgq_plan_create.
+ *   - Compute calls are asynchronous on `stream` (a hipStream_t; NULL = default
+ *     stream).  Inputs must stay valid until the stream reaches the call.
+ *   - Every function returns an sgq_status and never throws.  Argument errors found
+ *     on the host are returned before anything is launched; errors found by the GPU
+ *     (non-finite input, a node touching more atoms than the library supports) are
+ *     latched in the plan and reported by sgq_plan_status.
+ *   - A plan is not thread-safe: calls on one plan must be serialised by the caller
+ *     (they share the plan's workspace).
+ */
+#ifndef SGQ_H
+#define SGQ_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SGQ_OK = 0,
+  SGQ_EINVAL = -1,      /* invalid argument (null pointer, bad size, kT <= 0, ...) */
+  SGQ_ENOMEM = -2,      /* device allocation failed at plan creation */
+  SGQ_EHIP = -3,        /* a HIP runtime call failed */
+  SGQ_EPLAN = -4,       /* the call does not match the plan (e.g. no projectors planned) */
+  SGQ_ENONFINITE = -5,  /* device status: NaN/Inf in an input */
+  SGQ_ELIMIT = -6       /* device status: a node overlaps more atoms than supported */
+} sgq_status;
+
+enum { SGQ_FP64 = 0, SGQ_FP32 = 1 };           /* storage / matvec precision */
+enum { SGQ_BAND = 0, SGQ_FREE = 1, SGQ_GRAND = 2 };
+
+/* Integrands F of e_p = 2 sum_k w_k F(lambda_k), x = (lambda - mu)/kT, g = 1/(1+e^x):
+ *   SGQ_BAND  F = lambda g                                  (first term of Eq. eq:tot)
+ *   SGQ_FREE  F = lambda g + kT [g ln g + (1-g) ln(1-g)]    (Mermin free energy)
+ *   SGQ_GRAND F = -kT ln(1 + e^-x)                          (grand potential)      */
+
+typedef struct {
+  int32_t n[3];          /* global grid points (nx, ny, nz), each >= 1 */
+  double h;              /* grid spacing, bohr, > 0 */
+  int32_t n_atoms;       /* M >= 0 */
+  int32_t n_proj;        /* 0 (local potential only) or 4 (s, px, py, pz) */
+  double proj_rc;        /* projector cutoff radius, bohr (> 0 when n_proj = 4) */
+  double proj_rg;        /* projector Gaussian width, bohr (> 0 when n_proj = 4) */
+  int32_t n_nodes;       /* Nq >= 0 */
+  int32_t precision;     /* SGQ_FP64 or SGQ_FP32 (dots, tridiagonal and quadrature are FP64) */
+} sgq_problem;
+
+typedef struct sgq_plan sgq_plan;
+
+/* Create a plan for a fixed grid and node set.  Host arrays of length n_nodes:
+ *   center[q]     linear grid index of node q, in [0, nx*ny*nz)
+ *   half_width[q] R_q >= 0 (cube side 2R_q+1 <= min(n) - 6) or -1 (whole periodic grid)
+ *   depth[q]      Lanczos depth K_q in [1, 128]
+ * Sorts the nodes by cost for the persistent launch and allocates the device
+ * workspace (SGQ_ENOMEM if that fails).  Synchronous.  *out receives the plan. */
+int sgq_plan_create(const sgq_problem* prob, const int64_t* center, const int32_t* half_width,
+                    const int32_t* depth, sgq_plan** out);
+
+int sgq_plan_destroy(sgq_plan* plan);
+
+/* Density at every node.
+ *   v_loc   [nz*ny*nx] double   local potential, Ha
+ *   atom_R  [M*3]      double   atom positions (x, y, z), bohr; NULL allowed when M = 0
+ *   proj_E  [M*4]      double   projector energies, Ha; NULL allowed when n_proj = 0
+ *   mu, kT                      Fermi level and temperature, Ha (kT > 0)
+ *   rho     [Nq]       double   out: rho_q, electrons / bohr^3
+ *   theta_w [Nq*Kmax*2] double  out (optional, NULL): (lambda_k, w_k) of node q at
+ *                               [(q*Kmax + k)*2], zero beyond K_eff; Kmax = max depth
+ *   k_eff   [Nq]       int32    out (optional, NULL): nodes of the rule (< K_q after a
+ *                               Lanczos breakdown, when the rule is exact)           */
+int rho_quadrature(sgq_plan* plan, const double* v_loc, const double* atom_R,
+                   const double* proj_E, double mu, double kT, double* rho, double* theta_w,
+                   int32_t* k_eff, void* stream);
+
+/* Per-node energy term and the weighted sum (Eq. eq:tot first and entropy terms,
+ * Eq. eq:free_cg).
+ *   node_weight [Nq] double   n_q
+ *   integrand            SGQ_BAND, SGQ_FREE or SGQ_GRAND
+ *   e_node  [Nq] double       out: e_q = 2 sum_k w_k F(lambda_k), Ha
+ *   omega   [1]  double       out: Omega = sum_q n_q e_q, summed in a fixed order     */
+int band_energy(sgq_plan* plan, const double* v_loc, const double* atom_R,
+                const double* proj_E, const double* node_weight, double mu, double kT,
+                int integrand, double* e_node, double* omega, void* stream);
+
+/* Adjoint of Omega (reverse mode through the Lanczos recurrence; the Lanczos vectors
+ * of each node are recomputed from the start vector, the only checkpoint kept).
+ *   grad_omega [1] double        upstream dL/dOmega
+ *   dV    [nz*ny*nx] double      out: dL/dV_loc(x)
+ *   dR_nl [M*3] double           out: dL/dR_J through the projectors (NULL allowed when
+ *                                n_proj = 0); the local-potential part is
+ *                                sgq_vloc_gaussian_backward of dV
+ *   dE    [M*4] double           out (optional, NULL): dL/dE_Jl                       */
+int band_energy_backward(sgq_plan* plan, const double* v_loc, const double* atom_R,
+                         const double* proj_E, const double* node_weight, double mu,
+                         double kT, int integrand, const double* grad_omega, double* dV,
+                         double* dR_nl, double* dE, void* stream);
+
+/* Chain rule through the Gaussian local potential
+ *   V(x) = depth sum_J sum_images exp(-|x - R_J - L m|^2 / (2 sigma^2))
+ * keeping image terms with distance <= cutoff_sigmas * sigma:
+ *   dR[J] += sum_x dV(x) dV(x)/dR_J.
+ *   dV [nz*ny*nx] double, atom_R [M*3] double, dR [M*3] double (accumulated into). */
+int sgq_vloc_gaussian_backward(sgq_plan* plan, const double* dV, const double* atom_R,
+                               double depth, double sigma, double cutoff_sigmas, double* dR,
+                               void* stream);
+
+/* Wait for the plan's last call and report a latched device-side error (SGQ_OK,
+ * SGQ_ENONFINITE or SGQ_ELIMIT); the latch is cleared by the next compute call. */
+int sgq_plan_status(sgq_plan* plan, int32_t* host_status);
+
+/* Message of the last error raised on the calling thread ("" if none). */
+const char* sgq_last_error(void);
+
+/* Host-only Gauss rule of a symmetric tridiagonal (the same QR sweeps the kernels run):
+ *   alpha [K], beta [K-1] host arrays; theta [K] out ascending, weight [K] out = squared
+ *   first eigenvector components.  For testing the eigensolver on a CPU. */
+int sgq_gauss_rule_host(const double* alpha, const double* beta, int K, double* theta,
+                        double* weight);
+
+/* Validate a problem and node arrays without touching the GPU (no plan is made). */
+int sgq_validate(const sgq_problem* prob, const int64_t* center, const int32_t* half_width,
+                 const int32_t* depth);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SGQ_H */

@@ -1,0 +1,386 @@
+// Host side of libsgq: argument validation, plans (node order, workspace), the C ABI.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/sgq.h"
+#include "sgq_common.h"
+#include "tridiag.h"
+
+namespace sgq {
+hipError_t launch_forward(const LaunchParams& P, bool fp64, int grid, int block, int kg,
+                          hipStream_t s);
+hipError_t launch_setup(const LaunchParams& P, bool fp64, const double* v64, void* vstore,
+                        void* chi, int32_t* g0, double* vmax, hipStream_t s);
+hipError_t launch_weighted_sum(const double* e, const double* w, int n, double* out,
+                               hipStream_t s);
+hipError_t launch_backward(const LaunchParams& P, bool fp64, int grid, int block, int kg,
+                           hipStream_t s);
+hipError_t launch_backward_gather(const LaunchParams& P, bool fp64, const int32_t* cell_start,
+                                  const int32_t* cell_nodes, int cell, double* dV, double* dR,
+                                  double* dE, hipStream_t s);
+hipError_t launch_vloc_backward(const double* dV, const double* R, int M, int nx, int ny, int nz,
+                                double h, double depth, double sigma, double cutoff, double* dR,
+                                hipStream_t s);
+}  // namespace sgq
+
+using namespace sgq;
+
+static thread_local std::string g_error;
+
+static int fail(int code, const std::string& msg) {
+  g_error = msg;
+  return code;
+}
+
+#define HIP_OR_FAIL(expr)                                                             \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess) return fail(SGQ_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+struct sgq_plan {
+  sgq_problem prob{};
+  int device = 0;
+  int kmax = 0, box_m = 0, kg = 8, block = 256, grid = 0;
+  double norm_s = 0, norm_p = 0;
+  size_t npad = 0, slot_stride = 0, n_grid = 0;
+  bool fp64 = false;
+  std::vector<int32_t> h_center, h_hw, h_depth, h_order;
+  int32_t *d_order = nullptr, *d_center = nullptr, *d_hw = nullptr, *d_depth = nullptr;
+  void *d_W = nullptr, *d_U = nullptr, *d_v = nullptr, *d_chi = nullptr;
+  int32_t* d_g0 = nullptr;
+  double* d_vmax = nullptr;
+  int* d_queue = nullptr;
+  int* d_status = nullptr;
+  double* d_enode = nullptr;
+  // backward state (allocated on first use)
+  void* d_U2 = nullptr;
+  double* d_tri = nullptr;
+  void* d_P = nullptr;
+  int64_t* d_cube_off = nullptr;
+  double* d_dRp = nullptr;
+  double* d_dEp = nullptr;
+  int32_t* d_node_atoms = nullptr;
+  int32_t* d_cell_start = nullptr;
+  int32_t* d_cell_nodes = nullptr;
+  int cell = 8;
+  hipStream_t last = nullptr;
+  std::vector<void*> allocs;
+};
+
+static void free_all(sgq_plan* p) {
+  for (void* a : p->allocs) hipFree(a);
+  p->allocs.clear();
+}
+
+template <typename T>
+static hipError_t dalloc(sgq_plan* p, T** out, size_t bytes) {
+  void* ptr = nullptr;
+  hipError_t e = hipMalloc(&ptr, bytes ? bytes : 16);
+  if (e == hipSuccess) {
+    p->allocs.push_back(ptr);
+    *out = reinterpret_cast<T*>(ptr);
+  }
+  return e;
+}
+
+static int box_half_width(double rc, double h) {
+  // grid offsets d from the nearest grid point that can lie within rc: d < rc/h + 1/2
+  return (int)std::ceil(rc / h + 0.5) - 1;
+}
+
+// Continuum normalisation of the projectors: int chi^2 d^3r = 1 (composite Simpson).
+static void projector_norms(double rg, double rc, double* ns, double* np_) {
+  const int n = 200000;
+  const double dr = rc / n;
+  double is = 0.0, ip = 0.0;
+  for (int i = 0; i <= n; ++i) {
+    double r = i * dr;
+    double t = 1.0 - (r * r) / (rc * rc);
+    double g = std::exp(-r * r / (2.0 * rg * rg)) * t * t * t;
+    double fs = 4.0 * M_PI * r * r * g * g;
+    double fp = fs * r * r / (3.0 * rg * rg);
+    double wgt = (i == 0 || i == n) ? 1.0 : ((i & 1) ? 4.0 : 2.0);
+    is += wgt * fs;
+    ip += wgt * fp;
+  }
+  is *= dr / 3.0;
+  ip *= dr / 3.0;
+  *ns = 1.0 / std::sqrt(is);
+  *np_ = 1.0 / std::sqrt(ip);
+}
+
+extern "C" const char* sgq_last_error(void) { return g_error.c_str(); }
+
+extern "C" int sgq_validate(const sgq_problem* prob, const int64_t* center,
+                            const int32_t* half_width, const int32_t* depth) {
+  if (!prob) return fail(SGQ_EINVAL, "problem is null");
+  for (int a = 0; a < 3; ++a)
+    if (prob->n[a] < 1) return fail(SGQ_EINVAL, "grid extent must be >= 1");
+  double ng = (double)prob->n[0] * prob->n[1] * prob->n[2];
+  if (ng >= 2147483647.0) return fail(SGQ_EINVAL, "grid has 2^31 or more points");
+  if (!(prob->h > 0.0) || !std::isfinite(prob->h)) return fail(SGQ_EINVAL, "h must be > 0");
+  if (prob->n_atoms < 0) return fail(SGQ_EINVAL, "n_atoms < 0");
+  if (prob->n_proj != 0 && prob->n_proj != 4) return fail(SGQ_EINVAL, "n_proj must be 0 or 4");
+  if (prob->precision != SGQ_FP64 && prob->precision != SGQ_FP32)
+    return fail(SGQ_EINVAL, "precision must be SGQ_FP64 or SGQ_FP32");
+  int m = 3;
+  if (prob->n_proj == 4) {
+    if (!(prob->proj_rc > 0.0) || !(prob->proj_rg > 0.0) || !std::isfinite(prob->proj_rc) ||
+        !std::isfinite(prob->proj_rg))
+      return fail(SGQ_EINVAL, "projector radii must be > 0");
+    m = std::max(3, box_half_width(prob->proj_rc, prob->h));
+    if (2 * m + 1 > 33) return fail(SGQ_EINVAL, "projector cutoff spans more than 33 points");
+  }
+  if (prob->n_nodes < 0) return fail(SGQ_EINVAL, "n_nodes < 0");
+  if (prob->n_nodes > 0 && (!center || !half_width || !depth))
+    return fail(SGQ_EINVAL, "node arrays are null");
+  int nmin = std::min(prob->n[0], std::min(prob->n[1], prob->n[2]));
+  for (int q = 0; q < prob->n_nodes; ++q) {
+    if (center[q] < 0 || (double)center[q] >= ng)
+      return fail(SGQ_EINVAL, "node " + std::to_string(q) + ": centre outside the grid");
+    if (depth[q] < 1 || depth[q] > kMaxDepth)
+      return fail(SGQ_EINVAL, "node " + std::to_string(q) + ": depth outside [1, 128]");
+    int R = half_width[q];
+    if (R < -1) return fail(SGQ_EINVAL, "node " + std::to_string(q) + ": half_width < -1");
+    if (R >= 0 && 2 * R + 1 > nmin - 2 * m)
+      return fail(SGQ_EINVAL, "node " + std::to_string(q) +
+                                  ": cube side exceeds the grid minus the stencil/projector reach");
+  }
+  return SGQ_OK;
+}
+
+extern "C" int sgq_plan_create(const sgq_problem* prob, const int64_t* center,
+                               const int32_t* half_width, const int32_t* depth, sgq_plan** out) {
+  if (!out) return fail(SGQ_EINVAL, "out is null");
+  *out = nullptr;
+  int st = sgq_validate(prob, center, half_width, depth);
+  if (st != SGQ_OK) return st;
+  sgq_plan* p = new sgq_plan();
+  p->prob = *prob;
+  p->fp64 = prob->precision == SGQ_FP64;
+  HIP_OR_FAIL(hipGetDevice(&p->device));
+  int ncu = 0;
+  HIP_OR_FAIL(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, p->device));
+  const int nq = prob->n_nodes;
+  p->n_grid = (size_t)prob->n[0] * prob->n[1] * prob->n[2];
+  p->box_m = prob->n_proj ? box_half_width(prob->proj_rc, prob->h) : 0;
+  if (prob->n_proj) projector_norms(prob->proj_rg, prob->proj_rc, &p->norm_s, &p->norm_p);
+  p->h_center.resize(nq);
+  p->h_hw.assign(half_width, half_width + nq);
+  p->h_depth.assign(depth, depth + nq);
+  size_t nmax = 1;
+  std::vector<double> cost(nq);
+  for (int q = 0; q < nq; ++q) {
+    p->h_center[q] = (int32_t)center[q];
+    size_t n = half_width[q] < 0 ? p->n_grid : (size_t)std::pow(2 * half_width[q] + 1, 3);
+    nmax = std::max(nmax, n);
+    p->kmax = std::max(p->kmax, (int)depth[q]);
+    double K = depth[q];
+    cost[q] = (double)n * (3.0 * K + K * (K + 1.0) / 2.0);
+  }
+  if (p->kmax == 0) p->kmax = 1;
+  p->h_order.resize(nq);
+  std::iota(p->h_order.begin(), p->h_order.end(), 0);
+  std::stable_sort(p->h_order.begin(), p->h_order.end(),
+                   [&](int a, int b) { return cost[a] > cost[b]; });
+  // basis vectors spanned by one lane group in the fused sweep
+  int kg_need = (p->kmax + 3) / 4;
+  p->kg = kg_need <= 8 ? 8 : (kg_need <= 16 ? 16 : 32);
+  p->block = 256;
+  int wg_per_cu = 2;
+  if (const char* env = std::getenv("SGQ_WG_PER_CU")) wg_per_cu = std::max(1, atoi(env));
+  if (const char* env = std::getenv("SGQ_BLOCK")) p->block = atoi(env) == 512 ? 512 : 256;
+  p->grid = std::max(1, std::min(nq, ncu * wg_per_cu));
+  p->npad = (nmax + 63) / 64 * 64;
+  p->slot_stride = (size_t)p->kmax * p->npad;
+  const size_t es = p->fp64 ? 8 : 4;
+  hipError_t e = hipSuccess;
+  e = e ? e : dalloc(p, &p->d_order, nq * 4);
+  e = e ? e : dalloc(p, &p->d_center, nq * 4);
+  e = e ? e : dalloc(p, &p->d_hw, nq * 4);
+  e = e ? e : dalloc(p, &p->d_depth, nq * 4);
+  e = e ? e : dalloc(p, &p->d_W, (size_t)p->grid * p->slot_stride * es);
+  e = e ? e : dalloc(p, &p->d_U, (size_t)p->grid * p->npad * es);
+  if (!p->fp64) e = e ? e : dalloc(p, &p->d_v, p->n_grid * es);
+  int B = 2 * p->box_m + 1;
+  if (prob->n_proj) {
+    e = e ? e : dalloc(p, &p->d_chi, (size_t)std::max(1, prob->n_atoms) * B * B * B * 4 * es);
+    e = e ? e : dalloc(p, &p->d_g0, (size_t)std::max(1, prob->n_atoms) * 3 * 4);
+  }
+  e = e ? e : dalloc(p, &p->d_vmax, 8);
+  e = e ? e : dalloc(p, &p->d_queue, 8);
+  e = e ? e : dalloc(p, &p->d_status, 8);
+  e = e ? e : dalloc(p, &p->d_enode, (size_t)nq * 8);
+  if (e != hipSuccess) {
+    free_all(p);
+    delete p;
+    (void)hipGetLastError();
+    return fail(SGQ_ENOMEM, std::string("device allocation failed: ") + hipGetErrorString(e));
+  }
+  e = hipMemcpy(p->d_order, p->h_order.data(), nq * 4, hipMemcpyHostToDevice);
+  e = e ? e : hipMemcpy(p->d_center, p->h_center.data(), nq * 4, hipMemcpyHostToDevice);
+  e = e ? e : hipMemcpy(p->d_hw, p->h_hw.data(), nq * 4, hipMemcpyHostToDevice);
+  e = e ? e : hipMemcpy(p->d_depth, p->h_depth.data(), nq * 4, hipMemcpyHostToDevice);
+  e = e ? e : hipMemset(p->d_status, 0, 8);
+  if (e != hipSuccess) {
+    free_all(p);
+    delete p;
+    return fail(SGQ_EHIP, std::string("plan upload failed: ") + hipGetErrorString(e));
+  }
+  *out = p;
+  return SGQ_OK;
+}
+
+extern "C" int sgq_plan_destroy(sgq_plan* plan) {
+  if (!plan) return SGQ_OK;
+  hipSetDevice(plan->device);
+  if (plan->last) hipStreamSynchronize(plan->last);
+  hipDeviceSynchronize();
+  free_all(plan);
+  delete plan;
+  return SGQ_OK;
+}
+
+static int check_call(sgq_plan* plan, const double* v_loc, const double* atom_R,
+                      const double* proj_E, double mu, double kT) {
+  if (!plan) return fail(SGQ_EINVAL, "plan is null");
+  if (!v_loc) return fail(SGQ_EINVAL, "v_loc is null");
+  if (!(kT > 0.0) || !std::isfinite(kT)) return fail(SGQ_EINVAL, "kT must be finite and > 0");
+  if (!std::isfinite(mu)) return fail(SGQ_EINVAL, "mu must be finite");
+  if (plan->prob.n_proj && plan->prob.n_atoms > 0 && (!atom_R || !proj_E))
+    return fail(SGQ_EINVAL, "atom_R and proj_E are required when projectors are planned");
+  return SGQ_OK;
+}
+
+static LaunchParams base_params(sgq_plan* p, const double* v_loc, const double* atom_R,
+                                const double* proj_E, double mu, double kT) {
+  LaunchParams P{};
+  P.nx = p->prob.n[0];
+  P.ny = p->prob.n[1];
+  P.nz = p->prob.n[2];
+  P.h = p->prob.h;
+  P.n_atoms = p->prob.n_atoms;
+  P.n_proj = p->prob.n_proj;
+  P.box_m = p->box_m;
+  P.proj_norm_s = p->norm_s;
+  P.proj_norm_p = p->norm_p;
+  P.proj_rg = p->prob.proj_rg;
+  P.proj_rc = p->prob.proj_rc;
+  P.n_nodes = p->prob.n_nodes;
+  P.order = p->d_order;
+  P.center = p->d_center;
+  P.half_width = p->d_hw;
+  P.depth = p->d_depth;
+  P.v = p->fp64 ? (const void*)v_loc : (const void*)p->d_v;
+  P.atom_R = atom_R;
+  P.proj_E = proj_E;
+  P.chi = p->d_chi;
+  P.atom_g0 = p->d_g0;
+  P.vmax = p->d_vmax;
+  P.mu = mu;
+  P.kT = kT;
+  P.tau = p->fp64 ? 1e-12 : 1e-6;
+  P.W = p->d_W;
+  P.U = p->d_U;
+  P.npad = p->npad;
+  P.slot_stride = p->slot_stride;
+  P.queue = p->d_queue;
+  P.status = p->d_status;
+  P.kmax_out = p->kmax;
+  return P;
+}
+
+static int run_forward(sgq_plan* p, LaunchParams& P, const double* v_loc, hipStream_t s) {
+  HIP_OR_FAIL(hipSetDevice(p->device));
+  HIP_OR_FAIL(launch_setup(P, p->fp64, v_loc, p->d_v, p->d_chi, p->d_g0, p->d_vmax, s));
+  if (p->prob.n_nodes > 0) HIP_OR_FAIL(launch_forward(P, p->fp64, p->grid, p->block, p->kg, s));
+  p->last = s;
+  return SGQ_OK;
+}
+
+extern "C" int rho_quadrature(sgq_plan* plan, const double* v_loc, const double* atom_R,
+                              const double* proj_E, double mu, double kT, double* rho,
+                              double* theta_w, int32_t* k_eff, void* stream) {
+  int st = check_call(plan, v_loc, atom_R, proj_E, mu, kT);
+  if (st != SGQ_OK) return st;
+  if (!rho && plan->prob.n_nodes > 0) return fail(SGQ_EINVAL, "rho is null");
+  LaunchParams P = base_params(plan, v_loc, atom_R, proj_E, mu, kT);
+  P.rho = rho;
+  P.theta_w = theta_w;
+  P.k_eff = k_eff;
+  P.integrand = 0;
+  return run_forward(plan, P, v_loc, (hipStream_t)stream);
+}
+
+extern "C" int band_energy(sgq_plan* plan, const double* v_loc, const double* atom_R,
+                           const double* proj_E, const double* node_weight, double mu, double kT,
+                           int integrand, double* e_node, double* omega, void* stream) {
+  int st = check_call(plan, v_loc, atom_R, proj_E, mu, kT);
+  if (st != SGQ_OK) return st;
+  if (!omega || (plan->prob.n_nodes > 0 && (!node_weight || !e_node)))
+    return fail(SGQ_EINVAL, "node_weight, e_node and omega are required");
+  if (integrand < SGQ_BAND || integrand > SGQ_GRAND) return fail(SGQ_EINVAL, "bad integrand");
+  LaunchParams P = base_params(plan, v_loc, atom_R, proj_E, mu, kT);
+  P.e_node = e_node;
+  P.integrand = integrand;
+  hipStream_t s = (hipStream_t)stream;
+  st = run_forward(plan, P, v_loc, s);
+  if (st != SGQ_OK) return st;
+  HIP_OR_FAIL(launch_weighted_sum(e_node, node_weight, plan->prob.n_nodes, omega, s));
+  return SGQ_OK;
+}
+
+extern "C" int band_energy_backward(sgq_plan* plan, const double* v_loc, const double* atom_R,
+                                    const double* proj_E, const double* node_weight, double mu,
+                                    double kT, int integrand, const double* grad_omega,
+                                    double* dV, double* dR_nl, double* dE, void* stream) {
+  (void)plan; (void)v_loc; (void)atom_R; (void)proj_E; (void)node_weight; (void)mu; (void)kT;
+  (void)integrand; (void)grad_omega; (void)dV; (void)dR_nl; (void)dE; (void)stream;
+  return fail(SGQ_EPLAN, "backward not built yet");
+}
+
+extern "C" int sgq_vloc_gaussian_backward(sgq_plan* plan, const double* dV, const double* atom_R,
+                                          double depth, double sigma, double cutoff_sigmas,
+                                          double* dR, void* stream) {
+  (void)plan; (void)dV; (void)atom_R; (void)depth; (void)sigma; (void)cutoff_sigmas; (void)dR;
+  (void)stream;
+  return fail(SGQ_EPLAN, "not built yet");
+}
+
+extern "C" int sgq_plan_status(sgq_plan* plan, int32_t* host_status) {
+  if (!plan || !host_status) return fail(SGQ_EINVAL, "null argument");
+  HIP_OR_FAIL(hipSetDevice(plan->device));
+  if (plan->last) HIP_OR_FAIL(hipStreamSynchronize(plan->last));
+  else HIP_OR_FAIL(hipDeviceSynchronize());
+  int bits = 0;
+  HIP_OR_FAIL(hipMemcpy(&bits, plan->d_status, 4, hipMemcpyDeviceToHost));
+  *host_status = (bits & kStatusNonFinite) ? SGQ_ENONFINITE
+                 : (bits & kStatusLimit)   ? SGQ_ELIMIT
+                                           : SGQ_OK;
+  return SGQ_OK;
+}
+
+extern "C" int sgq_gauss_rule_host(const double* alpha, const double* beta, int K, double* theta,
+                                   double* weight) {
+  if (!alpha || !theta || !weight || K < 1 || K > kMaxDepth || (K > 1 && !beta))
+    return fail(SGQ_EINVAL, "bad arguments");
+  double a[kMaxDepth], b[kMaxDepth], z[kMaxDepth];
+  for (int i = 0; i < K; ++i) a[i] = alpha[i];
+  for (int i = 0; i + 1 < K; ++i) b[i] = beta[i];
+  if (!tridiag_gauss(a, b, z, K)) return fail(SGQ_ENONFINITE, "tridiagonal QR did not converge");
+  std::vector<int> idx(K);
+  std::iota(idx.begin(), idx.end(), 0);
+  std::sort(idx.begin(), idx.end(), [&](int i, int j) { return a[i] < a[j]; });
+  for (int k = 0; k < K; ++k) {
+    theta[k] = a[idx[k]];
+    weight[k] = z[idx[k]] * z[idx[k]];
+  }
+  return SGQ_OK;
+}

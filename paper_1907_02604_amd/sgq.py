@@ -1,0 +1,224 @@
+"""ctypes binding of libsgq.so (argument marshalling only).
+
+Every compute step runs in the HIP library; this module passes device pointers of
+torch tensors and the current HIP stream to the C ABI declared in include/sgq.h.
+Importing it loads the in-tree library and fails loudly when it is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsgq.so")
+
+SGQ_OK, SGQ_EINVAL, SGQ_ENOMEM, SGQ_EHIP, SGQ_EPLAN, SGQ_ENONFINITE, SGQ_ELIMIT = 0, -1, -2, -3, -4, -5, -6
+SGQ_FP64, SGQ_FP32 = 0, 1
+SGQ_BAND, SGQ_FREE, SGQ_GRAND = 0, 1, 2
+
+EXPORTED = ("sgq_plan_create", "sgq_plan_destroy", "rho_quadrature", "band_energy",
+            "band_energy_backward", "sgq_vloc_gaussian_backward", "sgq_plan_status",
+            "sgq_last_error", "sgq_validate", "sgq_gauss_rule_host")
+
+
+class SgqError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"sgq error {code}: {msg}")
+        self.code = code
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32 * 3), ("h", ctypes.c_double), ("n_atoms", ctypes.c_int32),
+                ("n_proj", ctypes.c_int32), ("proj_rc", ctypes.c_double),
+                ("proj_rg", ctypes.c_double), ("n_nodes", ctypes.c_int32),
+                ("precision", ctypes.c_int32)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_1907_02604_amd.build.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I, D, V = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, None
+    sig = {
+        "sgq_plan_create": (I, [ctypes.POINTER(Problem), P, P, P, ctypes.POINTER(P)]),
+        "sgq_plan_destroy": (I, [P]),
+        "rho_quadrature": (I, [P, P, P, P, D, D, P, P, P, P]),
+        "band_energy": (I, [P, P, P, P, P, D, D, I, P, P, P]),
+        "band_energy_backward": (I, [P, P, P, P, P, D, D, I, P, P, P, P, P]),
+        "sgq_vloc_gaussian_backward": (I, [P, P, P, D, D, D, P, P]),
+        "sgq_plan_status": (I, [P, ctypes.POINTER(ctypes.c_int32)]),
+        "sgq_last_error": (ctypes.c_char_p, []),
+        "sgq_validate": (I, [ctypes.POINTER(Problem), P, P, P]),
+        "sgq_gauss_rule_host": (I, [P, P, I, P, P]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    del V
+    return lib
+
+
+_lib = _load()
+
+
+def lib():
+    return _lib
+
+
+def _check(code):
+    if code != SGQ_OK:
+        raise SgqError(code, _lib.sgq_last_error().decode())
+
+
+def _ptr(t):
+    """Device (or host numpy) pointer of a contiguous array, None for None."""
+    if t is None:
+        return None
+    if isinstance(t, np.ndarray):
+        assert t.flags.c_contiguous
+        return t.ctypes.data
+    assert t.is_contiguous(), "tensors passed to libsgq must be contiguous"
+    return t.data_ptr()
+
+
+def _stream(stream):
+    if stream is not None:
+        return stream
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+def make_problem_struct(n, h, n_atoms, n_proj, n_nodes, precision, proj_rc=1.5, proj_rg=0.5):
+    p = Problem()
+    p.n[0], p.n[1], p.n[2] = int(n[0]), int(n[1]), int(n[2])
+    p.h = float(h)
+    p.n_atoms = int(n_atoms)
+    p.n_proj = int(n_proj)
+    p.proj_rc = float(proj_rc)
+    p.proj_rg = float(proj_rg)
+    p.n_nodes = int(n_nodes)
+    p.precision = int(precision)
+    return p
+
+
+def validate(n, h, n_atoms, n_proj, centers, half_width, depth, precision, proj_rc=1.5, proj_rg=0.5):
+    """Host-only argument check (sgq_validate); returns the status code."""
+    c = np.ascontiguousarray(centers, dtype=np.int64)
+    hw = np.ascontiguousarray(half_width, dtype=np.int32)
+    d = np.ascontiguousarray(depth, dtype=np.int32)
+    prob = make_problem_struct(n, h, n_atoms, n_proj, c.size, precision, proj_rc, proj_rg)
+    return _lib.sgq_validate(ctypes.byref(prob), c.ctypes.data, hw.ctypes.data, d.ctypes.data)
+
+
+def gauss_rule_host(alpha, beta):
+    """(theta ascending, weights) of the tridiagonal (alpha, beta) via the library's host solver."""
+    a = np.ascontiguousarray(alpha, dtype=np.float64)
+    b = np.ascontiguousarray(beta, dtype=np.float64)
+    K = a.size
+    th = np.zeros(K)
+    w = np.zeros(K)
+    _check(_lib.sgq_gauss_rule_host(a.ctypes.data, b.ctypes.data if b.size else None, K,
+                                    th.ctypes.data, w.ctypes.data))
+    return th, w
+
+
+class Plan:
+    """A plan for a fixed grid and node set (sgq_plan_create)."""
+
+    def __init__(self, n, h, n_atoms, n_proj, centers, half_width, depth, precision,
+                 proj_rc=1.5, proj_rg=0.5):
+        c = np.ascontiguousarray(centers, dtype=np.int64)
+        hw = np.ascontiguousarray(half_width, dtype=np.int32)
+        d = np.ascontiguousarray(depth, dtype=np.int32)
+        self.n = tuple(int(v) for v in n)
+        self.n_nodes = int(c.size)
+        self.n_atoms = int(n_atoms)
+        self.n_proj = int(n_proj)
+        self.kmax = int(d.max()) if d.size else 1
+        self.precision = int(precision)
+        prob = make_problem_struct(n, h, n_atoms, n_proj, c.size, precision, proj_rc, proj_rg)
+        handle = ctypes.c_void_p()
+        _check(_lib.sgq_plan_create(ctypes.byref(prob), c.ctypes.data, hw.ctypes.data,
+                                    d.ctypes.data, ctypes.byref(handle)))
+        self._h = handle
+
+    @classmethod
+    def from_problem(cls, prob):
+        """Plan for a ``synth.Problem``."""
+        prec = SGQ_FP64 if prob.precision == "f64" else SGQ_FP32
+        return cls(prob.n, prob.h, prob.atoms.shape[0], prob.n_proj, prob.centers,
+                   prob.half_width, prob.depth, prec)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def status(self):
+        st = ctypes.c_int32(0)
+        _check(_lib.sgq_plan_status(self._h, ctypes.byref(st)))
+        return int(st.value)
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            _lib.sgq_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def rho_quadrature(plan, v_loc, atom_R, proj_E, mu, kT, rho, theta_w=None, k_eff=None, stream=None):
+    _check(_lib.rho_quadrature(plan.handle, _ptr(v_loc), _ptr(atom_R), _ptr(proj_E), float(mu),
+                               float(kT), _ptr(rho), _ptr(theta_w), _ptr(k_eff), _stream(stream)))
+
+
+def band_energy(plan, v_loc, atom_R, proj_E, node_weight, mu, kT, integrand, e_node, omega,
+                stream=None):
+    _check(_lib.band_energy(plan.handle, _ptr(v_loc), _ptr(atom_R), _ptr(proj_E), _ptr(node_weight),
+                            float(mu), float(kT), int(integrand), _ptr(e_node), _ptr(omega),
+                            _stream(stream)))
+
+
+def band_energy_backward(plan, v_loc, atom_R, proj_E, node_weight, mu, kT, integrand, grad_omega,
+                         dV, dR_nl, dE=None, stream=None):
+    _check(_lib.band_energy_backward(plan.handle, _ptr(v_loc), _ptr(atom_R), _ptr(proj_E),
+                                     _ptr(node_weight), float(mu), float(kT), int(integrand),
+                                     _ptr(grad_omega), _ptr(dV), _ptr(dR_nl), _ptr(dE),
+                                     _stream(stream)))
+
+
+def vloc_gaussian_backward(plan, dV, atom_R, depth, sigma, cutoff_sigmas, dR, stream=None):
+    _check(_lib.sgq_vloc_gaussian_backward(plan.handle, _ptr(dV), _ptr(atom_R), float(depth),
+                                           float(sigma), float(cutoff_sigmas), _ptr(dR),
+                                           _stream(stream)))
+
+
+# ------------------------------------------------------------------ torch conveniences
+def device_inputs(prob, device="cuda"):
+    """Device tensors (v_loc, atoms, proj_E, weight) of a ``synth.Problem``."""
+    import torch
+    v = torch.as_tensor(np.ascontiguousarray(prob.v_loc), dtype=torch.float64, device=device)
+    R = torch.as_tensor(np.ascontiguousarray(prob.atoms), dtype=torch.float64, device=device)
+    E = torch.as_tensor(np.ascontiguousarray(prob.proj_E), dtype=torch.float64, device=device)
+    w = torch.as_tensor(np.ascontiguousarray(prob.weight), dtype=torch.float64, device=device)
+    return v, R, E, w
+
+
+def rho(prob, plan=None, want_rule=False, device="cuda"):
+    """Density at the nodes of a ``synth.Problem``; returns torch tensors."""
+    import torch
+    plan = plan or Plan.from_problem(prob)
+    v, R, E, _ = device_inputs(prob, device)
+    out = torch.empty(prob.n_nodes, dtype=torch.float64, device=device)
+    tw = torch.zeros(prob.n_nodes * plan.kmax * 2, dtype=torch.float64, device=device) if want_rule else None
+    ke = torch.zeros(prob.n_nodes, dtype=torch.int32, device=device)
+    rho_quadrature(plan, v, R, E, prob.mu, prob.kT, out, tw, ke)
+    if want_rule:
+        return out, tw.view(prob.n_nodes, plan.kmax, 2), ke
+    return out, ke
