@@ -196,7 +196,10 @@ extern "C" int sgq_plan_create(const sgq_problem* prob, const int64_t* center,
   p->block = 256;
   int wg_per_cu = 2;
   if (const char* env = std::getenv("SGQ_WG_PER_CU")) wg_per_cu = std::max(1, atoi(env));
-  if (const char* env = std::getenv("SGQ_BLOCK")) p->block = atoi(env) == 512 ? 512 : 256;
+  if (const char* env = std::getenv("SGQ_BLOCK")) {
+    int b = atoi(env);
+    p->block = (b == 128 || b == 512) && !p->fp64 ? b : 256;
+  }
   p->grid = std::max(1, std::min(nq, ncu * wg_per_cu));
   p->npad = (nmax + 63) / 64 * 64;
   p->slot_stride = (size_t)p->kmax * p->npad;

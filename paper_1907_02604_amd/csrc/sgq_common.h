@@ -5,6 +5,11 @@
 #include <stddef.h>
 #include <stdint.h>
 
+// Address-space qualifiers for device functions that are not inlined: without them the
+// compiler must use FLAT accesses (and wait on every memory counter at once).
+#define SGQ_G __attribute__((address_space(1)))   // global memory
+#define SGQ_L __attribute__((address_space(3)))   // LDS
+
 namespace sgq {
 
 constexpr int kWave = 64;            // CDNA wavefront

@@ -13,8 +13,9 @@ namespace sgq {
 // Z         optional [K*K] (row-major, Z[i*ld + k] = component i of eigenvector k): if
 //           non-null the full eigenvector matrix is accumulated as well.
 // Returns false if an unreduced block failed to converge in 40*K sweeps.
-__host__ __device__ inline bool tridiag_gauss(double* a, double* b, double* z, int K,
-                                              double* Z = nullptr, int ld = 0) {
+template <typename PA, typename PZ = double*>
+__host__ __device__ inline bool tridiag_gauss(PA a, PA b, PA z, int K, PZ Z = nullptr,
+                                              int ld = 0) {
   for (int k = 0; k < K; ++k) z[k] = (k == 0) ? 1.0 : 0.0;
   if (Z) {
     for (int i = 0; i < K; ++i)

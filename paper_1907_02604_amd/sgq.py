@@ -12,7 +12,7 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libsgq.so")
+LIB_PATH = os.environ.get("SGQ_LIBRARY") or os.path.join(_HERE, "libsgq.so")
 
 SGQ_OK, SGQ_EINVAL, SGQ_ENOMEM, SGQ_EHIP, SGQ_EPLAN, SGQ_ENONFINITE, SGQ_ELIMIT = 0, -1, -2, -3, -4, -5, -6
 SGQ_FP64, SGQ_FP32 = 0, 1
