@@ -1,0 +1,776 @@
+// Device building blocks of the Lanczos-Gauss kernels (forward and adjoint): the node
+// state in LDS, node geometry and projector atom lists, the fused reorthogonalisation
+// sweep, the stencil passes and the projector passes, and one full Lanczos run.
+#pragma once
+
+#include "sgq_common.h"
+#include "tridiag.h"
+
+namespace sgq {
+
+
+constexpr int kMarchPlane = 5 * 256;  // largest cube cross-section of the plane march
+
+template <typename T, int BLOCK>
+struct NodeState {
+  static constexpr int NW = BLOCK / kWave;
+  int node;
+  int sx, sy, sz, ox, oy, oz, periodic, n, start, natoms, abort;
+  int atom[kMaxNodeAtoms];
+  int abox[kMaxNodeAtoms][3];       // local coordinates of the projector box corner
+  int aphase[kMaxNodeAtoms];        // 0: scatter with the parallel group, 1: alone
+  int grp[kMaxNodeAtoms];           // the parallel group, in atom order
+  int ngrp;
+  int wcount[NW];
+  T acoef[kMaxNodeAtoms][4];        // E h^3 (chi . q): weights of the projector scatter
+  double anl[kMaxNodeAtoms];        // q . V_nl q contribution of each atom
+  double alpha[kMaxDepth];
+  double beta[kMaxDepth];
+  double scale[kMaxDepth + 1];      // 1 / |W_i| (q_i = scale_i W_i)
+  double gram[kMaxDepth + 1];       // q_i . q_j of the current vector
+  T ct[kMaxDepth + 1];              // c_i * scale_i
+  double red[NW][kMaxDepth + 2];
+  double ta[kMaxDepth], tb[kMaxDepth], tz[kMaxDepth];
+  double dsave[kMaxDepth + 1];      // D_i of the last sweep
+  double orth_tol;
+  int redo;
+  int wflag[NW];
+  T plane[2][kMarchPlane];          // z planes of the cube for the stencil march
+};
+
+// local linear index -> (x, y, z) of a cube with extents sx, sy
+__device__ __forceinline__ void unflatten(int p, int sx, int sxy, float inv_sx, float inv_sxy,
+                                          int& x, int& y, int& z) {
+  z = (int)(((float)p + 0.5f) * inv_sxy);
+  int r = p - z * sxy;
+  if (r < 0) { --z; r += sxy; } else if (r >= sxy) { ++z; r -= sxy; }
+  y = (int)(((float)r + 0.5f) * inv_sx);
+  x = r - y * sx;
+  if (x < 0) { --y; x += sx; } else if (x >= sx) { ++y; x -= sx; }
+}
+
+// Projector box point b of node atom a -> local linear index, or -1 outside the cube.
+template <typename S>
+__device__ __forceinline__ int box_point(const S& st, int a, int b, int B) {
+  int bx = b % B, by = (b / B) % B, bz = b / (B * B);
+  int x = st.abox[a][0] + bx, y = st.abox[a][1] + by, z = st.abox[a][2] + bz;
+  if (st.periodic) {
+    x = wrap_index(x, st.sx);
+    y = wrap_index(y, st.sy);
+    z = wrap_index(z, st.sz);
+  } else if (x < 0 || y < 0 || z < 0 || x >= st.sx || y >= st.sy || z >= st.sz) {
+    return -1;
+  }
+  return x + st.sx * (y + st.sy * z);
+}
+
+// Sets up the cube geometry and the node's projector atom list (ordered by atom id).
+template <typename T, int BLOCK>
+__device__ __noinline__ void node_setup(const LaunchParams& P, SGQ_L NodeState<T, BLOCK>& st, int q) {
+  constexpr int NW = BLOCK / kWave;
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+  if (tid == 0) {
+    int R = P.half_width[q];
+    int c = P.center[q];
+    int cx = c % P.nx, cy = (c / P.nx) % P.ny, cz = c / (P.nx * P.ny);
+    if (R < 0) {
+      st.sx = P.nx; st.sy = P.ny; st.sz = P.nz;
+      st.ox = st.oy = st.oz = 0;
+      st.periodic = 1;
+      st.start = c;
+    } else {
+      int s = 2 * R + 1;
+      st.sx = st.sy = st.sz = s;
+      st.ox = cx - R; st.oy = cy - R; st.oz = cz - R;
+      st.periodic = 0;
+      st.start = R + s * (R + s * R);
+    }
+    st.n = st.sx * st.sy * st.sz;
+    st.natoms = 0;
+    st.abort = 0;
+  }
+  __syncthreads();
+  if (P.n_proj == 0) return;
+  const int m = P.box_m;
+  const int nn[3] = {P.nx, P.ny, P.nz};
+  for (int base = 0; base < P.n_atoms; base += BLOCK) {
+    int J = base + tid;
+    bool hit = false;
+    int lo[3] = {0, 0, 0};
+    if (J < P.n_atoms) {
+      const int o[3] = {st.ox, st.oy, st.oz};
+      const int s[3] = {st.sx, st.sy, st.sz};
+      hit = true;
+      for (int ax = 0; ax < 3; ++ax) {
+        int d = wrap_index(P.atom_g0[3 * J + ax] - o[ax], nn[ax]);
+        if (!st.periodic) {
+          if (d >= nn[ax] - m) d -= nn[ax];
+          if (d + m < 0 || d - m > s[ax] - 1) hit = false;
+        }
+        lo[ax] = d - m;
+      }
+    }
+    uint64_t mask = __ballot(hit);
+    int before = __popcll(mask & ((1ull << lane) - 1ull));
+    if (lane == 0) st.wcount[wave] = __popcll(mask);
+    __syncthreads();
+    int off = st.natoms;
+    for (int w = 0; w < wave; ++w) off += st.wcount[w];
+    if (hit) {
+      int slot = off + before;
+      if (slot < kMaxNodeAtoms) {
+        st.atom[slot] = J;
+        st.abox[slot][0] = lo[0];
+        st.abox[slot][1] = lo[1];
+        st.abox[slot][2] = lo[2];
+      }
+    }
+    __syncthreads();
+    if (tid == 0) {
+      int tot = 0;
+      for (int w = 0; w < NW; ++w) tot += st.wcount[w];
+      st.natoms += tot;
+    }
+    __syncthreads();
+  }
+  if (st.natoms > kMaxNodeAtoms) {
+    if (tid == 0) {
+      st.abort = 1;
+      atomicOr(P.status, kStatusLimit);
+    }
+    __syncthreads();
+    return;
+  }
+  // Scatter groups: an atom whose box overlaps no earlier atom's box joins the
+  // parallel group; the others are added one at a time, in atom order.
+  const int B = 2 * m + 1;
+  bool alias = st.periodic && (P.nx < B || P.ny < B || P.nz < B);
+  for (int a = tid; a < st.natoms; a += BLOCK) {
+    int ph = alias ? 1 : 0;
+    for (int b = 0; b < a && ph == 0; ++b) {
+      bool ov = true;
+      for (int ax = 0; ax < 3; ++ax) {
+        int d = st.abox[a][ax] - st.abox[b][ax];
+        if (st.periodic) {
+          int nax = nn[ax];
+          d = wrap_index(d, nax);
+          d = d > nax / 2 ? nax - d : d;
+        }
+        if (abs(d) > 2 * m) ov = false;
+      }
+      if (ov) ph = 1;
+    }
+    st.aphase[a] = ph;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int c = 0;
+    for (int a = 0; a < st.natoms; ++a)
+      if (!st.aphase[a]) st.grp[c++] = a;
+    st.ngrp = c;
+  }
+  __syncthreads();
+}
+
+// dst(p) = src(p) - sum_{i<=j} ct_i W_i(p) for every cube point, with the FP64 dots
+// D_i = W_i . dst and |dst|^2 left per wave in st.red.
+//
+// Layout: four lanes share a point group of VEC consecutive points, each lane taking
+// the basis vectors i = g (mod 4), i.e. KS "slots" i = 4m + g, m < KS.  A lane handles
+// PU point groups per iteration, so one iteration issues KS*PU vector loads before any
+// of them is consumed; the variants keep KS*PU*VEC near 64 registers of loads in
+// flight whatever the step (few slots and many groups early in the recurrence, many
+// slots and few groups late).  Row tails [n, npad) of W are kept zero.
+template <typename T, int BLOCK, int KS, int PU, int VEC>
+__device__ __noinline__ void fused_sweep_v(SGQ_L NodeState<T, BLOCK>& st,
+                                           const SGQ_G T* __restrict__ W, const SGQ_G T* src,
+                                           SGQ_G T* dst, int j, int n, size_t npad) {
+  using V = T __attribute__((ext_vector_type(VEC)));
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+  const int g = lane & 3;
+  double D[KS];
+  T cg[KS];
+#pragma unroll
+  for (int m = 0; m < KS; ++m) {
+    D[m] = 0.0;
+    const int i = 4 * m + g;
+    cg[m] = (i <= j) ? st.ct[i] : (T)0;
+  }
+  double n2 = 0.0;
+  const int ngroups = (n + VEC - 1) / VEC;
+  constexpr int STRIDE = BLOCK / 4;
+  for (int pg0 = tid >> 2; pg0 < ngroups; pg0 += STRIDE * PU) {
+    V qv[PU][KS];
+    V sv[PU];
+#pragma unroll
+    for (int u = 0; u < PU; ++u) {
+      const int pg = pg0 + u * STRIDE;
+      const int p0 = (pg < ngroups ? pg : 0) * VEC;
+#pragma unroll
+      for (int m = 0; m < KS; ++m) {
+        const int i = 4 * m + g;
+        // rows i > j are read from row j (finite data) and weighted by cg = 0; their
+        // D sums are never stored
+        qv[u][m] = *reinterpret_cast<const SGQ_G V*>(W + (size_t)(i <= j ? i : j) * npad + p0);
+      }
+      sv[u] = *reinterpret_cast<const SGQ_G V*>(src + p0);
+    }
+#pragma unroll
+    for (int u = 0; u < PU; ++u) {
+      const int pg = pg0 + u * STRIDE;
+      const int p0 = pg * VEC;
+      V acc = (V)(T)0;
+#pragma unroll
+      for (int m = 0; m < KS; ++m) acc += cg[m] * qv[u][m];
+#pragma unroll
+      for (int k = 0; k < VEC; ++k) {
+        acc[k] += __shfl_xor(acc[k], 1, kWave);
+        acc[k] += __shfl_xor(acc[k], 2, kWave);
+      }
+      V w = sv[u] - acc;
+#pragma unroll
+      for (int k = 0; k < VEC; ++k)
+        if (pg >= ngroups || p0 + k >= n) w[k] = (T)0;
+      if (g == 0 && pg < ngroups) {
+        *reinterpret_cast<SGQ_G V*>(dst + p0) = w;
+#pragma unroll
+        for (int k = 0; k < VEC; ++k) n2 += (double)w[k] * (double)w[k];
+      }
+#pragma unroll
+      for (int m = 0; m < KS; ++m) {
+#pragma unroll
+        for (int k = 0; k < VEC; ++k) D[m] += (double)qv[u][m][k] * (double)w[k];
+      }
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < KS; ++m) {
+    double v = D[m];
+    v += __shfl_xor(v, 4, kWave);
+    v += __shfl_xor(v, 8, kWave);
+    v += __shfl_xor(v, 16, kWave);
+    v += __shfl_xor(v, 32, kWave);
+    const int i = 4 * m + g;
+    if (lane < 4 && i <= j) st.red[wave][i] = v;
+  }
+  n2 = wave_sum(n2);
+  if (lane == 0) st.red[wave][kMaxDepth + 1] = n2;
+}
+
+// Picks the sweep variant for step j (slots KS >= (j+1)/4, at most KG).
+template <typename T, int BLOCK, int KG>
+__device__ __forceinline__ void fused_sweep(SGQ_L NodeState<T, BLOCK>& st,
+                                            const SGQ_G T* __restrict__ W, const SGQ_G T* src,
+                                            SGQ_G T* dst, int j, int n, size_t npad) {
+  const int need = j / 4 + 1;
+  if constexpr (sizeof(T) == 4) {
+    if (need <= 2) return fused_sweep_v<T, BLOCK, 2, 8, 4>(st, W, src, dst, j, n, npad);
+    if (need <= 4) return fused_sweep_v<T, BLOCK, 4, 4, 4>(st, W, src, dst, j, n, npad);
+    if (KG <= 8 || need <= 8) return fused_sweep_v<T, BLOCK, 8, 4, 2>(st, W, src, dst, j, n, npad);
+    if (KG <= 16 || need <= 16) return fused_sweep_v<T, BLOCK, 16, 2, 2>(st, W, src, dst, j, n, npad);
+    return fused_sweep_v<T, BLOCK, 32, 1, 1>(st, W, src, dst, j, n, npad);
+  } else {
+    if (need <= 2) return fused_sweep_v<T, BLOCK, 2, 8, 2>(st, W, src, dst, j, n, npad);
+    if (need <= 4) return fused_sweep_v<T, BLOCK, 4, 4, 2>(st, W, src, dst, j, n, npad);
+    if (KG <= 8 || need <= 8) return fused_sweep_v<T, BLOCK, 8, 4, 1>(st, W, src, dst, j, n, npad);
+    if (KG <= 16 || need <= 16) return fused_sweep_v<T, BLOCK, 16, 2, 1>(st, W, src, dst, j, n, npad);
+    return fused_sweep_v<T, BLOCK, 32, 1, 1>(st, W, src, dst, j, n, npad);
+  }
+}
+
+// Totals of a sweep: beta_j, the scale of the new vector, its Gram column against
+// q_0..q_j and the semi-orthogonality flag.  Ends with a barrier.
+template <typename T, int BLOCK>
+__device__ __forceinline__ void finish_sweep(SGQ_L NodeState<T, BLOCK>& st, int j) {
+  constexpr int NW = BLOCK / kWave;
+  const int tid = threadIdx.x;
+  double dsum = 0.0;
+  if (tid <= j) {
+    for (int w = 0; w < NW; ++w) dsum += st.red[w][tid];
+    st.dsave[tid] = dsum;
+  }
+  if (tid == 0) {
+    double nn2 = 0.0;
+    for (int w = 0; w < NW; ++w) nn2 += st.red[w][kMaxDepth + 1];
+    double b = sqrt(nn2);
+    st.beta[j] = b;
+    st.scale[j + 1] = b > 0.0 ? 1.0 / b : 0.0;
+  }
+  __syncthreads();
+  double gi = 0.0;
+  if (tid <= j) {
+    gi = st.scale[tid] * st.scale[j + 1] * dsum;
+    st.gram[tid] = gi;
+  }
+  // semi-orthogonality test: any |G_i| above sqrt(eps) (or not finite)
+  int bad = (tid <= j) && !(fabs(gi) <= st.orth_tol);
+  bad = __any(bad);
+  if ((tid & (kWave - 1)) == 0) st.wflag[tid / kWave] = bad;
+  __syncthreads();
+  if (tid == 0) {
+    int r = 0;
+    for (int w = 0; w < NW; ++w) r |= st.wflag[w];
+    st.redo = r;
+  }
+  __syncthreads();
+}
+
+// chi . q_j of every node atom (projector overlaps).  A wave takes NA atoms at a time
+// with every box point of all of them unrolled, so their loads are in flight together.
+template <typename T, int BLOCK>
+__device__ __noinline__ void projector_dots(const SGQ_G double* proj_E,
+                                            SGQ_L NodeState<T, BLOCK>& st,
+                                            const SGQ_G T* __restrict__ chi, const SGQ_G T* Wj,
+                                            double sjd, double h3, int B, int B3) {
+  using T4 = T __attribute__((ext_vector_type(4)));
+  constexpr int NW = BLOCK / kWave;
+  constexpr int UNR = 6;    // 6 x 64 box points cover the 7^3 box of h = rc/3
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const int natoms = st.natoms;
+  constexpr int NA = 4;
+  for (int a0 = NA * wave; a0 < natoms; a0 += NA * NW) {
+    T4 acc[NA];
+#pragma unroll
+    for (int t = 0; t < NA; ++t) acc[t] = (T4)(T)0;
+    for (int b0 = 0; b0 < B3; b0 += UNR * kWave) {
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        const int b = b0 + u * kWave + lane;
+#pragma unroll
+        for (int t = 0; t < NA; ++t) {
+          const int a = a0 + t;
+          const bool live = (b < B3) && (a < natoms);
+          const int lp = live ? box_point(st, a, b, B) : -1;
+          const int J = st.atom[a < natoms ? a : a0];
+          const T wv = Wj[lp >= 0 ? lp : 0] * (T)(lp >= 0);
+          const T4 c = *reinterpret_cast<const SGQ_G T4*>(chi + ((size_t)J * B3 + (live ? b : 0)) * 4);
+          acc[t] += c * wv;
+        }
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < NA; ++t) {
+      const int a = a0 + t;
+      if (a >= natoms) break;
+      const int J = st.atom[a];
+      double nl = 0.0;
+#pragma unroll
+      for (int l = 0; l < 4; ++l) {
+        double cl = (double)wave_sum(acc[t][l]) * sjd;     // chi_l . q_j
+        double El = proj_E[4 * J + l];
+        if (lane == 0) st.acoef[a][l] = (T)(El * h3 * cl);
+        nl += El * h3 * cl * cl;
+      }
+      if (lane == 0) st.anl[a] = nl;
+    }
+  }
+}
+
+// u += sum_l chi_l E_l h^3 (chi_l . q) over the box of atom a: `lanes` threads starting
+// at `first` cover its box points (lanes == 1: one point at a time, for grids narrower
+// than the box where box points alias).
+template <typename T, int BLOCK>
+__device__ __noinline__ void scatter_atom(SGQ_L NodeState<T, BLOCK>& st,
+                                          const SGQ_G T* __restrict__ chi, SGQ_G T* U, int a,
+                                          int B, int B3, int first, int lanes) {
+  using T4 = T __attribute__((ext_vector_type(4)));
+  const int J = st.atom[a];
+  const T4 coef = {st.acoef[a][0], st.acoef[a][1], st.acoef[a][2], st.acoef[a][3]};
+  if (lanes == 1) {
+    for (int b = 0; b < B3; ++b) {
+      int lp = box_point(st, a, b, B);
+      if (lp < 0) continue;
+      T4 prod = *reinterpret_cast<const SGQ_G T4*>(chi + ((size_t)J * B3 + b) * 4) * coef;
+      U[lp] += prod[0] + prod[1] + prod[2] + prod[3];
+    }
+    return;
+  }
+  constexpr int UNR = 6;
+  for (int b0 = first; b0 < B3; b0 += UNR * lanes) {
+    int lp[UNR];
+    T old[UNR];
+    T4 c[UNR];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const int b = b0 + u * lanes;
+      lp[u] = b < B3 ? box_point(st, a, b, B) : -1;
+      old[u] = U[lp[u] >= 0 ? lp[u] : 0];
+      c[u] = *reinterpret_cast<const SGQ_G T4*>(chi + ((size_t)J * B3 + (b < B3 ? b : 0)) * 4);
+    }
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      if (lp[u] >= 0) {
+        T4 prod = c[u] * coef;
+        U[lp[u]] = old[u] + (prod[0] + prod[1] + prod[2] + prod[3]);
+      }
+    }
+  }
+}
+
+// The parallel scatter group: atoms whose boxes overlap no earlier atom's box, so their
+// updates never touch the same point.  A wave takes NA of them per round with all the
+// loads of the round issued before any update.
+template <typename T, int BLOCK>
+__device__ __noinline__ void scatter_group(SGQ_L NodeState<T, BLOCK>& st,
+                                           const SGQ_G T* __restrict__ chi, SGQ_G T* U, int B,
+                                           int B3) {
+  using T4 = T __attribute__((ext_vector_type(4)));
+  constexpr int NW = BLOCK / kWave;
+  constexpr int NA = 3;
+  constexpr int UNR = 6;    // 6 x 64 box points cover the 7^3 box of h = rc/3
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  // atoms of the group (st.grp, in atom order) dealt round-robin to the waves
+  const int ngrp = st.ngrp;
+  const int cnt = ngrp > wave ? (ngrp - wave + NW - 1) / NW : 0;
+  auto mine = [&](int i) { return st.grp[wave + NW * i]; };
+  for (int i0 = 0; i0 < cnt; i0 += NA) {
+    for (int b0 = 0; b0 < B3; b0 += UNR * kWave) {
+      int lp[NA][UNR];
+      T old[NA][UNR];
+      T4 c[NA][UNR];
+#pragma unroll
+      for (int t = 0; t < NA; ++t) {
+        const int a = i0 + t < cnt ? mine(i0 + t) : mine(i0);
+        const int J = st.atom[a];
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+          const int b = b0 + u * kWave + lane;
+          lp[t][u] = (b < B3 && i0 + t < cnt) ? box_point(st, a, b, B) : -1;
+          old[t][u] = U[lp[t][u] >= 0 ? lp[t][u] : 0];
+          c[t][u] = *reinterpret_cast<const SGQ_G T4*>(chi + ((size_t)J * B3 + (b < B3 ? b : 0)) * 4);
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < NA; ++t) {
+        const int a = i0 + t < cnt ? mine(i0 + t) : mine(i0);
+        const T4 coef = {st.acoef[a][0], st.acoef[a][1], st.acoef[a][2], st.acoef[a][3]};
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+          if (lp[t][u] >= 0) {
+            T4 prod = c[t][u] * coef;
+            U[lp[t][u]] = old[t][u] + (prod[0] + prod[1] + prod[2] + prod[3]);
+          }
+        }
+      }
+    }
+  }
+}
+
+// u = s_j (-1/2 Lap_6 + V) W_j on a Dirichlet cube, four points per thread with every
+// load issued unconditionally (out-of-cube neighbours read the centre and are masked).
+// Returns this thread's part of q_j . u.
+template <typename T, int BLOCK, bool ACC = false>
+__device__ __noinline__ double stencil_cube(int gnx, int gny, int gnz,
+                                            const SGQ_L NodeState<T, BLOCK>& st,
+                                            const SGQ_G T* __restrict__ V,
+                                            const SGQ_G T* __restrict__ Wj, SGQ_G T* __restrict__ U,
+                                            T sj, T kin) {
+  const int n = st.n, sx = st.sx, sy = st.sy, sz = st.sz, sxy = sx * sy;
+  const float inv_sx = 1.0f / (float)sx, inv_sxy = 1.0f / (float)sxy;
+  const T w0 = (T)(3.0 * kFd0), w1 = (T)kFd1, w2 = (T)kFd2, w3 = (T)kFd3;
+  const int ox = st.ox, oy = st.oy, oz = st.oz;
+  double apart = 0.0;
+  constexpr int UNR = 4;
+  for (int base = threadIdx.x; base < n; base += UNR * BLOCK) {
+    T u[UNR], wc[UNR];
+    int pk[UNR];
+#pragma unroll
+    for (int k = 0; k < UNR; ++k) {
+      const int p = base + k * BLOCK;
+      const int pc = p < n ? p : 0;
+      pk[k] = p;
+      int x, y, z;
+      unflatten(pc, sx, sxy, inv_sx, inv_sxy, x, y, z);
+      const T c = Wj[pc];
+      wc[k] = c;
+      auto nb = [&](bool ok, int idx) -> T {
+        T v = Wj[ok ? idx : pc];
+        return ok ? v : (T)0;
+      };
+      T l1 = nb(x >= 1, pc - 1) + nb(x + 1 < sx, pc + 1) + nb(y >= 1, pc - sx) +
+             nb(y + 1 < sy, pc + sx) + nb(z >= 1, pc - sxy) + nb(z + 1 < sz, pc + sxy);
+      T l2 = nb(x >= 2, pc - 2) + nb(x + 2 < sx, pc + 2) + nb(y >= 2, pc - 2 * sx) +
+             nb(y + 2 < sy, pc + 2 * sx) + nb(z >= 2, pc - 2 * sxy) + nb(z + 2 < sz, pc + 2 * sxy);
+      T l3 = nb(x >= 3, pc - 3) + nb(x + 3 < sx, pc + 3) + nb(y >= 3, pc - 3 * sx) +
+             nb(y + 3 < sy, pc + 3 * sx) + nb(z >= 3, pc - 3 * sxy) + nb(z + 3 < sz, pc + 3 * sxy);
+      int gx = ox + x, gy = oy + y, gz = oz + z;
+      gx = gx < 0 ? gx + gnx : (gx >= gnx ? gx - gnx : gx);
+      gy = gy < 0 ? gy + gny : (gy >= gny ? gy - gny : gy);
+      gz = gz < 0 ? gz + gnz : (gz >= gnz ? gz - gnz : gz);
+      const T vloc = V[gx + gnx * (gy + gny * gz)];
+      const T lap = w0 * c + w1 * l1 + w2 * l2 + w3 * l3;
+      u[k] = sj * (kin * lap + vloc * c);
+    }
+#pragma unroll
+    for (int k = 0; k < UNR; ++k) {
+      if (pk[k] < n) {
+        if (ACC) U[pk[k]] += u[k]; else U[pk[k]] = u[k];
+        apart += (double)(sj * wc[k]) * (double)u[k];
+      }
+    }
+  }
+  return apart;
+}
+
+// u = s_j (-1/2 Lap_6 + V) W_j on a Dirichlet cube by marching through the z planes.
+// Thread t owns the in-plane points t + k*BLOCK (k < PPT) of every plane.  Their values
+// at planes z-3 .. z+6 live in a register ring indexed statically (the z loop is
+// unrolled by the ring length), so a plane is loaded four planes before it is first
+// used and the potential five planes before; x/y neighbours of plane z come from a
+// double-buffered copy of the plane in LDS (one barrier per plane).  Returns this
+// thread's part of q_j . u.
+template <typename T, int BLOCK, int PPT, bool ACC = false>
+__device__ __noinline__ double stencil_march(int gnx, int gny, int gnz,
+                                             SGQ_L NodeState<T, BLOCK>& st,
+                                             const SGQ_G T* __restrict__ V,
+                                             const SGQ_G T* __restrict__ Wj, SGQ_G T* __restrict__ U,
+                                             T sj, T kin) {
+  constexpr int NQ = 10;   // ring of W planes z-3 .. z+6
+  constexpr int NV = 5;    // ring of V planes z .. z+4
+  const int sx = st.sx, sy = st.sy, sz = st.sz, sxy = sx * sy;
+  const int tid = threadIdx.x;
+  const int vplane = gnx * gny;
+  const T w0 = (T)(3.0 * kFd0), w1 = (T)kFd1, w2 = (T)kFd2, w3 = (T)kFd3;
+  T ring[PPT][NQ];
+  T vring[PPT][NV];
+  int px[PPT], py[PPT], vrow[PPT];
+  bool own[PPT];
+  int gz0 = st.oz < 0 ? st.oz + gnz : st.oz;     // global z of local plane 0
+#pragma unroll
+  for (int k = 0; k < PPT; ++k) {
+    const int p2 = tid + k * BLOCK;
+    own[k] = p2 < sxy;
+    const int pc = own[k] ? p2 : 0;
+    py[k] = pc / sx;
+    px[k] = pc - py[k] * sx;
+    int gx = st.ox + px[k], gy = st.oy + py[k];
+    gx = gx < 0 ? gx + gnx : (gx >= gnx ? gx - gnx : gx);
+    gy = gy < 0 ? gy + gny : (gy >= gny ? gy - gny : gy);
+    vrow[k] = gx + gnx * gy;
+#pragma unroll
+    for (int d = 0; d < NQ; ++d) {
+      // slot d holds plane d (d <= 6) or plane d - NQ (below the cube: masked at use);
+      // planes outside the cube are read clamped and masked where they are used
+      const int z = d <= 6 ? d : d - NQ;
+      const int zc = z < 0 ? 0 : (z < sz ? z : sz - 1);
+      ring[k][d] = Wj[pc + zc * sxy];
+    }
+#pragma unroll
+    for (int d = 0; d < NV; ++d) {
+      int gz = gz0 + (d < sz ? d : sz - 1);
+      gz = gz >= gnz ? gz - gnz : gz;
+      vring[k][d] = V[vrow[k] + vplane * gz];
+    }
+  }
+  double apart = 0.0;
+  for (int z0 = 0; z0 < sz; z0 += NQ) {
+#pragma unroll
+    for (int r = 0; r < NQ; ++r) {
+      const int z = z0 + r;
+      if (z < sz) {
+        SGQ_L T* plane = st.plane[z & 1];
+#pragma unroll
+        for (int k = 0; k < PPT; ++k)
+          if (own[k]) plane[tid + k * BLOCK] = ring[k][r];
+        __syncthreads();
+        // uniform masks of the z neighbours (zero outside the cube)
+        const T mz1 = (T)(z >= 1), pz1 = (T)(z + 1 < sz);
+        const T mz2 = (T)(z >= 2), pz2 = (T)(z + 2 < sz);
+        const T mz3 = (T)(z >= 3), pz3 = (T)(z + 3 < sz);
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+          const int p2 = own[k] ? tid + k * BLOCK : 0;
+          const int x = px[k], y = py[k];
+          // LDS reads at clamped indices, masked by a 0/1 factor afterwards
+          auto at = [&](bool ok, int idx) -> T { return plane[ok ? idx : p2] * (T)ok; };
+          const T c = ring[k][r];
+          T l1 = mz1 * ring[k][(r + NQ - 1) % NQ] + pz1 * ring[k][(r + 1) % NQ] +
+                 at(x >= 1, p2 - 1) + at(x + 1 < sx, p2 + 1) + at(y >= 1, p2 - sx) +
+                 at(y + 1 < sy, p2 + sx);
+          T l2 = mz2 * ring[k][(r + NQ - 2) % NQ] + pz2 * ring[k][(r + 2) % NQ] +
+                 at(x >= 2, p2 - 2) + at(x + 2 < sx, p2 + 2) + at(y >= 2, p2 - 2 * sx) +
+                 at(y + 2 < sy, p2 + 2 * sx);
+          T l3 = mz3 * ring[k][(r + NQ - 3) % NQ] + pz3 * ring[k][(r + 3) % NQ] +
+                 at(x >= 3, p2 - 3) + at(x + 3 < sx, p2 + 3) + at(y >= 3, p2 - 3 * sx) +
+                 at(y + 3 < sy, p2 + 3 * sx);
+          const T lap = w0 * c + w1 * l1 + w2 * l2 + w3 * l3;
+          const T u = sj * (kin * lap + vring[k][r % NV] * c);
+          if (own[k]) {
+            if (ACC) U[p2 + z * sxy] += u; else U[p2 + z * sxy] = u;
+            apart += (double)(sj * c) * (double)u;
+          }
+        }
+        // refill: plane z+7 replaces plane z-3, potential of plane z+5 replaces plane z
+        const int zw = z + 7, zv = z + NV < sz ? z + NV : sz - 1;
+        int gz = gz0 + zv;
+        gz = gz >= gnz ? gz - gnz : gz;
+        gz = gz >= gnz ? gz - gnz : gz;
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+          const int pc = own[k] ? tid + k * BLOCK : 0;
+          ring[k][(r + NQ - 3) % NQ] = Wj[pc + (zw < sz ? zw : sz - 1) * sxy];
+          vring[k][r % NV] = V[vrow[k] + vplane * gz];
+        }
+      }
+    }
+  }
+  return apart;
+}
+
+// The same operator on the whole periodic grid (untruncated nodes).
+template <typename T, int BLOCK, bool ACC = false>
+__device__ __noinline__ double stencil_periodic(const SGQ_L NodeState<T, BLOCK>& st,
+                                                const SGQ_G T* __restrict__ V,
+                                                const SGQ_G T* __restrict__ Wj,
+                                                SGQ_G T* __restrict__ U, T sj, T kin) {
+  const int n = st.n, sx = st.sx, sy = st.sy, sz = st.sz, sxy = sx * sy;
+  const float inv_sx = 1.0f / (float)sx, inv_sxy = 1.0f / (float)sxy;
+  const T w0 = (T)(3.0 * kFd0);
+  const T wd[4] = {(T)0, (T)kFd1, (T)kFd2, (T)kFd3};
+  double apart = 0.0;
+  for (int p = threadIdx.x; p < n; p += BLOCK) {
+    int x, y, z;
+    unflatten(p, sx, sxy, inv_sx, inv_sxy, x, y, z);
+    T wc = Wj[p];
+    T lap = w0 * wc;
+    for (int d = 1; d <= 3; ++d) {
+      lap += wd[d] * (Wj[wrap_index(x - d, sx) + sx * (y + sy * z)] +
+                      Wj[wrap_index(x + d, sx) + sx * (y + sy * z)]);
+      lap += wd[d] * (Wj[x + sx * (wrap_index(y - d, sy) + sy * z)] +
+                      Wj[x + sx * (wrap_index(y + d, sy) + sy * z)]);
+      lap += wd[d] * (Wj[x + sx * (y + sy * wrap_index(z - d, sz))] +
+                      Wj[x + sx * (y + sy * wrap_index(z + d, sz))]);
+    }
+    T u = sj * (kin * lap + V[p] * wc);
+    if (ACC) U[p] += u; else U[p] = u;
+    apart += (double)(sj * wc) * (double)u;
+  }
+  return apart;
+}
+
+
+// u = H v for one vector of the node cube (stencil, local potential, and the projector
+// scatter with weights st.acoef that the caller has set): dispatches the stencil form.
+// ACC adds into U instead of storing.  Returns this thread's part of (s v) . u_local.
+template <typename T, int BLOCK, bool ACC>
+__device__ __forceinline__ double apply_local(const LaunchParams& P, SGQ_L NodeState<T, BLOCK>& st,
+                                              const SGQ_G T* V, const SGQ_G T* v, SGQ_G T* U,
+                                              T s, T kin) {
+  if (st.periodic) return stencil_periodic<T, BLOCK, ACC>(st, V, v, U, s, kin);
+  if (st.sx * st.sy <= 5 * BLOCK && st.sx * st.sy <= kMarchPlane)
+    return stencil_march<T, BLOCK, 5, ACC>(P.nx, P.ny, P.nz, st, V, v, U, s, kin);
+  return stencil_cube<T, BLOCK, ACC>(P.nx, P.ny, P.nz, st, V, v, U, s, kin);
+}
+
+template <typename T, int BLOCK>
+__device__ __forceinline__ void apply_scatter(const LaunchParams& P, SGQ_L NodeState<T, BLOCK>& st,
+                                              const SGQ_G T* chi, SGQ_G T* U, int B, int B3) {
+  const int tid = threadIdx.x;
+  if (st.natoms == 0) return;
+  scatter_group<T, BLOCK>(st, chi, U, B, B3);
+  __syncthreads();
+  const bool alias = st.periodic && (P.nx < B || P.ny < B || P.nz < B);
+  for (int a = 0; a < st.natoms; ++a) {
+    if (!st.aphase[a]) continue;
+    if (alias) {
+      if (tid == 0) scatter_atom<T, BLOCK>(st, chi, U, a, B, B3, 0, 1);
+    } else {
+      scatter_atom<T, BLOCK>(st, chi, U, a, B, B3, tid, BLOCK);
+    }
+    __syncthreads();
+  }
+}
+
+// One K-step Lanczos run of the current node (after node_setup): W rows 0..K_eff-1 hold
+// the unnormalised basis (q_i = st.scale[i] W_i), st.alpha / st.beta the tridiagonal.
+// u_j = H q_j is written to U + j*ustride (ustride 0: one reused row).  Returns K_eff.
+template <typename T, int BLOCK, int KG>
+__device__ int run_lanczos(const LaunchParams& P, SGQ_L NodeState<T, BLOCK>& st,
+                           SGQ_G T* __restrict__ W, SGQ_G T* __restrict__ Ubase, size_t ustride,
+                           int K) {
+  constexpr int NW = BLOCK / kWave;
+  constexpr int VEC = sizeof(T) == 4 ? 4 : 2;   // widest point group of the sweeps
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+  const SGQ_G T* __restrict__ V = (const SGQ_G T*)P.v;
+  const SGQ_G T* __restrict__ chi = (const SGQ_G T*)P.chi;
+  const SGQ_G double* proj_E = (const SGQ_G double*)P.proj_E;
+  const size_t npad = P.npad;
+  const double h = P.h;
+  const double h3 = h * h * h;
+  const T kin = (T)(-0.5 / (h * h));
+  const double hscale = 1.5 * (-kFd0 + 2.0 * (kFd1 - kFd2 + kFd3)) / (h * h) + *P.vmax;
+  const double tol = P.tau * hscale;
+  const int B = 2 * P.box_m + 1, B3 = B * B * B;
+  const int n = st.n;
+  const int natoms = st.natoms;
+  const int nzero = ((n + VEC - 1) / VEC) * VEC;
+  for (int p = tid; p < nzero; p += BLOCK) W[p] = (T)0;
+  __syncthreads();
+  if (tid == 0) {
+    W[st.start] = (T)1;
+    st.scale[0] = 1.0;
+  }
+  __syncthreads();
+
+  int keff = K;
+  for (int j = 0; j < K; ++j) {
+    const SGQ_G T* __restrict__ Wj = W + (size_t)j * npad;
+    SGQ_G T* __restrict__ U = Ubase + (size_t)j * ustride;
+    const double sjd = st.scale[j];
+    const T sj = (T)sjd;
+    // ---- H q_j: projector overlaps, stencil + local potential, projector scatter
+    projector_dots<T, BLOCK>(proj_E, st, chi, Wj, sjd, h3, B, B3);
+    double apart = apply_local<T, BLOCK, false>(P, st, V, Wj, U, sj, kin);
+    apart = wave_sum(apart);
+    if (lane == 0) st.red[wave][0] = apart;
+    __syncthreads();
+    apply_scatter<T, BLOCK>(P, st, chi, U, B, B3);
+    if (tid < kWave) {
+      double al = 0.0;
+      for (int a = tid; a < natoms; a += kWave) al += st.anl[a];
+      al = wave_sum(al);
+      if (tid == 0) {
+        for (int w = 0; w < NW; ++w) al += st.red[w][0];
+        st.alpha[j] = al;
+      }
+    }
+    __syncthreads();
+    if (j == K - 1) break;
+    // ---- reorthogonalisation coefficients (Gram column through the tridiagonal)
+    for (int i = tid; i <= j; i += BLOCK) {
+      double c;
+      if (i == j) {
+        c = st.alpha[j];
+      } else {
+        double gi1 = (i + 1 == j) ? 1.0 : st.gram[i + 1];
+        c = st.alpha[i] * st.gram[i] + st.beta[i] * gi1;
+        if (i > 0) c += st.beta[i - 1] * st.gram[i - 1];
+      }
+      st.ct[i] = (T)(c * st.scale[i]);
+    }
+    __syncthreads();
+    // ---- fused sweep: w = u - sum c_i q_i, D_i = W_i . w, |w|^2
+    SGQ_G T* __restrict__ Wn = W + (size_t)(j + 1) * npad;
+    fused_sweep<T, BLOCK, KG>(st, W, U, Wn, j, n, npad);
+    __syncthreads();
+    finish_sweep<T, BLOCK>(st, j);
+    // Semi-orthogonality guard: the coefficients above are exact up to O(G^2); when
+    // the measured Gram column exceeds sqrt(eps) (only near an invariant subspace)
+    // the projection is repeated once with the exact dots of this sweep.
+    if (st.redo && st.beta[j] > tol) {
+      for (int i = tid; i <= j; i += BLOCK)
+        st.ct[i] = (T)(st.scale[i] * st.scale[i] * st.dsave[i]);
+      __syncthreads();
+      fused_sweep<T, BLOCK, KG>(st, W, Wn, Wn, j, n, npad);
+      __syncthreads();
+      finish_sweep<T, BLOCK>(st, j);
+    }
+    if (!(st.beta[j] > tol)) {   // breakdown (or NaN): the Krylov space is invariant
+      keff = j + 1;
+      break;
+    }
+  }
+  return keff;
+}
+
+}  // namespace sgq

@@ -22,8 +22,11 @@ hipError_t launch_weighted_sum(const double* e, const double* w, int n, double* 
 hipError_t launch_backward(const LaunchParams& P, bool fp64, int grid, int block, int kg,
                            hipStream_t s);
 hipError_t launch_backward_gather(const LaunchParams& P, bool fp64, const int32_t* cell_start,
-                                  const int32_t* cell_nodes, int cell, double* dV, double* dR,
+                                  const int32_t* cell_nodes, int ncells, double* dV, double* dR,
                                   double* dE, hipStream_t s);
+hipError_t launch_zero(double* p, size_t n, hipStream_t s);
+int backward_max_depth();
+int gather_cell();
 hipError_t launch_vloc_backward(const double* dV, const double* R, int M, int nx, int ny, int nz,
                                 double h, double depth, double sigma, double cutoff, double* dR,
                                 hipStream_t s);
@@ -59,9 +62,12 @@ struct sgq_plan {
   int* d_queue = nullptr;
   int* d_status = nullptr;
   double* d_enode = nullptr;
-  // backward state (allocated on first use)
-  void* d_U2 = nullptr;
-  double* d_tri = nullptr;
+  // backward state (allocated on the first backward call)
+  bool bwd_ready = false;
+  int grid_bwd = 0;
+  size_t bwd_slot_stride = 0;
+  void* d_Wb = nullptr;
+  void* d_dchi = nullptr;
   void* d_P = nullptr;
   int64_t* d_cube_off = nullptr;
   double* d_dRp = nullptr;
@@ -69,7 +75,8 @@ struct sgq_plan {
   int32_t* d_node_atoms = nullptr;
   int32_t* d_cell_start = nullptr;
   int32_t* d_cell_nodes = nullptr;
-  int cell = 8;
+  int ncells = 0;
+  int ncu = 0;
   hipStream_t last = nullptr;
   std::vector<void*> allocs;
 };
@@ -168,6 +175,7 @@ extern "C" int sgq_plan_create(const sgq_problem* prob, const int64_t* center,
   HIP_OR_FAIL(hipGetDevice(&p->device));
   int ncu = 0;
   HIP_OR_FAIL(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, p->device));
+  p->ncu = ncu;
   const int nq = prob->n_nodes;
   p->n_grid = (size_t)prob->n[0] * prob->n[1] * prob->n[2];
   p->box_m = prob->n_proj ? box_half_width(prob->proj_rc, prob->h) : 0;
@@ -340,21 +348,150 @@ extern "C" int band_energy(sgq_plan* plan, const double* v_loc, const double* at
   return SGQ_OK;
 }
 
+// Backward workspace, node cube offsets and the dV gather lists (first backward call).
+static int ensure_backward(sgq_plan* p) {
+  if (p->bwd_ready) return SGQ_OK;
+  const int nq = p->prob.n_nodes;
+  const size_t es = p->fp64 ? 8 : 4;
+  const int nx = p->prob.n[0], ny = p->prob.n[1], nz = p->prob.n[2];
+  // node cubes of the per-node dV contributions
+  std::vector<int64_t> off(nq + 1, 0);
+  for (int q = 0; q < nq; ++q) {
+    int64_t n = p->h_hw[q] < 0 ? (int64_t)p->n_grid : (int64_t)std::pow(2 * p->h_hw[q] + 1, 3);
+    off[q + 1] = off[q] + n;
+  }
+  // gather lists: for every cell of the grid, the nodes (ascending) whose cube meets it
+  const int C = gather_cell();
+  const int ncx = (nx + C - 1) / C, ncy = (ny + C - 1) / C, ncz = (nz + C - 1) / C;
+  const int ncells = ncx * ncy * ncz;
+  auto axis_cells = [&](int c, int R, int n, int nc, std::vector<int>& out) {
+    out.clear();
+    if (R < 0) {
+      for (int i = 0; i < nc; ++i) out.push_back(i);
+      return;
+    }
+    std::vector<char> seen(nc, 0);
+    for (int x = c - R; x <= c + R; ++x) {
+      int cx = ((x % n) + n) % n / C;
+      if (!seen[cx]) { seen[cx] = 1; out.push_back(cx); }
+    }
+  };
+  std::vector<int32_t> count(ncells + 1, 0);
+  std::vector<int> ax, ay, az;
+  for (int pass = 0; pass < 2; ++pass) {
+    std::vector<int32_t> fill;
+    if (pass == 1) fill.assign(count.begin(), count.end() - 1);
+    std::vector<int32_t>* nodes = nullptr;
+    static thread_local std::vector<int32_t> list;
+    if (pass == 1) {
+      list.assign(count[ncells], 0);
+      nodes = &list;
+    }
+    for (int q = 0; q < nq; ++q) {
+      const int c = p->h_center[q], R = p->h_hw[q];
+      axis_cells(c % nx, R, nx, ncx, ax);
+      axis_cells((c / nx) % ny, R, ny, ncy, ay);
+      axis_cells(c / (nx * ny), R, nz, ncz, az);
+      for (int kz : az)
+        for (int ky : ay)
+          for (int kx : ax) {
+            const int cell = kx + ncx * (ky + ncy * kz);
+            if (pass == 0) ++count[cell + 1];
+            else (*nodes)[fill[cell]++] = q;
+          }
+    }
+    if (pass == 0)
+      for (int i = 0; i < ncells; ++i) count[i + 1] += count[i];
+    if (pass == 1) {
+      hipError_t e = hipSuccess;
+      e = e ? e : dalloc(p, &p->d_cell_start, (size_t)(ncells + 1) * 4);
+      e = e ? e : dalloc(p, &p->d_cell_nodes, std::max<size_t>(1, list.size()) * 4);
+      if (e != hipSuccess) return fail(SGQ_ENOMEM, "gather lists: " + std::string(hipGetErrorString(e)));
+      HIP_OR_FAIL(hipMemcpy(p->d_cell_start, count.data(), (ncells + 1) * 4, hipMemcpyHostToDevice));
+      if (!list.empty())
+        HIP_OR_FAIL(hipMemcpy(p->d_cell_nodes, list.data(), list.size() * 4, hipMemcpyHostToDevice));
+      list.clear();
+      list.shrink_to_fit();
+    }
+  }
+  p->ncells = ncells;
+  // one workgroup per CU (the eigenvector matrix of T lives in LDS)
+  p->grid_bwd = std::max(1, std::min(nq, p->ncu));
+  p->bwd_slot_stride = (size_t)(2 * p->kmax + 4) * p->npad;
+  const int B = 2 * p->box_m + 1;
+  hipError_t e = hipSuccess;
+  e = e ? e : dalloc(p, &p->d_Wb, (size_t)p->grid_bwd * p->bwd_slot_stride * es);
+  e = e ? e : dalloc(p, &p->d_P, (size_t)std::max<int64_t>(1, off[nq]) * es);
+  e = e ? e : dalloc(p, &p->d_cube_off, (size_t)(nq + 1) * 8);
+  e = e ? e : dalloc(p, &p->d_dRp, (size_t)nq * kMaxNodeAtoms * 3 * 8);
+  e = e ? e : dalloc(p, &p->d_dEp, (size_t)nq * kMaxNodeAtoms * 4 * 8);
+  e = e ? e : dalloc(p, &p->d_node_atoms, (size_t)nq * (kMaxNodeAtoms + 1) * 4);
+  if (p->prob.n_proj)
+    e = e ? e : dalloc(p, &p->d_dchi, (size_t)std::max(1, p->prob.n_atoms) * B * B * B * 12 * es);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(SGQ_ENOMEM, std::string("backward workspace: ") + hipGetErrorString(e));
+  }
+  HIP_OR_FAIL(hipMemcpy(p->d_cube_off, off.data(), (nq + 1) * 8, hipMemcpyHostToDevice));
+  p->bwd_ready = true;
+  return SGQ_OK;
+}
+
 extern "C" int band_energy_backward(sgq_plan* plan, const double* v_loc, const double* atom_R,
                                     const double* proj_E, const double* node_weight, double mu,
                                     double kT, int integrand, const double* grad_omega,
                                     double* dV, double* dR_nl, double* dE, void* stream) {
-  (void)plan; (void)v_loc; (void)atom_R; (void)proj_E; (void)node_weight; (void)mu; (void)kT;
-  (void)integrand; (void)grad_omega; (void)dV; (void)dR_nl; (void)dE; (void)stream;
-  return fail(SGQ_EPLAN, "backward not built yet");
+  int st = check_call(plan, v_loc, atom_R, proj_E, mu, kT);
+  if (st != SGQ_OK) return st;
+  if (!grad_omega || !dV || (plan->prob.n_nodes > 0 && !node_weight))
+    return fail(SGQ_EINVAL, "grad_omega, dV and node_weight are required");
+  if (integrand < SGQ_BAND || integrand > SGQ_GRAND) return fail(SGQ_EINVAL, "bad integrand");
+  if (plan->kmax > backward_max_depth())
+    return fail(SGQ_EPLAN, "backward supports Lanczos depths up to " +
+                               std::to_string(backward_max_depth()));
+  HIP_OR_FAIL(hipSetDevice(plan->device));
+  st = ensure_backward(plan);
+  if (st != SGQ_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  LaunchParams P = base_params(plan, v_loc, atom_R, proj_E, mu, kT);
+  P.W = plan->d_Wb;
+  P.slot_stride = plan->bwd_slot_stride;
+  P.integrand = integrand;
+  P.node_weight = node_weight;
+  P.grad_omega = grad_omega;
+  P.P_cube = plan->d_P;
+  P.cube_offset = plan->d_cube_off;
+  P.node_atoms = plan->d_node_atoms;
+  P.dE_part = plan->d_dEp;
+  P.dR_part = plan->d_dRp;
+  P.dchi = plan->d_dchi;
+  HIP_OR_FAIL(launch_setup(P, plan->fp64, v_loc, plan->d_v, plan->d_chi, plan->d_g0, plan->d_vmax, s));
+  if (plan->prob.n_nodes > 0)
+    HIP_OR_FAIL(launch_backward(P, plan->fp64, plan->grid_bwd, 256, plan->kg, s));
+  const bool have_proj = plan->prob.n_proj > 0 && plan->prob.n_atoms > 0;
+  if (!have_proj) {
+    HIP_OR_FAIL(launch_zero(dR_nl, dR_nl ? (size_t)plan->prob.n_atoms * 3 : 0, s));
+    HIP_OR_FAIL(launch_zero(dE, dE ? (size_t)plan->prob.n_atoms * 4 : 0, s));
+  }
+  HIP_OR_FAIL(launch_backward_gather(P, plan->fp64, plan->d_cell_start, plan->d_cell_nodes,
+                                     plan->ncells, dV, dR_nl, dE, s));
+  plan->last = s;
+  return SGQ_OK;
 }
 
 extern "C" int sgq_vloc_gaussian_backward(sgq_plan* plan, const double* dV, const double* atom_R,
                                           double depth, double sigma, double cutoff_sigmas,
                                           double* dR, void* stream) {
-  (void)plan; (void)dV; (void)atom_R; (void)depth; (void)sigma; (void)cutoff_sigmas; (void)dR;
-  (void)stream;
-  return fail(SGQ_EPLAN, "not built yet");
+  if (!plan || !dV || (plan->prob.n_atoms > 0 && (!atom_R || !dR)))
+    return fail(SGQ_EINVAL, "null argument");
+  if (!(sigma > 0.0) || !(cutoff_sigmas > 0.0) || !std::isfinite(depth))
+    return fail(SGQ_EINVAL, "sigma and cutoff must be > 0, depth finite");
+  HIP_OR_FAIL(hipSetDevice(plan->device));
+  hipStream_t s = (hipStream_t)stream;
+  HIP_OR_FAIL(launch_vloc_backward(dV, atom_R, plan->prob.n_atoms, plan->prob.n[0], plan->prob.n[1],
+                                   plan->prob.n[2], plan->prob.h, depth, sigma, cutoff_sigmas, dR, s));
+  plan->last = s;
+  return SGQ_OK;
 }
 
 extern "C" int sgq_plan_status(sgq_plan* plan, int32_t* host_status) {

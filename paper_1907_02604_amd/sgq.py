@@ -222,3 +222,70 @@ def rho(prob, plan=None, want_rule=False, device="cuda"):
     if want_rule:
         return out, tw.view(prob.n_nodes, plan.kmax, 2), ke
     return out, ke
+
+
+def energy(prob, kind=SGQ_FREE, plan=None, device="cuda"):
+    """(e_node, Omega) of a ``synth.Problem`` as torch tensors."""
+    import torch
+    plan = plan or Plan.from_problem(prob)
+    v, R, E, w = device_inputs(prob, device)
+    e = torch.empty(prob.n_nodes, dtype=torch.float64, device=device)
+    om = torch.empty(1, dtype=torch.float64, device=device)
+    band_energy(plan, v, R, E, w, prob.mu, prob.kT, kind, e, om)
+    return e, om
+
+
+def energy_backward(prob, kind=SGQ_FREE, grad_omega=1.0, plan=None, device="cuda"):
+    """(dV [z,y,x], dR_nl [M,3], dE [M,4]) of Omega for a ``synth.Problem``."""
+    import torch
+    plan = plan or Plan.from_problem(prob)
+    v, R, E, w = device_inputs(prob, device)
+    g = torch.full((1,), float(grad_omega), dtype=torch.float64, device=device)
+    dV = torch.empty_like(v)
+    dR = torch.zeros_like(R)
+    dE = torch.zeros_like(E)
+    band_energy_backward(plan, v, R, E, w, prob.mu, prob.kT, kind, g, dV, dR, dE)
+    return dV, dR, dE
+
+
+def _autograd():
+    import torch
+
+    class BandEnergy(torch.autograd.Function):
+        """Omega(V_loc, R, E) = sum_q n_q e_q through libsgq, with the hand-written adjoint.
+
+        forward: band_energy; backward: band_energy_backward (dV, the projector part of
+        dR, dE).  When ``vloc_model = (depth, sigma, cutoff_sigmas)`` is given, V_loc is
+        taken as that Gaussian function of R and its chain rule is added to dR."""
+
+        @staticmethod
+        def forward(ctx, v_loc, atom_R, proj_E, plan, node_weight, mu, kT, integrand, vloc_model):
+            e = torch.empty(plan.n_nodes, dtype=torch.float64, device=v_loc.device)
+            om = torch.empty(1, dtype=torch.float64, device=v_loc.device)
+            v_loc, atom_R, proj_E = v_loc.contiguous(), atom_R.contiguous(), proj_E.contiguous()
+            band_energy(plan, v_loc, atom_R, proj_E, node_weight, mu, kT, integrand, e, om)
+            ctx.save_for_backward(v_loc, atom_R, proj_E, node_weight)
+            ctx.plan, ctx.mu, ctx.kT, ctx.integrand, ctx.vloc_model = plan, mu, kT, integrand, vloc_model
+            return om[0]
+
+        @staticmethod
+        def backward(ctx, g):
+            v_loc, atom_R, proj_E, node_weight = ctx.saved_tensors
+            gw = g.reshape(1).to(torch.float64).contiguous()
+            dV = torch.empty_like(v_loc)
+            dR = torch.zeros_like(atom_R)
+            dE = torch.zeros_like(proj_E)
+            band_energy_backward(ctx.plan, v_loc, atom_R, proj_E, node_weight, ctx.mu, ctx.kT,
+                                 ctx.integrand, gw, dV, dR, dE)
+            if ctx.vloc_model is not None:
+                depth, sigma, cutoff = ctx.vloc_model
+                vloc_gaussian_backward(ctx.plan, dV, atom_R, depth, sigma, cutoff, dR)
+            return dV, dR, dE, None, None, None, None, None, None
+
+    return BandEnergy
+
+
+def band_energy_fn(v_loc, atom_R, proj_E, plan, node_weight, mu, kT, integrand=SGQ_FREE,
+                   vloc_model=None):
+    """Differentiable Omega (a 0-d tensor) for torch autograd."""
+    return _autograd().apply(v_loc, atom_R, proj_E, plan, node_weight, mu, kT, integrand, vloc_model)
