@@ -8,17 +8,12 @@ tridiagonal and quadrature.  One step = one rho_quadrature call over all nodes
 in HBM.  Prints one JSON line.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-plain]
+                    [--plain-nodes N] [--adjoint-nodes N]
 """
-import os
-
-# The CPU baseline runs the oracle one process per core; keep BLAS single-threaded in
-# each (set before numpy is imported).
-for _var in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
-    os.environ.setdefault(_var, "1")
-
 import argparse
 import json
 import multiprocessing as mp
+import os
 import sys
 import time
 
@@ -29,6 +24,34 @@ sys.path.insert(0, ROOT)
 
 METRIC = "density nodes/sec and % HBM roofline at ≤1e-4 rel err, batched vs plain"
 HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ("sgq_common.h", "tridiag.h", "lanczos_device.h", "forward.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_lanczos_forward_64grid_8192nodes.txt")
+
+
+def kernel_source_digest():
+    """sha256 of the sources the forward kernel is built from."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1907_02604_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or None when the
+    kernel sources changed since the counters were taken."""
+    try:
+        kv = {}
+        for line in open(TRAFFIC_FILE):
+            if "=" in line and not line.lstrip().startswith("#"):
+                k, v = line.split("=", 1)
+                kv[k.strip()] = v.strip()
+        if kv.get("source_sha256") != kernel_source_digest():
+            return None
+        return float(kv["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def alg_bytes(n, K, elem=4):
@@ -42,6 +65,10 @@ def _oracle_node(args):
     cfg, q = args
     import oracle as O
     from paper_1907_02604_amd import synth
+    if "blas" not in _CACHE:
+        # one BLAS thread per worker process: the pool already uses every core
+        from threadpoolctl import threadpool_limits
+        _CACHE["blas"] = threadpool_limits(1)
     P = _CACHE.get(cfg)
     if P is None:
         P = synth.make_problem(cfg)
@@ -85,6 +112,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--plain-nodes", type=int, default=32)
+    ap.add_argument("--adjoint-nodes", type=int, default=2048)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run a 1 GiB device-to-device copy first (reference for byte counters)")
     ap.add_argument("--config", type=int, default=2, help=argparse.SUPPRESS)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -104,6 +135,12 @@ def main():
 
     import torch
     from paper_1907_02604_amd import sgq
+    if args.calibrate_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     plan = sgq.Plan.from_problem(P)
     v, R, E, _ = sgq.device_inputs(P)
     rho = torch.empty(P.n_nodes, dtype=torch.float64, device="cuda")
@@ -146,10 +183,56 @@ def main():
                                "33^3 cubes, K=60, kT=0.01, mu=-0.1, FP32 matvec / FP64 dots",
                    "grid": list(P.n), "nodes": P.n_nodes, "cube_points": n_cube, "depth": K},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "kernel": "lanczos_forward_kernel<float,256,16>",
                      "alg_bytes_per_launch": bytes_launch, "avg_launch_ms": t_launch * 1e3},
     }
+    if not args.no_plain:
+        # per-node GPU baseline: the plain schedule on a seeded node sample
+        idx = np.random.default_rng(7).choice(P.n_nodes, args.plain_nodes, replace=False)
+        Q = P.subset(np.sort(idx))
+        pplan = sgq.Plan.from_problem(Q)
+        pplan.set_schedule(sgq.SGQ_SCHEDULE_PLAIN)
+        prho = torch.empty(Q.n_nodes, dtype=torch.float64, device="cuda")
+        sgq.rho_quadrature(pplan, v, R, E, Q.mu, Q.kT, prho)       # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sgq.rho_quadrature(pplan, v, R, E, Q.mu, Q.kT, prho)
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - t0
+        assert pplan.status() == sgq.SGQ_OK
+        perr = float(np.max(np.abs(prho.cpu().numpy() - rho.cpu().numpy()[np.sort(idx)]))
+                     / np.max(np.abs(rho.cpu().numpy()[np.sort(idx)])))
+        rec["plain"] = {"value": Q.n_nodes / tp, "unit": "nodes/s", "nodes": Q.n_nodes,
+                        "schedule": "one node at a time, grid-wide kernels per Lanczos step",
+                        "rel_diff_vs_batched": perr,
+                        "batched_speedup": value / (Q.n_nodes / tp)}
+        pplan.close()
+        print(f"[bench] plain {Q.n_nodes / tp:.1f} nodes/s", file=sys.stderr, flush=True)
+    if args.adjoint_nodes > 0:
+        # adjoint throughput on the differentiation workload (48^3, 16 atoms, 33^3 cubes,
+        # K = 60): forward recompute + reverse recurrence + gathers, on a node sample
+        P4 = synth.make_problem(4)
+        idx = np.random.default_rng(8).choice(P4.n_nodes, args.adjoint_nodes, replace=False)
+        Q4 = P4.subset(np.sort(idx))
+        aplan = sgq.Plan.from_problem(Q4)
+        v4, R4, E4, w4 = sgq.device_inputs(Q4)
+        g = torch.ones(1, dtype=torch.float64, device="cuda")
+        dV = torch.empty_like(v4)
+        dR = torch.zeros_like(R4)
+        dE = torch.zeros_like(E4)
+        sgq.band_energy_backward(aplan, v4, R4, E4, w4, Q4.mu, Q4.kT, sgq.SGQ_FREE, g, dV, dR, dE)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sgq.band_energy_backward(aplan, v4, R4, E4, w4, Q4.mu, Q4.kT, sgq.SGQ_FREE, g, dV, dR, dE)
+        torch.cuda.synchronize()
+        ta = time.perf_counter() - t0
+        assert aplan.status() == sgq.SGQ_OK
+        rec["adjoint"] = {"value": Q4.n_nodes / ta, "unit": "nodes/s", "nodes": Q4.n_nodes,
+                          "workload": "48^3 grid, 16 atoms with KB projectors, 33^3 cubes, K=60, "
+                                      "FP32, dOmega/dV + dOmega/dR + dOmega/dE"}
+        aplan.close()
+        print(f"[bench] adjoint {Q4.n_nodes / ta:.1f} nodes/s", file=sys.stderr, flush=True)
     if cpu_rec is not None:
         got = rho.cpu().numpy()[sample]
         err = float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))

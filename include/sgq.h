@@ -55,6 +55,7 @@ typedef enum {
 
 enum { SGQ_FP64 = 0, SGQ_FP32 = 1 };           /* storage / matvec precision */
 enum { SGQ_BAND = 0, SGQ_FREE = 1, SGQ_GRAND = 2 };
+enum { SGQ_SCHEDULE_BATCHED = 0, SGQ_SCHEDULE_PLAIN = 1 };
 
 /* Integrands F of e_p = 2 sum_k w_k F(lambda_k), x = (lambda - mu)/kT, g = 1/(1+e^x):
  *   SGQ_BAND  F = lambda g                                  (first term of Eq. eq:tot)
@@ -130,6 +131,15 @@ int band_energy_backward(sgq_plan* plan, const double* v_loc, const double* atom
 int sgq_vloc_gaussian_backward(sgq_plan* plan, const double* dV, const double* atom_R,
                                double depth, double sigma, double cutoff_sigmas, double* dR,
                                void* stream);
+
+/* Execution schedule of rho_quadrature on this plan.
+ *   SGQ_SCHEDULE_BATCHED (default): all nodes in one persistent launch, one workgroup per
+ *                        node, the reorthogonalised Lanczos step fused as described above.
+ *   SGQ_SCHEDULE_PLAIN:  one node after another, every Lanczos step as grid-wide kernels
+ *                        (classical Gram-Schmidt against all earlier vectors); the
+ *                        per-node GPU baseline.  Same precision and depth; theta_w must be
+ *                        NULL.  Returns SGQ_EINVAL for an unknown schedule. */
+int sgq_plan_set_schedule(sgq_plan* plan, int schedule);
 
 /* Wait for the plan's last call and report a latched device-side error (SGQ_OK,
  * SGQ_ENONFINITE or SGQ_ELIMIT); the latch is cleared by the next compute call. */

@@ -25,6 +25,9 @@ hipError_t launch_backward_gather(const LaunchParams& P, bool fp64, const int32_
                                   const int32_t* cell_nodes, int ncells, double* dV, double* dR,
                                   double* dE, hipStream_t s);
 hipError_t launch_zero(double* p, size_t n, hipStream_t s);
+hipError_t launch_plain(const LaunchParams& P, bool fp64, const int32_t* h_center,
+                        const int32_t* h_hw, const int32_t* h_depth, void* scratch, hipStream_t s);
+size_t plain_scratch_bytes(size_t npad, int kmax, bool fp64);
 int backward_max_depth();
 int gather_cell();
 hipError_t launch_vloc_backward(const double* dV, const double* R, int M, int nx, int ny, int nz,
@@ -77,6 +80,8 @@ struct sgq_plan {
   int32_t* d_cell_nodes = nullptr;
   int ncells = 0;
   int ncu = 0;
+  int schedule = SGQ_SCHEDULE_BATCHED;
+  void* d_plain = nullptr;
   hipStream_t last = nullptr;
   std::vector<void*> allocs;
 };
@@ -327,7 +332,33 @@ extern "C" int rho_quadrature(sgq_plan* plan, const double* v_loc, const double*
   P.theta_w = theta_w;
   P.k_eff = k_eff;
   P.integrand = 0;
+  if (plan->schedule == SGQ_SCHEDULE_PLAIN) {
+    if (theta_w) return fail(SGQ_EPLAN, "the plain schedule does not return the Gauss rule");
+    hipStream_t s = (hipStream_t)stream;
+    HIP_OR_FAIL(hipSetDevice(plan->device));
+    if (!plan->d_plain) {
+      hipError_t e = dalloc(plan, &plan->d_plain, plain_scratch_bytes(plan->npad, plan->kmax, plan->fp64));
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(SGQ_ENOMEM, "plain schedule scratch");
+      }
+    }
+    P.slot_stride = (size_t)plan->kmax * plan->npad;
+    HIP_OR_FAIL(launch_setup(P, plan->fp64, v_loc, plan->d_v, plan->d_chi, plan->d_g0, plan->d_vmax, s));
+    HIP_OR_FAIL(launch_plain(P, plan->fp64, plan->h_center.data(), plan->h_hw.data(),
+                             plan->h_depth.data(), plan->d_plain, s));
+    plan->last = s;
+    return SGQ_OK;
+  }
   return run_forward(plan, P, v_loc, (hipStream_t)stream);
+}
+
+extern "C" int sgq_plan_set_schedule(sgq_plan* plan, int schedule) {
+  if (!plan) return fail(SGQ_EINVAL, "plan is null");
+  if (schedule != SGQ_SCHEDULE_BATCHED && schedule != SGQ_SCHEDULE_PLAIN)
+    return fail(SGQ_EINVAL, "unknown schedule");
+  plan->schedule = schedule;
+  return SGQ_OK;
 }
 
 extern "C" int band_energy(sgq_plan* plan, const double* v_loc, const double* atom_R,

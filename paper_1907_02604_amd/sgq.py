@@ -17,10 +17,11 @@ LIB_PATH = os.environ.get("SGQ_LIBRARY") or os.path.join(_HERE, "libsgq.so")
 SGQ_OK, SGQ_EINVAL, SGQ_ENOMEM, SGQ_EHIP, SGQ_EPLAN, SGQ_ENONFINITE, SGQ_ELIMIT = 0, -1, -2, -3, -4, -5, -6
 SGQ_FP64, SGQ_FP32 = 0, 1
 SGQ_BAND, SGQ_FREE, SGQ_GRAND = 0, 1, 2
+SGQ_SCHEDULE_BATCHED, SGQ_SCHEDULE_PLAIN = 0, 1
 
 EXPORTED = ("sgq_plan_create", "sgq_plan_destroy", "rho_quadrature", "band_energy",
             "band_energy_backward", "sgq_vloc_gaussian_backward", "sgq_plan_status",
-            "sgq_last_error", "sgq_validate", "sgq_gauss_rule_host")
+            "sgq_last_error", "sgq_validate", "sgq_gauss_rule_host", "sgq_plan_set_schedule")
 
 
 class SgqError(RuntimeError):
@@ -52,6 +53,7 @@ def _load():
         "sgq_last_error": (ctypes.c_char_p, []),
         "sgq_validate": (I, [ctypes.POINTER(Problem), P, P, P]),
         "sgq_gauss_rule_host": (I, [P, P, I, P, P]),
+        "sgq_plan_set_schedule": (I, [P, I]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -155,6 +157,10 @@ class Plan:
     @property
     def handle(self):
         return self._h
+
+    def set_schedule(self, schedule):
+        """SGQ_SCHEDULE_BATCHED (default) or SGQ_SCHEDULE_PLAIN (per-node baseline)."""
+        _check(_lib.sgq_plan_set_schedule(self._h, int(schedule)))
 
     def status(self):
         st = ctypes.c_int32(0)

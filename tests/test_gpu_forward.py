@@ -197,3 +197,25 @@ def test_bitwise_deterministic():
     a, _, _ = gpu_rho(P)
     b, _, _ = gpu_rho(P)
     assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("precision,tol", [("f32", FP32_TOL), ("f64", FP64_TOL)])
+def test_plain_schedule_matches_oracle(precision, tol):
+    """The per-node baseline schedule computes the same densities (64^3 workload, 6 nodes)."""
+    import torch
+    from paper_1907_02604_amd import sgq
+    P = synth.make_problem(2).subset(np.arange(6))
+    ref, _ = oracle_rho(P, range(P.n_nodes))
+    prec = sgq.SGQ_FP64 if precision == "f64" else sgq.SGQ_FP32
+    plan = sgq.Plan(P.n, P.h, P.atoms.shape[0], P.n_proj, P.centers, P.half_width, P.depth, prec)
+    plan.set_schedule(sgq.SGQ_SCHEDULE_PLAIN)
+    v, R, E, _ = sgq.device_inputs(P)
+    rho = torch.empty(P.n_nodes, dtype=torch.float64, device="cuda")
+    announce(f"plain schedule {precision}")
+    sgq.rho_quadrature(plan, v, R, E, P.mu, P.kT, rho)
+    torch.cuda.synchronize()
+    assert plan.status() == 0
+    err = O.normwise_rel_err(rho.cpu().numpy(), ref)
+    print("plain err", err)
+    assert err < tol
+    plan.close()
