@@ -111,7 +111,7 @@ __device__ __noinline__ void projector_adjoint(const SGQ_G double* proj_E,
                                                SGQ_L NodeState<T, BLOCK>& st, SGQ_L BwdState& bs,
                                                const SGQ_G T* __restrict__ chi,
                                                const SGQ_G T* __restrict__ dchi,
-                                               const SGQ_G T* ub, const SGQ_G T* Wj, double sj,
+                                               const SGQ_G T* ub, const SGQ_G T* Wj, int wbs, double sj,
                                                double h3, int B, int B3) {
   using T4 = T __attribute__((ext_vector_type(4)));
   constexpr int NW = BLOCK / kWave;
@@ -126,7 +126,7 @@ __device__ __noinline__ void projector_adjoint(const SGQ_G double* proj_E,
       const int lp = box_point(st, a, b, B);
       if (lp < 0) continue;
       const T u = ub[lp];
-      const T qv = Wj[lp] * (T)sj;
+      const T qv = Wj[bidx(lp, wbs)] * (T)sj;
       const T4 c4 = *reinterpret_cast<const SGQ_G T4*>(chi + ((size_t)J * B3 + b) * 4);
       const SGQ_G T* g = dchi + ((size_t)J * B3 + b) * 12;
 #pragma unroll
@@ -181,6 +181,7 @@ __global__ __launch_bounds__(BLOCK) void lanczos_backward_kernel(LaunchParams P)
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
   const size_t npad = P.npad;
   const int kmax = P.kmax_out;
+  const int wbs = P.wbs;
   SGQ_G T* __restrict__ W = (SGQ_G T*)P.W + (size_t)blockIdx.x * P.slot_stride;
   SGQ_G T* __restrict__ Ubase = W + (size_t)kmax * npad;
   SGQ_G T* __restrict__ R[3] = {Ubase + (size_t)kmax * npad, Ubase + (size_t)(kmax + 1) * npad,
@@ -189,6 +190,7 @@ __global__ __launch_bounds__(BLOCK) void lanczos_backward_kernel(LaunchParams P)
   const SGQ_G T* __restrict__ V = (const SGQ_G T*)P.v;
   const SGQ_G T* __restrict__ chi = (const SGQ_G T*)P.chi;
   const SGQ_G T* __restrict__ dchi = (const SGQ_G T*)P.dchi;
+  const ProjEval<T> pe = proj_eval<T>(P);
   const SGQ_G double* proj_E = (const SGQ_G double*)P.proj_E;
   const double h = P.h, h3 = h * h * h;
   const T kin = (T)(-0.5 / (h * h));
@@ -271,9 +273,10 @@ __global__ __launch_bounds__(BLOCK) void lanczos_backward_kernel(LaunchParams P)
     // ---- reverse recurrence
     int r0 = 0, r1 = 1, r2 = 2;
     for (int j = keff - 1; j >= 0; --j) {
-      const SGQ_G T* Wc = W + (size_t)j * npad;
-      const SGQ_G T* Wn = W + (size_t)(j + 1) * npad;
-      const SGQ_G T* Wp = W + (size_t)(j > 0 ? j - 1 : 0) * npad;
+      // rows of the point-blocked basis (block stride wbs)
+      const SGQ_G T* Wc = W + 64 * j;
+      const SGQ_G T* Wn = W + 64 * (j + 1);
+      const SGQ_G T* Wp = W + 64 * (j > 0 ? j - 1 : 0);
       const SGQ_G T* Uj = Ubase + (size_t)j * npad;
       SGQ_G T* Q0 = R[r0];
       SGQ_G T* Q1 = R[r1];
@@ -287,9 +290,9 @@ __global__ __launch_bounds__(BLOCK) void lanczos_backward_kernel(LaunchParams P)
         double d[5] = {0, 0, 0, 0, 0};
         for (int p = tid; p < n; p += BLOCK) {
           const double qb = (double)Q0[p];
-          const double qn = sn * (double)Wn[p];
-          const double qc = sc_ * (double)Wc[p];
-          const double qp = sp * (double)Wp[p];
+          const double qn = sn * (double)Wn[bidx(p, wbs)];
+          const double qc = sc_ * (double)Wc[bidx(p, wbs)];
+          const double qp = sp * (double)Wp[bidx(p, wbs)];
           d[0] += qb * qn;
           d[1] += qb * qc;
           d[2] += qb * qp;
@@ -327,8 +330,8 @@ __global__ __launch_bounds__(BLOCK) void lanczos_backward_kernel(LaunchParams P)
         const double al = st.alpha[j];
         const double bprev = j > 0 ? st.beta[j - 1] : 0.0;
         for (int p = tid; p < n; p += BLOCK) {
-          const double qc = sc_ * (double)Wc[p];
-          const double rb = last ? 0.0 : (double)Q0[p] * ib + bb * sn * (double)Wn[p];
+          const double qc = sc_ * (double)Wc[bidx(p, wbs)];
+          const double rb = last ? 0.0 : (double)Q0[p] * ib + bb * sn * (double)Wn[bidx(p, wbs)];
           const double ub = rb + ahat * qc;
           UB[p] = (T)ub;
           Pq[p] = (T)((last ? 0.0 : (double)Pq[p]) + ub * qc);
@@ -338,10 +341,10 @@ __global__ __launch_bounds__(BLOCK) void lanczos_backward_kernel(LaunchParams P)
       }
       __syncthreads();
       // pass C: qbar_j += H ubar_j, with the projector adjoints of this step
-      if (natoms > 0) projector_adjoint<T, BLOCK>(proj_E, st, bs, chi, dchi, UB, Wc, sc_, h3, B, B3);
-      apply_local<T, BLOCK, true>(P, st, V, UB, Q1, (T)1, kin);
+      if (natoms > 0) projector_adjoint<T, BLOCK>(proj_E, st, bs, chi, dchi, UB, Wc, wbs, sc_, h3, B, B3);
+      apply_local<T, BLOCK, true>(P, st, V, UB, 64, Q1, (T)1, kin);
       __syncthreads();
-      apply_scatter<T, BLOCK>(P, st, chi, Q1, B, B3);
+      apply_scatter<T, BLOCK>(P, st, pe, Q1, B, B3);
       __syncthreads();
       const int t0 = r0;
       r0 = r1;

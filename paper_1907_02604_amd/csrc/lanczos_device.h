@@ -9,7 +9,7 @@
 namespace sgq {
 
 
-constexpr int kMarchPlane = 5 * 256;  // largest cube cross-section of the plane march
+constexpr int kMarchPad = 1700;  // padded plane (sx + 6)(sy + 6) of the plane march (sx <= 35)
 
 template <typename T, int BLOCK>
 struct NodeState {
@@ -22,6 +22,7 @@ struct NodeState {
   int grp[kMaxNodeAtoms];           // the parallel group, in atom order
   int ngrp;
   int wcount[NW];
+  T afrac[kMaxNodeAtoms][4];        // g0 h - R of each node atom (x, y, z): box offsets
   T acoef[kMaxNodeAtoms][4];        // E h^3 (chi . q): weights of the projector scatter
   double anl[kMaxNodeAtoms];        // q . V_nl q contribution of each atom
   double alpha[kMaxDepth];
@@ -35,7 +36,7 @@ struct NodeState {
   double orth_tol;
   int redo;
   int wflag[NW];
-  T plane[2][kMarchPlane];          // z planes of the cube for the stencil march
+  T plane[2][kMarchPad];            // z planes of the cube (zero halo of 3) for the march
 };
 
 // local linear index -> (x, y, z) of a cube with extents sx, sy
@@ -49,10 +50,10 @@ __device__ __forceinline__ void unflatten(int p, int sx, int sxy, float inv_sx, 
   if (x < 0) { --y; x += sx; } else if (x >= sx) { ++y; x -= sx; }
 }
 
-// Projector box point b of node atom a -> local linear index, or -1 outside the cube.
+// Projector box point (bx, by, bz) of node atom a -> local linear index, or -1 outside
+// the cube.
 template <typename S>
-__device__ __forceinline__ int box_point(const S& st, int a, int b, int B) {
-  int bx = b % B, by = (b / B) % B, bz = b / (B * B);
+__device__ __forceinline__ int box_point(const S& st, int a, int bx, int by, int bz) {
   int x = st.abox[a][0] + bx, y = st.abox[a][1] + by, z = st.abox[a][2] + bz;
   if (st.periodic) {
     x = wrap_index(x, st.sx);
@@ -62,6 +63,51 @@ __device__ __forceinline__ int box_point(const S& st, int a, int b, int B) {
     return -1;
   }
   return x + st.sx * (y + st.sy * z);
+}
+
+template <typename S>
+__device__ __forceinline__ int box_point(const S& st, int a, int b, int B) {
+  return box_point(st, a, b % B, (b / B) % B, b / (B * B));
+}
+
+// The four projectors of one atom (s, px, py, pz: Gaussian of width rg times the
+// smooth cutoff (1 - r^2/rc^2)^3, continuum-normalised), evaluated at a box point from
+// the atom's offset f = g0 h - R instead of being read from a table.
+template <typename T>
+struct ProjEval {
+  T h, ns, npr, inv_rc2, k2;
+  int m;
+};
+
+template <typename T>
+__host__ __device__ inline ProjEval<T> proj_eval(const LaunchParams& P) {
+  ProjEval<T> e;
+  e.h = (T)P.h;
+  e.ns = (T)P.proj_norm_s;
+  e.npr = (T)(P.proj_norm_p / P.proj_rg);
+  e.inv_rc2 = (T)(1.0 / (P.proj_rc * P.proj_rc));
+  e.k2 = (T)(0.5 / (P.proj_rg * P.proj_rg));
+  e.m = P.box_m;
+  return e;
+}
+
+__device__ __forceinline__ float exp_neg(float x) { return __expf(-x); }
+__device__ __forceinline__ double exp_neg(double x) { return exp(-x); }
+
+template <typename T, typename F>
+__device__ __forceinline__ void chi_at(const ProjEval<T>& pe, const F& f, int bx, int by, int bz,
+                                       T (&c)[4]) {
+  const T dx = (T)(bx - pe.m) * pe.h + f[0];
+  const T dy = (T)(by - pe.m) * pe.h + f[1];
+  const T dz = (T)(bz - pe.m) * pe.h + f[2];
+  const T r2 = dx * dx + dy * dy + dz * dz;
+  const T t = (T)1 - r2 * pe.inv_rc2;
+  const T g = t > (T)0 ? exp_neg(r2 * pe.k2) * (t * t * t) : (T)0;
+  const T gp = pe.npr * g;
+  c[0] = pe.ns * g;
+  c[1] = gp * dx;
+  c[2] = gp * dy;
+  c[3] = gp * dz;
 }
 
 // Sets up the cube geometry and the node's projector atom list (ordered by atom id).
@@ -123,6 +169,9 @@ __device__ __noinline__ void node_setup(const LaunchParams& P, SGQ_L NodeState<T
         st.abox[slot][0] = lo[0];
         st.abox[slot][1] = lo[1];
         st.abox[slot][2] = lo[2];
+        for (int ax = 0; ax < 3; ++ax)
+          st.afrac[slot][ax] = (T)(P.atom_g0[3 * J + ax] * P.h - P.atom_R[3 * J + ax]);
+        st.afrac[slot][3] = (T)0;
       }
     }
     __syncthreads();
@@ -172,22 +221,47 @@ __device__ __noinline__ void node_setup(const LaunchParams& P, SGQ_L NodeState<T
   __syncthreads();
 }
 
+// Buffer resource over `bytes` bytes from `base` (raw, unswizzled): loads at offsets at
+// or beyond `bytes` return zero without touching memory.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_over(const void* base, int bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, bytes, 0x00020000);
+}
+
+template <typename V>
+__device__ __forceinline__ V buffer_load(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  if constexpr (sizeof(V) == 16)
+    return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+  else if constexpr (sizeof(V) == 8)
+    return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+  else
+    return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+
 // dst(p) = src(p) - sum_{i<=j} ct_i W_i(p) for every cube point, with the FP64 dots
 // D_i = W_i . dst and |dst|^2 left per wave in st.red.
 //
-// Layout: four lanes share a point group of VEC consecutive points, each lane taking
-// the basis vectors i = g (mod 4), i.e. KS "slots" i = 4m + g, m < KS.  A lane handles
-// PU point groups per iteration, so one iteration issues KS*PU vector loads before any
-// of them is consumed; the variants keep KS*PU*VEC near 64 registers of loads in
-// flight whatever the step (few slots and many groups early in the recurrence, many
-// slots and few groups late).  Row tails [n, npad) of W are kept zero.
+// The basis is stored in 64-point blocks, [npad/64][kmax][64] (block stride bs), so rows
+// 0..j of one block are a single contiguous run.  Four lanes share a point group of VEC
+// consecutive points, each lane taking the rows i = g (mod 4), i.e. KS "slots"
+// i = 4m + g; with VEC = 4 one load instruction of a wave reads four whole 256-byte rows
+// of a block.  A lane handles PU point groups per iteration, so one iteration issues
+// KS*PU vector loads before any of them is consumed.  Rows are addressed through a
+// buffer resource: one 32-bit lane offset plus a uniform per-slot offset.  Rows i > j of
+// the last slot are read from row j (finite data) and weighted zero.  src and dst are
+// row views with block strides sbs and bs.
 template <typename T, int BLOCK, int KS, int PU, int VEC>
 __device__ __noinline__ void fused_sweep_v(SGQ_L NodeState<T, BLOCK>& st,
-                                           const SGQ_G T* __restrict__ W, const SGQ_G T* src,
-                                           SGQ_G T* dst, int j, int n, size_t npad) {
+                                           const SGQ_G T* __restrict__ W, int bs, int wbytes,
+                                           const SGQ_G T* src, int sbs, SGQ_G T* dst, int j,
+                                           int n) {
   using V = T __attribute__((ext_vector_type(VEC)));
+  constexpr int ES = (int)sizeof(T);
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
   const int g = lane & 3;
+  const __amdgpu_buffer_rsrc_t rw = buffer_over((const void*)W, wbytes);
+  const int mlast = j / 4;        // last slot holding a row <= j
+  const int rlast = 4 * mlast + g <= j ? 4 * mlast + g : j;
+  const int dlast = (rlast - g - 4 * mlast) * 64 * ES;
   double D[KS];
   T cg[KS];
 #pragma unroll
@@ -206,14 +280,17 @@ __device__ __noinline__ void fused_sweep_v(SGQ_L NodeState<T, BLOCK>& st,
     for (int u = 0; u < PU; ++u) {
       const int pg = pg0 + u * STRIDE;
       const int p0 = (pg < ngroups ? pg : 0) * VEC;
+      const int voff = (bidx(p0, bs) + 64 * g) * ES;
 #pragma unroll
       for (int m = 0; m < KS; ++m) {
-        const int i = 4 * m + g;
-        // rows i > j are read from row j (finite data) and weighted by cg = 0; their
-        // D sums are never stored
-        qv[u][m] = *reinterpret_cast<const SGQ_G V*>(W + (size_t)(i <= j ? i : j) * npad + p0);
+        if (m < mlast)
+          qv[u][m] = buffer_load<V>(rw, voff, m * 256 * ES);
+        else if (m == mlast)
+          qv[u][m] = buffer_load<V>(rw, voff + dlast, m * 256 * ES);
+        else
+          qv[u][m] = (V)(T)0;
       }
-      sv[u] = *reinterpret_cast<const SGQ_G V*>(src + p0);
+      sv[u] = *reinterpret_cast<const SGQ_G V*>(src + bidx(p0, sbs));
     }
 #pragma unroll
     for (int u = 0; u < PU; ++u) {
@@ -232,7 +309,7 @@ __device__ __noinline__ void fused_sweep_v(SGQ_L NodeState<T, BLOCK>& st,
       for (int k = 0; k < VEC; ++k)
         if (pg >= ngroups || p0 + k >= n) w[k] = (T)0;
       if (g == 0 && pg < ngroups) {
-        *reinterpret_cast<SGQ_G V*>(dst + p0) = w;
+        *reinterpret_cast<SGQ_G V*>(dst + bidx(p0, bs)) = w;
 #pragma unroll
         for (int k = 0; k < VEC; ++k) n2 += (double)w[k] * (double)w[k];
       }
@@ -260,21 +337,22 @@ __device__ __noinline__ void fused_sweep_v(SGQ_L NodeState<T, BLOCK>& st,
 // Picks the sweep variant for step j (slots KS >= (j+1)/4, at most KG).
 template <typename T, int BLOCK, int KG>
 __device__ __forceinline__ void fused_sweep(SGQ_L NodeState<T, BLOCK>& st,
-                                            const SGQ_G T* __restrict__ W, const SGQ_G T* src,
-                                            SGQ_G T* dst, int j, int n, size_t npad) {
+                                            const SGQ_G T* __restrict__ W, int bs, int wbytes,
+                                            const SGQ_G T* src, int sbs, SGQ_G T* dst, int j,
+                                            int n) {
   const int need = j / 4 + 1;
   if constexpr (sizeof(T) == 4) {
-    if (need <= 2) return fused_sweep_v<T, BLOCK, 2, 8, 4>(st, W, src, dst, j, n, npad);
-    if (need <= 4) return fused_sweep_v<T, BLOCK, 4, 4, 4>(st, W, src, dst, j, n, npad);
-    if (KG <= 8 || need <= 8) return fused_sweep_v<T, BLOCK, 8, 4, 2>(st, W, src, dst, j, n, npad);
-    if (KG <= 16 || need <= 16) return fused_sweep_v<T, BLOCK, 16, 2, 2>(st, W, src, dst, j, n, npad);
-    return fused_sweep_v<T, BLOCK, 32, 1, 1>(st, W, src, dst, j, n, npad);
+    if (need <= 2) return fused_sweep_v<T, BLOCK, 2, 4, 4>(st, W, bs, wbytes, src, sbs, dst, j, n);
+    if (need <= 4) return fused_sweep_v<T, BLOCK, 4, 2, 4>(st, W, bs, wbytes, src, sbs, dst, j, n);
+    if (need <= 8) return fused_sweep_v<T, BLOCK, 8, 1, 4>(st, W, bs, wbytes, src, sbs, dst, j, n);
+    if (KG <= 16 || need <= 16) return fused_sweep_v<T, BLOCK, 16, 1, 2>(st, W, bs, wbytes, src, sbs, dst, j, n);
+    return fused_sweep_v<T, BLOCK, 32, 1, 1>(st, W, bs, wbytes, src, sbs, dst, j, n);
   } else {
-    if (need <= 2) return fused_sweep_v<T, BLOCK, 2, 8, 2>(st, W, src, dst, j, n, npad);
-    if (need <= 4) return fused_sweep_v<T, BLOCK, 4, 4, 2>(st, W, src, dst, j, n, npad);
-    if (KG <= 8 || need <= 8) return fused_sweep_v<T, BLOCK, 8, 4, 1>(st, W, src, dst, j, n, npad);
-    if (KG <= 16 || need <= 16) return fused_sweep_v<T, BLOCK, 16, 2, 1>(st, W, src, dst, j, n, npad);
-    return fused_sweep_v<T, BLOCK, 32, 1, 1>(st, W, src, dst, j, n, npad);
+    if (need <= 2) return fused_sweep_v<T, BLOCK, 2, 4, 2>(st, W, bs, wbytes, src, sbs, dst, j, n);
+    if (need <= 4) return fused_sweep_v<T, BLOCK, 4, 2, 2>(st, W, bs, wbytes, src, sbs, dst, j, n);
+    if (need <= 8) return fused_sweep_v<T, BLOCK, 8, 2, 1>(st, W, bs, wbytes, src, sbs, dst, j, n);
+    if (KG <= 16 || need <= 16) return fused_sweep_v<T, BLOCK, 16, 1, 1>(st, W, bs, wbytes, src, sbs, dst, j, n);
+    return fused_sweep_v<T, BLOCK, 32, 1, 1>(st, W, bs, wbytes, src, sbs, dst, j, n);
   }
 }
 
@@ -316,35 +394,50 @@ __device__ __forceinline__ void finish_sweep(SGQ_L NodeState<T, BLOCK>& st, int 
 }
 
 // chi . q_j of every node atom (projector overlaps).  A wave takes NA atoms at a time
-// with every box point of all of them unrolled, so their loads are in flight together.
+// with every box point of all of them unrolled, so their loads are in flight together;
+// the projector values are evaluated in registers.
 template <typename T, int BLOCK>
 __device__ __noinline__ void projector_dots(const SGQ_G double* proj_E,
-                                            SGQ_L NodeState<T, BLOCK>& st,
-                                            const SGQ_G T* __restrict__ chi, const SGQ_G T* Wj,
-                                            double sjd, double h3, int B, int B3) {
-  using T4 = T __attribute__((ext_vector_type(4)));
+                                            SGQ_L NodeState<T, BLOCK>& st, ProjEval<T> pe,
+                                            const SGQ_G T* Wj, int bs, double sjd, double h3,
+                                            int B, int B3) {
   constexpr int NW = BLOCK / kWave;
   constexpr int UNR = 6;    // 6 x 64 box points cover the 7^3 box of h = rc/3
+  constexpr int NA = sizeof(T) == 4 ? 3 : 1;
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   const int natoms = st.natoms;
-  constexpr int NA = 4;
   for (int a0 = NA * wave; a0 < natoms; a0 += NA * NW) {
-    T4 acc[NA];
+    T acc[NA][4];
 #pragma unroll
-    for (int t = 0; t < NA; ++t) acc[t] = (T4)(T)0;
+    for (int t = 0; t < NA; ++t)
+#pragma unroll
+      for (int l = 0; l < 4; ++l) acc[t][l] = (T)0;
     for (int b0 = 0; b0 < B3; b0 += UNR * kWave) {
+      int bc[UNR][3];
+      T wv[NA][UNR];
 #pragma unroll
       for (int u = 0; u < UNR; ++u) {
         const int b = b0 + u * kWave + lane;
+        bc[u][0] = b % B;
+        bc[u][1] = (b / B) % B;
+        bc[u][2] = b / (B * B);
 #pragma unroll
         for (int t = 0; t < NA; ++t) {
           const int a = a0 + t;
           const bool live = (b < B3) && (a < natoms);
-          const int lp = live ? box_point(st, a, b, B) : -1;
-          const int J = st.atom[a < natoms ? a : a0];
-          const T wv = Wj[lp >= 0 ? lp : 0] * (T)(lp >= 0);
-          const T4 c = *reinterpret_cast<const SGQ_G T4*>(chi + ((size_t)J * B3 + (live ? b : 0)) * 4);
-          acc[t] += c * wv;
+          const int lp = live ? box_point(st, a, bc[u][0], bc[u][1], bc[u][2]) : -1;
+          wv[t][u] = Wj[bidx(lp >= 0 ? lp : 0, bs)] * (T)(lp >= 0);
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < NA; ++t) {
+        const int a = a0 + t < natoms ? a0 + t : a0;
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+          T c[4];
+          chi_at(pe, st.afrac[a], bc[u][0], bc[u][1], bc[u][2], c);
+#pragma unroll
+          for (int l = 0; l < 4; ++l) acc[t][l] += c[l] * wv[t][u];
         }
       }
     }
@@ -370,38 +463,40 @@ __device__ __noinline__ void projector_dots(const SGQ_G double* proj_E,
 // at `first` cover its box points (lanes == 1: one point at a time, for grids narrower
 // than the box where box points alias).
 template <typename T, int BLOCK>
-__device__ __noinline__ void scatter_atom(SGQ_L NodeState<T, BLOCK>& st,
-                                          const SGQ_G T* __restrict__ chi, SGQ_G T* U, int a,
-                                          int B, int B3, int first, int lanes) {
-  using T4 = T __attribute__((ext_vector_type(4)));
-  const int J = st.atom[a];
-  const T4 coef = {st.acoef[a][0], st.acoef[a][1], st.acoef[a][2], st.acoef[a][3]};
+__device__ __noinline__ void scatter_atom(SGQ_L NodeState<T, BLOCK>& st, ProjEval<T> pe,
+                                          SGQ_G T* U, int a, int B, int B3, int first,
+                                          int lanes) {
+  const T coef[4] = {st.acoef[a][0], st.acoef[a][1], st.acoef[a][2], st.acoef[a][3]};
   if (lanes == 1) {
     for (int b = 0; b < B3; ++b) {
-      int lp = box_point(st, a, b, B);
+      const int bx = b % B, by = (b / B) % B, bz = b / (B * B);
+      int lp = box_point(st, a, bx, by, bz);
       if (lp < 0) continue;
-      T4 prod = *reinterpret_cast<const SGQ_G T4*>(chi + ((size_t)J * B3 + b) * 4) * coef;
-      U[lp] += prod[0] + prod[1] + prod[2] + prod[3];
+      T c[4];
+      chi_at(pe, st.afrac[a], bx, by, bz, c);
+      U[lp] += c[0] * coef[0] + c[1] * coef[1] + c[2] * coef[2] + c[3] * coef[3];
     }
     return;
   }
   constexpr int UNR = 6;
   for (int b0 = first; b0 < B3; b0 += UNR * lanes) {
-    int lp[UNR];
+    int lp[UNR], bc[UNR][3];
     T old[UNR];
-    T4 c[UNR];
 #pragma unroll
     for (int u = 0; u < UNR; ++u) {
       const int b = b0 + u * lanes;
-      lp[u] = b < B3 ? box_point(st, a, b, B) : -1;
+      bc[u][0] = b % B;
+      bc[u][1] = (b / B) % B;
+      bc[u][2] = b / (B * B);
+      lp[u] = b < B3 ? box_point(st, a, bc[u][0], bc[u][1], bc[u][2]) : -1;
       old[u] = U[lp[u] >= 0 ? lp[u] : 0];
-      c[u] = *reinterpret_cast<const SGQ_G T4*>(chi + ((size_t)J * B3 + (b < B3 ? b : 0)) * 4);
     }
 #pragma unroll
     for (int u = 0; u < UNR; ++u) {
       if (lp[u] >= 0) {
-        T4 prod = c[u] * coef;
-        U[lp[u]] = old[u] + (prod[0] + prod[1] + prod[2] + prod[3]);
+        T c[4];
+        chi_at(pe, st.afrac[a], bc[u][0], bc[u][1], bc[u][2], c);
+        U[lp[u]] = old[u] + (c[0] * coef[0] + c[1] * coef[1] + c[2] * coef[2] + c[3] * coef[3]);
       }
     }
   }
@@ -411,12 +506,10 @@ __device__ __noinline__ void scatter_atom(SGQ_L NodeState<T, BLOCK>& st,
 // updates never touch the same point.  A wave takes NA of them per round with all the
 // loads of the round issued before any update.
 template <typename T, int BLOCK>
-__device__ __noinline__ void scatter_group(SGQ_L NodeState<T, BLOCK>& st,
-                                           const SGQ_G T* __restrict__ chi, SGQ_G T* U, int B,
-                                           int B3) {
-  using T4 = T __attribute__((ext_vector_type(4)));
+__device__ __noinline__ void scatter_group(SGQ_L NodeState<T, BLOCK>& st, ProjEval<T> pe,
+                                           SGQ_G T* U, int B, int B3) {
   constexpr int NW = BLOCK / kWave;
-  constexpr int NA = 3;
+  constexpr int NA = sizeof(T) == 4 ? 3 : 1;
   constexpr int UNR = 6;    // 6 x 64 box points cover the 7^3 box of h = rc/3
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   // atoms of the group (st.grp, in atom order) dealt round-robin to the waves
@@ -425,30 +518,33 @@ __device__ __noinline__ void scatter_group(SGQ_L NodeState<T, BLOCK>& st,
   auto mine = [&](int i) { return st.grp[wave + NW * i]; };
   for (int i0 = 0; i0 < cnt; i0 += NA) {
     for (int b0 = 0; b0 < B3; b0 += UNR * kWave) {
+      int bc[UNR][3];
       int lp[NA][UNR];
       T old[NA][UNR];
-      T4 c[NA][UNR];
 #pragma unroll
-      for (int t = 0; t < NA; ++t) {
-        const int a = i0 + t < cnt ? mine(i0 + t) : mine(i0);
-        const int J = st.atom[a];
+      for (int u = 0; u < UNR; ++u) {
+        const int b = b0 + u * kWave + lane;
+        bc[u][0] = b % B;
+        bc[u][1] = (b / B) % B;
+        bc[u][2] = b / (B * B);
 #pragma unroll
-        for (int u = 0; u < UNR; ++u) {
-          const int b = b0 + u * kWave + lane;
-          lp[t][u] = (b < B3 && i0 + t < cnt) ? box_point(st, a, b, B) : -1;
+        for (int t = 0; t < NA; ++t) {
+          const int a = i0 + t < cnt ? mine(i0 + t) : mine(i0);
+          lp[t][u] = (b < B3 && i0 + t < cnt) ? box_point(st, a, bc[u][0], bc[u][1], bc[u][2]) : -1;
           old[t][u] = U[lp[t][u] >= 0 ? lp[t][u] : 0];
-          c[t][u] = *reinterpret_cast<const SGQ_G T4*>(chi + ((size_t)J * B3 + (b < B3 ? b : 0)) * 4);
         }
       }
 #pragma unroll
       for (int t = 0; t < NA; ++t) {
         const int a = i0 + t < cnt ? mine(i0 + t) : mine(i0);
-        const T4 coef = {st.acoef[a][0], st.acoef[a][1], st.acoef[a][2], st.acoef[a][3]};
+        const T coef[4] = {st.acoef[a][0], st.acoef[a][1], st.acoef[a][2], st.acoef[a][3]};
 #pragma unroll
         for (int u = 0; u < UNR; ++u) {
           if (lp[t][u] >= 0) {
-            T4 prod = c[t][u] * coef;
-            U[lp[t][u]] = old[t][u] + (prod[0] + prod[1] + prod[2] + prod[3]);
+            T c[4];
+            chi_at(pe, st.afrac[a], bc[u][0], bc[u][1], bc[u][2], c);
+            U[lp[t][u]] = old[t][u] +
+                          (c[0] * coef[0] + c[1] * coef[1] + c[2] * coef[2] + c[3] * coef[3]);
           }
         }
       }
@@ -463,8 +559,8 @@ template <typename T, int BLOCK, bool ACC = false>
 __device__ __noinline__ double stencil_cube(int gnx, int gny, int gnz,
                                             const SGQ_L NodeState<T, BLOCK>& st,
                                             const SGQ_G T* __restrict__ V,
-                                            const SGQ_G T* __restrict__ Wj, SGQ_G T* __restrict__ U,
-                                            T sj, T kin) {
+                                            const SGQ_G T* __restrict__ Wj, int vbs,
+                                            SGQ_G T* __restrict__ U, T sj, T kin) {
   const int n = st.n, sx = st.sx, sy = st.sy, sz = st.sz, sxy = sx * sy;
   const float inv_sx = 1.0f / (float)sx, inv_sxy = 1.0f / (float)sxy;
   const T w0 = (T)(3.0 * kFd0), w1 = (T)kFd1, w2 = (T)kFd2, w3 = (T)kFd3;
@@ -481,10 +577,10 @@ __device__ __noinline__ double stencil_cube(int gnx, int gny, int gnz,
       pk[k] = p;
       int x, y, z;
       unflatten(pc, sx, sxy, inv_sx, inv_sxy, x, y, z);
-      const T c = Wj[pc];
+      const T c = Wj[bidx(pc, vbs)];
       wc[k] = c;
       auto nb = [&](bool ok, int idx) -> T {
-        T v = Wj[ok ? idx : pc];
+        T v = Wj[bidx(ok ? idx : pc, vbs)];
         return ok ? v : (T)0;
       };
       T l1 = nb(x >= 1, pc - 1) + nb(x + 1 < sx, pc + 1) + nb(y >= 1, pc - sx) +
@@ -514,26 +610,31 @@ __device__ __noinline__ double stencil_cube(int gnx, int gny, int gnz,
 
 // u = s_j (-1/2 Lap_6 + V) W_j on a Dirichlet cube by marching through the z planes.
 // Thread t owns the in-plane points t + k*BLOCK (k < PPT) of every plane.  Their values
-// at planes z-3 .. z+6 live in a register ring indexed statically (the z loop is
-// unrolled by the ring length), so a plane is loaded four planes before it is first
-// used and the potential five planes before; x/y neighbours of plane z come from a
-// double-buffered copy of the plane in LDS (one barrier per plane).  Returns this
-// thread's part of q_j . u.
+// at planes z-3 .. z+NQ-4 live in a register ring indexed statically (the z loop is
+// unrolled by the ring length), so a plane is loaded NQ-6 planes before it is first
+// used; the potential is loaded NV planes ahead.  The x/y neighbours of plane z come
+// from a double-buffered copy of the plane in LDS with a zero halo three points wide,
+// which makes every neighbour a fixed offset (no clamping, no masks); one barrier per
+// plane.  Returns this thread's part of q_j . u.
 template <typename T, int BLOCK, int PPT, bool ACC = false>
 __device__ __noinline__ double stencil_march(int gnx, int gny, int gnz,
                                              SGQ_L NodeState<T, BLOCK>& st,
                                              const SGQ_G T* __restrict__ V,
-                                             const SGQ_G T* __restrict__ Wj, SGQ_G T* __restrict__ U,
-                                             T sj, T kin) {
-  constexpr int NQ = 10;   // ring of W planes z-3 .. z+6
-  constexpr int NV = 5;    // ring of V planes z .. z+4
+                                             const SGQ_G T* __restrict__ Wj, int vbs,
+                                             SGQ_G T* __restrict__ U, T sj, T kin) {
+  constexpr int NQ = 8;    // ring of W planes z-3 .. z+4
+  constexpr int NV = 4;    // ring of V planes z .. z+3
+  static_assert(NQ % NV == 0, "the unrolled z loop indexes both rings by r = z mod NQ");
   const int sx = st.sx, sy = st.sy, sz = st.sz, sxy = sx * sy;
+  const int rx = sx + 6;   // padded row
   const int tid = threadIdx.x;
   const int vplane = gnx * gny;
   const T w0 = (T)(3.0 * kFd0), w1 = (T)kFd1, w2 = (T)kFd2, w3 = (T)kFd3;
+  for (int i = tid; i < 2 * kMarchPad; i += BLOCK) (&st.plane[0][0])[i] = (T)0;
+  __syncthreads();
   T ring[PPT][NQ];
   T vring[PPT][NV];
-  int px[PPT], py[PPT], vrow[PPT];
+  int li[PPT], vrow[PPT];
   bool own[PPT];
   int gz0 = st.oz < 0 ? st.oz + gnz : st.oz;     // global z of local plane 0
 #pragma unroll
@@ -541,19 +642,19 @@ __device__ __noinline__ double stencil_march(int gnx, int gny, int gnz,
     const int p2 = tid + k * BLOCK;
     own[k] = p2 < sxy;
     const int pc = own[k] ? p2 : 0;
-    py[k] = pc / sx;
-    px[k] = pc - py[k] * sx;
-    int gx = st.ox + px[k], gy = st.oy + py[k];
+    const int y = pc / sx, x = pc - y * sx;
+    li[k] = (y + 3) * rx + (x + 3);
+    int gx = st.ox + x, gy = st.oy + y;
     gx = gx < 0 ? gx + gnx : (gx >= gnx ? gx - gnx : gx);
     gy = gy < 0 ? gy + gny : (gy >= gny ? gy - gny : gy);
     vrow[k] = gx + gnx * gy;
 #pragma unroll
     for (int d = 0; d < NQ; ++d) {
-      // slot d holds plane d (d <= 6) or plane d - NQ (below the cube: masked at use);
-      // planes outside the cube are read clamped and masked where they are used
-      const int z = d <= 6 ? d : d - NQ;
+      // slot d holds plane d (d <= NQ-4) or plane d - NQ (below the cube: masked at
+      // use); planes outside the cube are read clamped and masked where they are used
+      const int z = d <= NQ - 4 ? d : d - NQ;
       const int zc = z < 0 ? 0 : (z < sz ? z : sz - 1);
-      ring[k][d] = Wj[pc + zc * sxy];
+      ring[k][d] = Wj[bidx(pc + zc * sxy, vbs)];
     }
 #pragma unroll
     for (int d = 0; d < NV; ++d) {
@@ -571,7 +672,7 @@ __device__ __noinline__ double stencil_march(int gnx, int gny, int gnz,
         SGQ_L T* plane = st.plane[z & 1];
 #pragma unroll
         for (int k = 0; k < PPT; ++k)
-          if (own[k]) plane[tid + k * BLOCK] = ring[k][r];
+          if (own[k]) plane[li[k]] = ring[k][r];
         __syncthreads();
         // uniform masks of the z neighbours (zero outside the cube)
         const T mz1 = (T)(z >= 1), pz1 = (T)(z + 1 < sz);
@@ -579,36 +680,31 @@ __device__ __noinline__ double stencil_march(int gnx, int gny, int gnz,
         const T mz3 = (T)(z >= 3), pz3 = (T)(z + 3 < sz);
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
-          const int p2 = own[k] ? tid + k * BLOCK : 0;
-          const int x = px[k], y = py[k];
-          // LDS reads at clamped indices, masked by a 0/1 factor afterwards
-          auto at = [&](bool ok, int idx) -> T { return plane[ok ? idx : p2] * (T)ok; };
+          const SGQ_L T* c0 = plane + li[k];
           const T c = ring[k][r];
-          T l1 = mz1 * ring[k][(r + NQ - 1) % NQ] + pz1 * ring[k][(r + 1) % NQ] +
-                 at(x >= 1, p2 - 1) + at(x + 1 < sx, p2 + 1) + at(y >= 1, p2 - sx) +
-                 at(y + 1 < sy, p2 + sx);
-          T l2 = mz2 * ring[k][(r + NQ - 2) % NQ] + pz2 * ring[k][(r + 2) % NQ] +
-                 at(x >= 2, p2 - 2) + at(x + 2 < sx, p2 + 2) + at(y >= 2, p2 - 2 * sx) +
-                 at(y + 2 < sy, p2 + 2 * sx);
-          T l3 = mz3 * ring[k][(r + NQ - 3) % NQ] + pz3 * ring[k][(r + 3) % NQ] +
-                 at(x >= 3, p2 - 3) + at(x + 3 < sx, p2 + 3) + at(y >= 3, p2 - 3 * sx) +
-                 at(y + 3 < sy, p2 + 3 * sx);
+          const T l1 = mz1 * ring[k][(r + NQ - 1) % NQ] + pz1 * ring[k][(r + 1) % NQ] +
+                       (c0[-1] + c0[1]) + (c0[-rx] + c0[rx]);
+          const T l2 = mz2 * ring[k][(r + NQ - 2) % NQ] + pz2 * ring[k][(r + 2) % NQ] +
+                       (c0[-2] + c0[2]) + (c0[-2 * rx] + c0[2 * rx]);
+          const T l3 = mz3 * ring[k][(r + NQ - 3) % NQ] + pz3 * ring[k][(r + 3) % NQ] +
+                       (c0[-3] + c0[3]) + (c0[-3 * rx] + c0[3 * rx]);
           const T lap = w0 * c + w1 * l1 + w2 * l2 + w3 * l3;
           const T u = sj * (kin * lap + vring[k][r % NV] * c);
           if (own[k]) {
+            const int p2 = tid + k * BLOCK;
             if (ACC) U[p2 + z * sxy] += u; else U[p2 + z * sxy] = u;
             apart += (double)(sj * c) * (double)u;
           }
         }
-        // refill: plane z+7 replaces plane z-3, potential of plane z+5 replaces plane z
-        const int zw = z + 7, zv = z + NV < sz ? z + NV : sz - 1;
+        // refill: plane z+NQ-3 replaces plane z-3, the potential of plane z+NV replaces z
+        const int zw = z + NQ - 3, zv = z + NV < sz ? z + NV : sz - 1;
         int gz = gz0 + zv;
         gz = gz >= gnz ? gz - gnz : gz;
         gz = gz >= gnz ? gz - gnz : gz;
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
           const int pc = own[k] ? tid + k * BLOCK : 0;
-          ring[k][(r + NQ - 3) % NQ] = Wj[pc + (zw < sz ? zw : sz - 1) * sxy];
+          ring[k][(r + NQ - 3) % NQ] = Wj[bidx(pc + (zw < sz ? zw : sz - 1) * sxy, vbs)];
           vring[k][r % NV] = V[vrow[k] + vplane * gz];
         }
       }
@@ -621,7 +717,7 @@ __device__ __noinline__ double stencil_march(int gnx, int gny, int gnz,
 template <typename T, int BLOCK, bool ACC = false>
 __device__ __noinline__ double stencil_periodic(const SGQ_L NodeState<T, BLOCK>& st,
                                                 const SGQ_G T* __restrict__ V,
-                                                const SGQ_G T* __restrict__ Wj,
+                                                const SGQ_G T* __restrict__ Wj, int vbs,
                                                 SGQ_G T* __restrict__ U, T sj, T kin) {
   const int n = st.n, sx = st.sx, sy = st.sy, sz = st.sz, sxy = sx * sy;
   const float inv_sx = 1.0f / (float)sx, inv_sxy = 1.0f / (float)sxy;
@@ -631,15 +727,15 @@ __device__ __noinline__ double stencil_periodic(const SGQ_L NodeState<T, BLOCK>&
   for (int p = threadIdx.x; p < n; p += BLOCK) {
     int x, y, z;
     unflatten(p, sx, sxy, inv_sx, inv_sxy, x, y, z);
-    T wc = Wj[p];
+    T wc = Wj[bidx(p, vbs)];
     T lap = w0 * wc;
     for (int d = 1; d <= 3; ++d) {
-      lap += wd[d] * (Wj[wrap_index(x - d, sx) + sx * (y + sy * z)] +
-                      Wj[wrap_index(x + d, sx) + sx * (y + sy * z)]);
-      lap += wd[d] * (Wj[x + sx * (wrap_index(y - d, sy) + sy * z)] +
-                      Wj[x + sx * (wrap_index(y + d, sy) + sy * z)]);
-      lap += wd[d] * (Wj[x + sx * (y + sy * wrap_index(z - d, sz))] +
-                      Wj[x + sx * (y + sy * wrap_index(z + d, sz))]);
+      lap += wd[d] * (Wj[bidx(wrap_index(x - d, sx) + sx * (y + sy * z), vbs)] +
+                      Wj[bidx(wrap_index(x + d, sx) + sx * (y + sy * z), vbs)]);
+      lap += wd[d] * (Wj[bidx(x + sx * (wrap_index(y - d, sy) + sy * z), vbs)] +
+                      Wj[bidx(x + sx * (wrap_index(y + d, sy) + sy * z), vbs)]);
+      lap += wd[d] * (Wj[bidx(x + sx * (y + sy * wrap_index(z - d, sz)), vbs)] +
+                      Wj[bidx(x + sx * (y + sy * wrap_index(z + d, sz)), vbs)]);
     }
     T u = sj * (kin * lap + V[p] * wc);
     if (ACC) U[p] += u; else U[p] = u;
@@ -649,40 +745,41 @@ __device__ __noinline__ double stencil_periodic(const SGQ_L NodeState<T, BLOCK>&
 }
 
 
-// u = H v for one vector of the node cube (stencil, local potential, and the projector
-// scatter with weights st.acoef that the caller has set): dispatches the stencil form.
-// ACC adds into U instead of storing.  Returns this thread's part of (s v) . u_local.
+// u = (-1/2 Lap_6 + V) s v for one vector of the node cube (v a row view with block
+// stride vbs, u a plain vector): dispatches the stencil form.  ACC adds into U instead of
+// storing.  Returns this thread's part of (s v) . u.
 template <typename T, int BLOCK, bool ACC>
 __device__ __forceinline__ double apply_local(const LaunchParams& P, SGQ_L NodeState<T, BLOCK>& st,
-                                              const SGQ_G T* V, const SGQ_G T* v, SGQ_G T* U,
-                                              T s, T kin) {
-  if (st.periodic) return stencil_periodic<T, BLOCK, ACC>(st, V, v, U, s, kin);
-  if (st.sx * st.sy <= 5 * BLOCK && st.sx * st.sy <= kMarchPlane)
-    return stencil_march<T, BLOCK, 5, ACC>(P.nx, P.ny, P.nz, st, V, v, U, s, kin);
-  return stencil_cube<T, BLOCK, ACC>(P.nx, P.ny, P.nz, st, V, v, U, s, kin);
+                                              const SGQ_G T* V, const SGQ_G T* v, int vbs,
+                                              SGQ_G T* U, T s, T kin) {
+  if (st.periodic) return stencil_periodic<T, BLOCK, ACC>(st, V, v, vbs, U, s, kin);
+  if (st.sx * st.sy <= 5 * BLOCK && (st.sx + 6) * (st.sy + 6) <= kMarchPad)
+    return stencil_march<T, BLOCK, 5, ACC>(P.nx, P.ny, P.nz, st, V, v, vbs, U, s, kin);
+  return stencil_cube<T, BLOCK, ACC>(P.nx, P.ny, P.nz, st, V, v, vbs, U, s, kin);
 }
 
 template <typename T, int BLOCK>
 __device__ __forceinline__ void apply_scatter(const LaunchParams& P, SGQ_L NodeState<T, BLOCK>& st,
-                                              const SGQ_G T* chi, SGQ_G T* U, int B, int B3) {
+                                              ProjEval<T> pe, SGQ_G T* U, int B, int B3) {
   const int tid = threadIdx.x;
   if (st.natoms == 0) return;
-  scatter_group<T, BLOCK>(st, chi, U, B, B3);
+  scatter_group<T, BLOCK>(st, pe, U, B, B3);
   __syncthreads();
   const bool alias = st.periodic && (P.nx < B || P.ny < B || P.nz < B);
   for (int a = 0; a < st.natoms; ++a) {
     if (!st.aphase[a]) continue;
     if (alias) {
-      if (tid == 0) scatter_atom<T, BLOCK>(st, chi, U, a, B, B3, 0, 1);
+      if (tid == 0) scatter_atom<T, BLOCK>(st, pe, U, a, B, B3, 0, 1);
     } else {
-      scatter_atom<T, BLOCK>(st, chi, U, a, B, B3, tid, BLOCK);
+      scatter_atom<T, BLOCK>(st, pe, U, a, B, B3, tid, BLOCK);
     }
     __syncthreads();
   }
 }
 
-// One K-step Lanczos run of the current node (after node_setup): W rows 0..K_eff-1 hold
-// the unnormalised basis (q_i = st.scale[i] W_i), st.alpha / st.beta the tridiagonal.
+// One K-step Lanczos run of the current node (after node_setup): rows 0..K_eff-1 of the
+// point-blocked basis W (block stride P.wbs) hold the unnormalised vectors
+// (q_i = st.scale[i] W_i), st.alpha / st.beta the tridiagonal.
 // u_j = H q_j is written to U + j*ustride (ustride 0: one reused row).  Returns K_eff.
 template <typename T, int BLOCK, int KG>
 __device__ int run_lanczos(const LaunchParams& P, SGQ_L NodeState<T, BLOCK>& st,
@@ -692,7 +789,7 @@ __device__ int run_lanczos(const LaunchParams& P, SGQ_L NodeState<T, BLOCK>& st,
   constexpr int VEC = sizeof(T) == 4 ? 4 : 2;   // widest point group of the sweeps
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
   const SGQ_G T* __restrict__ V = (const SGQ_G T*)P.v;
-  const SGQ_G T* __restrict__ chi = (const SGQ_G T*)P.chi;
+  const ProjEval<T> pe = proj_eval<T>(P);
   const SGQ_G double* proj_E = (const SGQ_G double*)P.proj_E;
   const size_t npad = P.npad;
   const double h = P.h;
@@ -703,28 +800,30 @@ __device__ int run_lanczos(const LaunchParams& P, SGQ_L NodeState<T, BLOCK>& st,
   const int B = 2 * P.box_m + 1, B3 = B * B * B;
   const int n = st.n;
   const int natoms = st.natoms;
+  const int bs = P.wbs;
+  const int wbytes = (int)((npad / 64) * (size_t)bs * sizeof(T));
   const int nzero = ((n + VEC - 1) / VEC) * VEC;
-  for (int p = tid; p < nzero; p += BLOCK) W[p] = (T)0;
+  for (int p = tid; p < nzero; p += BLOCK) W[bidx(p, bs)] = (T)0;
   __syncthreads();
   if (tid == 0) {
-    W[st.start] = (T)1;
+    W[bidx(st.start, bs)] = (T)1;
     st.scale[0] = 1.0;
   }
   __syncthreads();
 
   int keff = K;
   for (int j = 0; j < K; ++j) {
-    const SGQ_G T* __restrict__ Wj = W + (size_t)j * npad;
+    const SGQ_G T* __restrict__ Wj = W + 64 * j;     // row j (block stride bs)
     SGQ_G T* __restrict__ U = Ubase + (size_t)j * ustride;
     const double sjd = st.scale[j];
     const T sj = (T)sjd;
     // ---- H q_j: projector overlaps, stencil + local potential, projector scatter
-    projector_dots<T, BLOCK>(proj_E, st, chi, Wj, sjd, h3, B, B3);
-    double apart = apply_local<T, BLOCK, false>(P, st, V, Wj, U, sj, kin);
+    projector_dots<T, BLOCK>(proj_E, st, pe, Wj, bs, sjd, h3, B, B3);
+    double apart = apply_local<T, BLOCK, false>(P, st, V, Wj, bs, U, sj, kin);
     apart = wave_sum(apart);
     if (lane == 0) st.red[wave][0] = apart;
     __syncthreads();
-    apply_scatter<T, BLOCK>(P, st, chi, U, B, B3);
+    apply_scatter<T, BLOCK>(P, st, pe, U, B, B3);
     if (tid < kWave) {
       double al = 0.0;
       for (int a = tid; a < natoms; a += kWave) al += st.anl[a];
@@ -750,8 +849,8 @@ __device__ int run_lanczos(const LaunchParams& P, SGQ_L NodeState<T, BLOCK>& st,
     }
     __syncthreads();
     // ---- fused sweep: w = u - sum c_i q_i, D_i = W_i . w, |w|^2
-    SGQ_G T* __restrict__ Wn = W + (size_t)(j + 1) * npad;
-    fused_sweep<T, BLOCK, KG>(st, W, U, Wn, j, n, npad);
+    SGQ_G T* __restrict__ Wn = W + 64 * (j + 1);
+    fused_sweep<T, BLOCK, KG>(st, W, bs, wbytes, U, 64, Wn, j, n);
     __syncthreads();
     finish_sweep<T, BLOCK>(st, j);
     // Semi-orthogonality guard: the coefficients above are exact up to O(G^2); when
@@ -761,7 +860,7 @@ __device__ int run_lanczos(const LaunchParams& P, SGQ_L NodeState<T, BLOCK>& st,
       for (int i = tid; i <= j; i += BLOCK)
         st.ct[i] = (T)(st.scale[i] * st.scale[i] * st.dsave[i]);
       __syncthreads();
-      fused_sweep<T, BLOCK, KG>(st, W, Wn, Wn, j, n, npad);
+      fused_sweep<T, BLOCK, KG>(st, W, bs, wbytes, Wn, bs, Wn, j, n);
       __syncthreads();
       finish_sweep<T, BLOCK>(st, j);
     }

@@ -8,7 +8,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/sgq.h"
+#include "sgq.h"
 #include "sgq_common.h"
 #include "tridiag.h"
 
@@ -87,7 +87,7 @@ struct sgq_plan {
 };
 
 static void free_all(sgq_plan* p) {
-  for (void* a : p->allocs) hipFree(a);
+  for (void* a : p->allocs) (void)hipFree(a);
   p->allocs.clear();
 }
 
@@ -217,6 +217,11 @@ extern "C" int sgq_plan_create(const sgq_problem* prob, const int64_t* center,
   p->npad = (nmax + 63) / 64 * 64;
   p->slot_stride = (size_t)p->kmax * p->npad;
   const size_t es = p->fp64 ? 8 : 4;
+  // the sweep addresses a node's basis with 32-bit byte offsets
+  if (p->slot_stride * es >= ((size_t)1 << 31)) {
+    delete p;
+    return fail(SGQ_EINVAL, "a node's Lanczos basis (depth x cube points) exceeds 2 GiB");
+  }
   hipError_t e = hipSuccess;
   e = e ? e : dalloc(p, &p->d_order, nq * 4);
   e = e ? e : dalloc(p, &p->d_center, nq * 4);
@@ -256,9 +261,9 @@ extern "C" int sgq_plan_create(const sgq_problem* prob, const int64_t* center,
 
 extern "C" int sgq_plan_destroy(sgq_plan* plan) {
   if (!plan) return SGQ_OK;
-  hipSetDevice(plan->device);
-  if (plan->last) hipStreamSynchronize(plan->last);
-  hipDeviceSynchronize();
+  (void)hipSetDevice(plan->device);
+  if (plan->last) (void)hipStreamSynchronize(plan->last);
+  (void)hipDeviceSynchronize();
   free_all(plan);
   delete plan;
   return SGQ_OK;
@@ -307,6 +312,7 @@ static LaunchParams base_params(sgq_plan* p, const double* v_loc, const double* 
   P.U = p->d_U;
   P.npad = p->npad;
   P.slot_stride = p->slot_stride;
+  P.wbs = p->kmax * 64;
   P.queue = p->d_queue;
   P.status = p->d_status;
   P.kmax_out = p->kmax;

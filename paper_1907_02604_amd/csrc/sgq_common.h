@@ -51,10 +51,11 @@ struct LaunchParams {
   int integrand;
   double tau;                 // breakdown threshold relative to the spectral scale
   // workspace
-  void* W;                    // [slots][kmax][npad]
+  void* W;                    // [slots]: basis [npad/64][kmax][64] (point-blocked)
   void* U;                    // [slots][npad]
   size_t npad;
   size_t slot_stride;         // elements of W per slot
+  int wbs;                    // element stride between 64-point blocks of the basis (kmax*64)
   int* queue;                 // node counter of the persistent launch
   int* status;                // latched error bits
   // outputs (by node id)
@@ -73,6 +74,10 @@ struct LaunchParams {
   double* dE_part;            // [Nq][kMaxNodeAtoms][4] node partials of dE
   int32_t* node_atoms;        // [Nq][1 + kMaxNodeAtoms]: count, then the node's atom ids
 };
+
+// Element index of point p in a vector stored in 64-point blocks with block stride bs
+// (bs = 64: a plain vector; bs = kmax*64: one row of the point-blocked Lanczos basis).
+__device__ __forceinline__ int bidx(int p, int bs) { return (p >> 6) * bs + (p & 63); }
 
 __device__ __forceinline__ int wrap_index(int i, int n) {
   int r = i % n;
