@@ -114,6 +114,8 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--plain-nodes", type=int, default=32)
     ap.add_argument("--adjoint-nodes", type=int, default=2048)
+    ap.add_argument("--tune-nodes", type=int, default=2048,
+                    help="nodes of the sample the launch-shape autotuner times")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a 1 GiB device-to-device copy first (reference for byte counters)")
     ap.add_argument("--config", type=int, default=2, help=argparse.SUPPRESS)
@@ -144,7 +146,14 @@ def main():
     plan = sgq.Plan.from_problem(P)
     v, R, E, _ = sgq.device_inputs(P)
     rho = torch.empty(P.n_nodes, dtype=torch.float64, device="cuda")
-    stream = torch.cuda.current_stream()
+    # a stream of its own (default priority): the launch sequence is captured into a HIP
+    # graph on the first call and replayed afterwards
+    stream = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    lanes, wg_per_cu = plan.autotune(v, R, E, P.mu, P.kT, sample_nodes=args.tune_nodes,
+                                     stream=stream.cuda_stream)
+    print(f"[bench] autotuned launch: {lanes} lanes per node, {wg_per_cu} workgroups per CU",
+          file=sys.stderr, flush=True)
 
     def step():
         sgq.rho_quadrature(plan, v, R, E, P.mu, P.kT, rho, stream=stream.cuda_stream)
@@ -162,6 +171,7 @@ def main():
         starts[i].record(stream)
         step()
         ends[i].record(stream)
+    stream.synchronize()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     launch_ms = [s.elapsed_time(e) for s, e in zip(starts, ends)]
@@ -181,10 +191,12 @@ def main():
         "data": "synthetic (seeded jittered-hcp Gaussian potential, U[-1,1] projector energies)",
         "config": {"workload": "64^3 grid h=0.5, 255 atoms with 4 KB projectors, 8192 nodes, "
                                "33^3 cubes, K=60, kT=0.01, mu=-0.1, FP32 matvec / FP64 dots",
-                   "grid": list(P.n), "nodes": P.n_nodes, "cube_points": n_cube, "depth": K},
+                   "grid": list(P.n), "nodes": P.n_nodes, "cube_points": n_cube, "depth": K,
+                   "launch": {"lanes_per_node": lanes, "workgroups_per_cu": wg_per_cu,
+                              "autotuned": True, "hip_graph": True}},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
-                     "kernel": "lanczos_forward_kernel<float,256,16>",
+                     "kernel": f"lanczos_forward_kernel<float,{lanes},16>",
                      "alg_bytes_per_launch": bytes_launch, "avg_launch_ms": t_launch * 1e3},
     }
     if not args.no_plain:

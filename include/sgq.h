@@ -141,6 +141,28 @@ int sgq_vloc_gaussian_backward(sgq_plan* plan, const double* dV, const double* a
  *                        NULL.  Returns SGQ_EINVAL for an unknown schedule. */
 int sgq_plan_set_schedule(sgq_plan* plan, int schedule);
 
+/* Launch capture.  With enable != 0 (the default), rho_quadrature and band_energy on a
+ * stream other than the legacy default stream capture their launch sequence (setup
+ * kernels, the persistent Lanczos-Gauss kernel, the weighted sum) into a HIP graph on the
+ * first call and replay it while the pointers, mu, kT, integrand and launch shape are
+ * unchanged; any change re-captures.  The sequence contains kernels only.  Calls on the
+ * default stream, or on a stream the caller is already capturing, launch directly.
+ * enable = 0 always launches directly.  Returns SGQ_EINVAL for a null plan. */
+int sgq_plan_set_graph(sgq_plan* plan, int enable);
+
+/* Launch-shape autotuner.  Times the candidate shapes of the persistent forward kernel
+ * (lanes per node: 128, 256 or 512; resident workgroups per CU: 1 to 3; FP64 plans use 256
+ * lanes) on `sample_nodes` nodes drawn evenly from the plan's cost-sorted node list, with
+ * the given inputs (same meaning as rho_quadrature), and keeps the fastest for the plan.
+ * The choice is cached per problem shape (device, precision, cube size, depth, projector
+ * box) for the process and, when the environment variable SGQ_TUNE_CACHE names a file,
+ * appended to that file and read from it by later processes.  May grow the plan's
+ * workspace (SGQ_ENOMEM if that fails).  Synchronous on `stream`.
+ *   chosen [2] int32  out (optional, host): lanes per node, workgroups per CU       */
+int sgq_plan_autotune(sgq_plan* plan, const double* v_loc, const double* atom_R,
+                      const double* proj_E, double mu, double kT, int sample_nodes,
+                      void* stream, int32_t* chosen);
+
 /* Wait for the plan's last call and report a latched device-side error (SGQ_OK,
  * SGQ_ENONFINITE or SGQ_ELIMIT); the latch is cleared by the next compute call. */
 int sgq_plan_status(sgq_plan* plan, int32_t* host_status);

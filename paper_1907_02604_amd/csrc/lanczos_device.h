@@ -334,7 +334,9 @@ __device__ __noinline__ void fused_sweep_v(SGQ_L NodeState<T, BLOCK>& st,
   if (lane == 0) st.red[wave][kMaxDepth + 1] = n2;
 }
 
-// Picks the sweep variant for step j (slots KS >= (j+1)/4, at most KG).
+// Picks the sweep variant for step j (slots KS >= (j+1)/4, at most KG).  The FP32
+// variants read 16 bytes per lane and row (a wave reads four whole 256-byte block rows
+// per instruction), which measured fastest at every depth.
 template <typename T, int BLOCK, int KG>
 __device__ __forceinline__ void fused_sweep(SGQ_L NodeState<T, BLOCK>& st,
                                             const SGQ_G T* __restrict__ W, int bs, int wbytes,
@@ -345,8 +347,9 @@ __device__ __forceinline__ void fused_sweep(SGQ_L NodeState<T, BLOCK>& st,
     if (need <= 2) return fused_sweep_v<T, BLOCK, 2, 4, 4>(st, W, bs, wbytes, src, sbs, dst, j, n);
     if (need <= 4) return fused_sweep_v<T, BLOCK, 4, 2, 4>(st, W, bs, wbytes, src, sbs, dst, j, n);
     if (need <= 8) return fused_sweep_v<T, BLOCK, 8, 1, 4>(st, W, bs, wbytes, src, sbs, dst, j, n);
-    if (KG <= 16 || need <= 16) return fused_sweep_v<T, BLOCK, 16, 1, 2>(st, W, bs, wbytes, src, sbs, dst, j, n);
-    return fused_sweep_v<T, BLOCK, 32, 1, 1>(st, W, bs, wbytes, src, sbs, dst, j, n);
+    if (need <= 12) return fused_sweep_v<T, BLOCK, 12, 1, 4>(st, W, bs, wbytes, src, sbs, dst, j, n);
+    if (KG <= 16 || need <= 16) return fused_sweep_v<T, BLOCK, 16, 1, 4>(st, W, bs, wbytes, src, sbs, dst, j, n);
+    return fused_sweep_v<T, BLOCK, 32, 1, 2>(st, W, bs, wbytes, src, sbs, dst, j, n);
   } else {
     if (need <= 2) return fused_sweep_v<T, BLOCK, 2, 4, 2>(st, W, bs, wbytes, src, sbs, dst, j, n);
     if (need <= 4) return fused_sweep_v<T, BLOCK, 4, 2, 2>(st, W, bs, wbytes, src, sbs, dst, j, n);

@@ -4,6 +4,8 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -50,10 +52,18 @@ static int fail(int code, const std::string& msg) {
     if (e_ != hipSuccess) return fail(SGQ_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
+// One captured launch sequence of a compute call and the arguments it was captured with.
+struct GraphCache {
+  hipGraphExec_t exec = nullptr;
+  hipStream_t stream = nullptr;
+  std::vector<uint64_t> key;
+};
+
 struct sgq_plan {
   sgq_problem prob{};
   int device = 0;
   int kmax = 0, box_m = 0, kg = 8, block = 256, grid = 0;
+  int slots = 0;            // Lanczos workspace slots allocated (>= grid)
   double norm_s = 0, norm_p = 0;
   size_t npad = 0, slot_stride = 0, n_grid = 0;
   bool fp64 = false;
@@ -84,9 +94,17 @@ struct sgq_plan {
   void* d_plain = nullptr;
   hipStream_t last = nullptr;
   std::vector<void*> allocs;
+  bool use_graph = true;
+  GraphCache graphs[2];     // rho_quadrature, band_energy
+  bool tuned = false;
 };
 
 static void free_all(sgq_plan* p) {
+  for (GraphCache& g : p->graphs) {
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    g.exec = nullptr;
+    g.key.clear();
+  }
   for (void* a : p->allocs) (void)hipFree(a);
   p->allocs.clear();
 }
@@ -214,6 +232,7 @@ extern "C" int sgq_plan_create(const sgq_problem* prob, const int64_t* center,
     p->block = (b == 128 || b == 512) && !p->fp64 ? b : 256;
   }
   p->grid = std::max(1, std::min(nq, ncu * wg_per_cu));
+  p->slots = p->grid;
   p->npad = (nmax + 63) / 64 * 64;
   p->slot_stride = (size_t)p->kmax * p->npad;
   const size_t es = p->fp64 ? 8 : 4;
@@ -227,8 +246,8 @@ extern "C" int sgq_plan_create(const sgq_problem* prob, const int64_t* center,
   e = e ? e : dalloc(p, &p->d_center, nq * 4);
   e = e ? e : dalloc(p, &p->d_hw, nq * 4);
   e = e ? e : dalloc(p, &p->d_depth, nq * 4);
-  e = e ? e : dalloc(p, &p->d_W, (size_t)p->grid * p->slot_stride * es);
-  e = e ? e : dalloc(p, &p->d_U, (size_t)p->grid * p->npad * es);
+  e = e ? e : dalloc(p, &p->d_W, (size_t)p->slots * p->slot_stride * es);
+  e = e ? e : dalloc(p, &p->d_U, (size_t)p->slots * p->npad * es);
   if (!p->fp64) e = e ? e : dalloc(p, &p->d_v, p->n_grid * es);
   int B = 2 * p->box_m + 1;
   if (prob->n_proj) {
@@ -319,11 +338,61 @@ static LaunchParams base_params(sgq_plan* p, const double* v_loc, const double* 
   return P;
 }
 
-static int run_forward(sgq_plan* p, LaunchParams& P, const double* v_loc, hipStream_t s) {
+// The launches of one forward call: potential copy and projector offsets, the persistent
+// Lanczos-Gauss kernel and, for the energy, the node-weighted sum.
+static hipError_t forward_sequence(sgq_plan* p, const LaunchParams& P, const double* v_loc,
+                                   const double* node_weight, double* omega, hipStream_t s) {
+  hipError_t e = launch_setup(P, p->fp64, v_loc, p->d_v, p->d_chi, p->d_g0, p->d_vmax, s);
+  if (e == hipSuccess && p->prob.n_nodes > 0)
+    e = launch_forward(P, p->fp64, p->grid, p->block, p->kg, s);
+  if (e == hipSuccess && omega)
+    e = launch_weighted_sum(P.e_node, node_weight, p->prob.n_nodes, omega, s);
+  return e;
+}
+
+// Runs the forward sequence on stream s.  On a stream that is not the legacy default
+// stream and not already being captured, the sequence is captured once into a HIP graph
+// and replayed while the call arguments (pointers, scalars, launch shape) are unchanged;
+// a changed argument re-captures it.  The sequence holds kernels only (no memset nodes).
+static int run_forward(sgq_plan* p, int kind, LaunchParams& P, const double* v_loc,
+                       const double* node_weight, double* omega, hipStream_t s) {
   HIP_OR_FAIL(hipSetDevice(p->device));
-  HIP_OR_FAIL(launch_setup(P, p->fp64, v_loc, p->d_v, p->d_chi, p->d_g0, p->d_vmax, s));
-  if (p->prob.n_nodes > 0) HIP_OR_FAIL(launch_forward(P, p->fp64, p->grid, p->block, p->kg, s));
   p->last = s;
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (s) HIP_OR_FAIL(hipStreamIsCapturing(s, &cap));
+  if (!p->use_graph || !s || cap != hipStreamCaptureStatusNone) {
+    HIP_OR_FAIL(forward_sequence(p, P, v_loc, node_weight, omega, s));
+    return SGQ_OK;
+  }
+  auto bits = [](double d) { uint64_t u; std::memcpy(&u, &d, 8); return u; };
+  std::vector<uint64_t> key = {
+      (uint64_t)(uintptr_t)s, (uint64_t)(uintptr_t)v_loc, (uint64_t)(uintptr_t)P.atom_R,
+      (uint64_t)(uintptr_t)P.proj_E, (uint64_t)(uintptr_t)P.rho, (uint64_t)(uintptr_t)P.theta_w,
+      (uint64_t)(uintptr_t)P.k_eff, (uint64_t)(uintptr_t)P.e_node,
+      (uint64_t)(uintptr_t)node_weight, (uint64_t)(uintptr_t)omega, bits(P.mu), bits(P.kT),
+      (uint64_t)P.integrand, (uint64_t)p->block, (uint64_t)p->grid};
+  GraphCache& g = p->graphs[kind];
+  if (!g.exec || g.key != key) {
+    if (g.exec) {
+      HIP_OR_FAIL(hipGraphExecDestroy(g.exec));
+      g.exec = nullptr;
+      g.key.clear();
+    }
+    HIP_OR_FAIL(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    hipError_t e = forward_sequence(p, P, v_loc, node_weight, omega, s);
+    hipGraph_t graph = nullptr;
+    hipError_t e2 = hipStreamEndCapture(s, &graph);
+    if (e == hipSuccess) e = e2;
+    if (e == hipSuccess) e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+      g.exec = nullptr;
+      return fail(SGQ_EHIP, std::string("graph capture of the forward launches: ") +
+                                hipGetErrorString(e));
+    }
+    g.key = key;
+  }
+  HIP_OR_FAIL(hipGraphLaunch(g.exec, s));
   return SGQ_OK;
 }
 
@@ -356,7 +425,7 @@ extern "C" int rho_quadrature(sgq_plan* plan, const double* v_loc, const double*
     plan->last = s;
     return SGQ_OK;
   }
-  return run_forward(plan, P, v_loc, (hipStream_t)stream);
+  return run_forward(plan, 0, P, v_loc, nullptr, nullptr, (hipStream_t)stream);
 }
 
 extern "C" int sgq_plan_set_schedule(sgq_plan* plan, int schedule) {
@@ -364,6 +433,167 @@ extern "C" int sgq_plan_set_schedule(sgq_plan* plan, int schedule) {
   if (schedule != SGQ_SCHEDULE_BATCHED && schedule != SGQ_SCHEDULE_PLAIN)
     return fail(SGQ_EINVAL, "unknown schedule");
   plan->schedule = schedule;
+  return SGQ_OK;
+}
+
+extern "C" int sgq_plan_set_graph(sgq_plan* plan, int enable) {
+  if (!plan) return fail(SGQ_EINVAL, "plan is null");
+  plan->use_graph = enable != 0;
+  return SGQ_OK;
+}
+
+// ------------------------------------------------------------------ launch-shape autotuner
+// Candidate launch shapes of the persistent forward kernel: workgroup size (lanes per
+// node) and resident workgroups per CU.  Each is timed on a stratified sample of the
+// plan's own nodes; the fastest is kept for the plan and cached per problem shape (in
+// the process, and in the file named by SGQ_TUNE_CACHE when it is set).
+namespace {
+std::mutex g_tune_mu;
+std::map<std::string, std::pair<int, int>> g_tune;
+bool g_tune_file_read = false;
+
+std::string tune_key(const sgq_plan* p) {
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, p->device) != hipSuccess) std::strcpy(prop.gcnArchName, "?");
+  char buf[320];
+  std::snprintf(buf, sizeof buf, "%s/cu%d/%s/npad%zu/kmax%d/proj%d/m%d", prop.gcnArchName, p->ncu,
+                p->fp64 ? "f64" : "f32", p->npad, p->kmax, p->prob.n_proj, p->box_m);
+  return buf;
+}
+
+void tune_file_read() {
+  if (g_tune_file_read) return;
+  g_tune_file_read = true;
+  const char* path = std::getenv("SGQ_TUNE_CACHE");
+  if (!path) return;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return;
+  char key[320];
+  int b, w;
+  while (std::fscanf(f, "%319s %d %d", key, &b, &w) == 3) g_tune[key] = {b, w};
+  std::fclose(f);
+}
+
+void tune_file_append(const std::string& key, int b, int w) {
+  const char* path = std::getenv("SGQ_TUNE_CACHE");
+  if (!path) return;
+  FILE* f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f, "%s %d %d\n", key.c_str(), b, w);
+  std::fclose(f);
+}
+}  // namespace
+
+static int ensure_slots(sgq_plan* p, int slots) {
+  if (slots <= p->slots) return SGQ_OK;
+  const size_t es = p->fp64 ? 8 : 4;
+  void *W = nullptr, *U = nullptr;
+  hipError_t e = hipMalloc(&W, (size_t)slots * p->slot_stride * es);
+  if (e == hipSuccess) e = hipMalloc(&U, (size_t)slots * p->npad * es);
+  if (e != hipSuccess) {
+    if (W) (void)hipFree(W);
+    (void)hipGetLastError();
+    return fail(SGQ_ENOMEM, "autotune: workspace for more resident workgroups");
+  }
+  HIP_OR_FAIL(hipDeviceSynchronize());
+  for (GraphCache& g : p->graphs) {   // captured launches name the old workspace
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    g.exec = nullptr;
+    g.key.clear();
+  }
+  for (void*& a : p->allocs) {
+    if (a == p->d_W) { (void)hipFree(a); a = W; }
+    else if (a == p->d_U) { (void)hipFree(a); a = U; }
+  }
+  p->d_W = W;
+  p->d_U = U;
+  p->slots = slots;
+  return SGQ_OK;
+}
+
+extern "C" int sgq_plan_autotune(sgq_plan* plan, const double* v_loc, const double* atom_R,
+                                 const double* proj_E, double mu, double kT, int sample_nodes,
+                                 void* stream, int32_t* chosen) {
+  int st = check_call(plan, v_loc, atom_R, proj_E, mu, kT);
+  if (st != SGQ_OK) return st;
+  if (sample_nodes < 1) return fail(SGQ_EINVAL, "sample_nodes must be >= 1");
+  HIP_OR_FAIL(hipSetDevice(plan->device));
+  hipStream_t s = (hipStream_t)stream;
+  const int nq = plan->prob.n_nodes;
+  std::vector<std::pair<int, int>> cand;
+  if (plan->fp64) cand = {{256, 2}, {256, 1}};
+  else cand = {{256, 2}, {256, 1}, {128, 3}, {128, 2}, {512, 1}};
+  const std::string key = tune_key(plan);
+  std::pair<int, int> best{plan->block, plan->grid / std::max(1, plan->ncu)};
+  bool cached = false;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_file_read();
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) {
+      best = it->second;
+      cached = true;
+    }
+  }
+  if (!cached && nq > 0) {
+    int maxwpc = 0;
+    for (auto& c : cand) maxwpc = std::max(maxwpc, c.second);
+    st = ensure_slots(plan, std::min(nq, plan->ncu * maxwpc));
+    if (st != SGQ_OK) return st;
+    const int S = std::min(sample_nodes, nq);
+    std::vector<int32_t> ids(S);
+    for (int i = 0; i < S; ++i) ids[i] = plan->h_order[(size_t)i * nq / S];   // cost order kept
+    int32_t* d_ids = nullptr;
+    double* d_rho = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipMalloc(&d_ids, S * sizeof(int32_t));
+    if (e == hipSuccess) e = hipMalloc(&d_rho, (size_t)nq * sizeof(double));
+    if (e == hipSuccess) e = hipMemcpy(d_ids, ids.data(), S * sizeof(int32_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    LaunchParams P = base_params(plan, v_loc, atom_R, proj_E, mu, kT);
+    P.order = d_ids;
+    P.n_nodes = S;
+    P.rho = d_rho;
+    float best_ms = 1e30f;
+    for (size_t c = 0; c < cand.size() && e == hipSuccess; ++c) {
+      const int grid = std::max(1, std::min(S, plan->ncu * cand[c].second));
+      float ms = 1e30f;
+      for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {   // first run warms up
+        e = launch_setup(P, plan->fp64, v_loc, plan->d_v, plan->d_chi, plan->d_g0, plan->d_vmax, s);
+        if (e == hipSuccess) e = hipEventRecord(e0, s);
+        if (e == hipSuccess) e = launch_forward(P, plan->fp64, grid, cand[c].first, plan->kg, s);
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float t = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+        if (rep > 0) ms = std::min(ms, t);
+      }
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = cand[c];
+      }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (d_ids) (void)hipFree(d_ids);
+    if (d_rho) (void)hipFree(d_rho);
+    if (e != hipSuccess) return fail(SGQ_EHIP, std::string("autotune: ") + hipGetErrorString(e));
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[key] = best;
+    tune_file_append(key, best.first, best.second);
+  }
+  if (nq > 0) {
+    st = ensure_slots(plan, std::min(nq, plan->ncu * best.second));
+    if (st != SGQ_OK) return st;
+  }
+  plan->block = best.first;
+  plan->grid = std::max(1, std::min(nq, plan->ncu * best.second));
+  plan->tuned = true;
+  if (chosen) {
+    chosen[0] = best.first;
+    chosen[1] = best.second;
+  }
   return SGQ_OK;
 }
 
@@ -378,11 +608,7 @@ extern "C" int band_energy(sgq_plan* plan, const double* v_loc, const double* at
   LaunchParams P = base_params(plan, v_loc, atom_R, proj_E, mu, kT);
   P.e_node = e_node;
   P.integrand = integrand;
-  hipStream_t s = (hipStream_t)stream;
-  st = run_forward(plan, P, v_loc, s);
-  if (st != SGQ_OK) return st;
-  HIP_OR_FAIL(launch_weighted_sum(e_node, node_weight, plan->prob.n_nodes, omega, s));
-  return SGQ_OK;
+  return run_forward(plan, 1, P, v_loc, node_weight, omega, (hipStream_t)stream);
 }
 
 // Backward workspace, node cube offsets and the dV gather lists (first backward call).

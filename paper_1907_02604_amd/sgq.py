@@ -21,7 +21,8 @@ SGQ_SCHEDULE_BATCHED, SGQ_SCHEDULE_PLAIN = 0, 1
 
 EXPORTED = ("sgq_plan_create", "sgq_plan_destroy", "rho_quadrature", "band_energy",
             "band_energy_backward", "sgq_vloc_gaussian_backward", "sgq_plan_status",
-            "sgq_last_error", "sgq_validate", "sgq_gauss_rule_host", "sgq_plan_set_schedule")
+            "sgq_last_error", "sgq_validate", "sgq_gauss_rule_host", "sgq_plan_set_schedule",
+            "sgq_plan_set_graph", "sgq_plan_autotune")
 
 
 class SgqError(RuntimeError):
@@ -54,6 +55,8 @@ def _load():
         "sgq_validate": (I, [ctypes.POINTER(Problem), P, P, P]),
         "sgq_gauss_rule_host": (I, [P, P, I, P, P]),
         "sgq_plan_set_schedule": (I, [P, I]),
+        "sgq_plan_set_graph": (I, [P, I]),
+        "sgq_plan_autotune": (I, [P, P, P, P, D, D, I, P, ctypes.POINTER(ctypes.c_int32)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -161,6 +164,19 @@ class Plan:
     def set_schedule(self, schedule):
         """SGQ_SCHEDULE_BATCHED (default) or SGQ_SCHEDULE_PLAIN (per-node baseline)."""
         _check(_lib.sgq_plan_set_schedule(self._h, int(schedule)))
+
+    def set_graph(self, enable):
+        """Capture and replay the forward launches as a HIP graph (default on)."""
+        _check(_lib.sgq_plan_set_graph(self._h, int(bool(enable))))
+
+    def autotune(self, v_loc, atom_R, proj_E, mu, kT, sample_nodes=2048, stream=None):
+        """Pick the launch shape of the forward kernel by timing candidates on a sample of
+        this plan's nodes (sgq_plan_autotune); returns (lanes per node, workgroups per CU)."""
+        out = (ctypes.c_int32 * 2)()
+        _check(_lib.sgq_plan_autotune(self._h, _ptr(v_loc), _ptr(atom_R), _ptr(proj_E),
+                                      float(mu), float(kT), int(sample_nodes),
+                                      _stream(stream), out))
+        return int(out[0]), int(out[1])
 
     def status(self):
         st = ctypes.c_int32(0)
