@@ -29,7 +29,6 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2, 2))) v
   const int tid = threadIdx.x;
   SGQ_G T* __restrict__ W = (SGQ_G T*)P.W + (size_t)blockIdx.x * P.slot_stride;
   SGQ_G T* __restrict__ U = (SGQ_G T*)P.U + (size_t)blockIdx.x * P.npad;
-  const double h3 = P.h * P.h * P.h;
   if (tid == 0) st.orth_tol = sizeof(T) == 4 ? 3.4526698300124393e-4 : 1.4901161193847656e-8;
 
   for (;;) {
@@ -41,53 +40,88 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2, 2))) v
     node_setup<T, BLOCK>(P, st, q);
     const int K = P.depth[q];
     if (st.abort) {
-      if (tid == 0) {
-        double nan = __builtin_nan("");
-        if (P.rho) P.rho[q] = nan;
-        if (P.e_node) P.e_node[q] = nan;
-        if (P.k_eff) P.k_eff[q] = 0;
-      }
+      if (tid == 0) P.tri_k[q] = -1;
       __syncthreads();
       continue;
     }
     const int keff = run_lanczos<T, BLOCK, KG>(P, st, W, U, 0, K);
-    // ---- Gauss rule and quadrature (one thread)
-    if (tid == 0) {
-      for (int k = 0; k < keff; ++k) st.ta[k] = st.alpha[k];
-      for (int k = 0; k + 1 < keff; ++k) st.tb[k] = st.beta[k];
-      bool ok = tridiag_gauss(st.ta, st.tb, st.tz, keff);
-      if (!ok) atomicOr(P.status, kStatusNonFinite);
-      double rho = 0.0, e = 0.0;
-      for (int k = 0; k < keff; ++k) {
-        double wk = st.tz[k] * st.tz[k];
-        double th = st.ta[k];
-        rho += wk * fermi_occ((th - P.mu) / P.kT);
-        if (P.e_node) e += wk * integrand_value(th, P.mu, P.kT, P.integrand);
-      }
-      if (P.rho) P.rho[q] = 2.0 / h3 * rho;
-      if (P.e_node) P.e_node[q] = 2.0 * e;
-      if (P.k_eff) P.k_eff[q] = keff;
-      if (P.theta_w) {
-        // ascending order of nodes
-        for (int k = 1; k < keff; ++k) {
-          double tk = st.ta[k], zk = st.tz[k];
-          int i = k - 1;
-          while (i >= 0 && st.ta[i] > tk) {
-            st.ta[i + 1] = st.ta[i];
-            st.tz[i + 1] = st.tz[i];
-            --i;
-          }
-          st.ta[i + 1] = tk;
-          st.tz[i + 1] = zk;
-        }
-        double* out = P.theta_w + (size_t)q * P.kmax_out * 2;
-        for (int k = 0; k < P.kmax_out; ++k) {
-          out[2 * k] = k < keff ? st.ta[k] : 0.0;
-          out[2 * k + 1] = k < keff ? st.tz[k] * st.tz[k] : 0.0;
-        }
-      }
+    // ---- the tridiagonal of the node, for the Gauss-rule kernel
+    double* tri = P.tri + (size_t)q * 2 * P.kmax_out;
+    for (int k = tid; k < keff; k += BLOCK) {
+      tri[k] = st.alpha[k];
+      tri[P.kmax_out + k] = k + 1 < keff ? st.beta[k] : 0.0;
     }
+    if (tid == 0) P.tri_k[q] = keff;
     __syncthreads();
+  }
+}
+
+// LDS array of one thread: element i at p[i * stride].
+struct LdsColumn {
+  SGQ_L double* p;
+  int stride;
+  __device__ SGQ_L double& operator[](int i) const { return p[i * stride]; }
+};
+
+// Gauss rule and quadrature of every node (one thread per node, nodes in cost order so a
+// wave holds tridiagonals of similar size): implicit-shift QR of T_K for the nodes
+// lambda_k and the weights w_k = (first eigenvector component)^2, then
+// rho = 2 h^-3 sum_k w_k g(lambda_k), e = 2 sum_k w_k F(lambda_k), and the sorted rule.
+// LDS holds the thread's diagonal, off-diagonal and first-row arrays, interleaved by
+// thread.
+__global__ void gauss_rule_kernel(LaunchParams P) {
+  extern __shared__ double lds_tri[];
+  const int t = threadIdx.x, nt = blockDim.x;
+  const int i = blockIdx.x * nt + t;
+  if (i >= P.n_nodes) return;
+  const int q = P.order[i];
+  const int kmax = P.kmax_out;
+  const int keff = P.tri_k[q];
+  if (keff < 0) {   // node skipped by the Lanczos kernel (status latched there)
+    double nan = __builtin_nan("");
+    if (P.rho) P.rho[q] = nan;
+    if (P.e_node) P.e_node[q] = nan;
+    if (P.k_eff) P.k_eff[q] = 0;
+    return;
+  }
+  SGQ_L double* base = (SGQ_L double*)lds_tri;
+  const LdsColumn a{base + t, nt}, b{base + (size_t)kmax * nt + t, nt},
+      z{base + (size_t)2 * kmax * nt + t, nt};
+  const double* tri = P.tri + (size_t)q * 2 * kmax;
+  for (int k = 0; k < keff; ++k) {
+    a[k] = tri[k];
+    b[k] = tri[kmax + k];
+  }
+  if (!tridiag_gauss(a, b, z, keff)) atomicOr(P.status, kStatusNonFinite);
+  const double h3 = P.h * P.h * P.h;
+  double rho = 0.0, e = 0.0;
+  for (int k = 0; k < keff; ++k) {
+    const double wk = z[k] * z[k];
+    const double th = a[k];
+    rho += wk * fermi_occ((th - P.mu) / P.kT);
+    if (P.e_node) e += wk * integrand_value(th, P.mu, P.kT, P.integrand);
+  }
+  if (P.rho) P.rho[q] = 2.0 / h3 * rho;
+  if (P.e_node) P.e_node[q] = 2.0 * e;
+  if (P.k_eff) P.k_eff[q] = keff;
+  if (P.theta_w) {
+    // ascending order of the nodes
+    for (int k = 1; k < keff; ++k) {
+      const double tk = a[k], zk = z[k];
+      int m = k - 1;
+      while (m >= 0 && a[m] > tk) {
+        a[m + 1] = a[m];
+        z[m + 1] = z[m];
+        --m;
+      }
+      a[m + 1] = tk;
+      z[m + 1] = zk;
+    }
+    double* out = P.theta_w + (size_t)q * kmax * 2;
+    for (int k = 0; k < kmax; ++k) {
+      out[2 * k] = k < keff ? a[k] : 0.0;
+      out[2 * k + 1] = k < keff ? z[k] * z[k] : 0.0;
+    }
   }
 }
 
@@ -222,6 +256,15 @@ hipError_t launch_setup(const LaunchParams& P, bool fp64, const double* v64, voi
       hipLaunchKernelGGL(projector_table_kernel<float>, dim3(P.n_atoms), dim3(256), 0, s, P,
                          (float*)chi, g0);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_gauss_rule(const LaunchParams& P, hipStream_t s) {
+  if (P.n_nodes <= 0) return hipSuccess;
+  // three K-arrays of doubles per thread; at most 61 KB of LDS per workgroup
+  const int nt = P.kmax_out <= 40 ? 64 : (P.kmax_out <= 80 ? 32 : 16);
+  const size_t lds = (size_t)3 * P.kmax_out * nt * sizeof(double);
+  hipLaunchKernelGGL(gauss_rule_kernel, dim3((P.n_nodes + nt - 1) / nt), dim3(nt), lds, s, P);
   return hipGetLastError();
 }
 

@@ -21,6 +21,7 @@ hipError_t launch_setup(const LaunchParams& P, bool fp64, const double* v64, voi
                         void* chi, int32_t* g0, double* vmax, hipStream_t s);
 hipError_t launch_weighted_sum(const double* e, const double* w, int n, double* out,
                                hipStream_t s);
+hipError_t launch_gauss_rule(const LaunchParams& P, hipStream_t s);
 hipError_t launch_backward(const LaunchParams& P, bool fp64, int grid, int block, int kg,
                            hipStream_t s);
 hipError_t launch_backward_gather(const LaunchParams& P, bool fp64, const int32_t* cell_start,
@@ -75,6 +76,8 @@ struct sgq_plan {
   int* d_queue = nullptr;
   int* d_status = nullptr;
   double* d_enode = nullptr;
+  double* d_tri = nullptr;
+  int32_t* d_trik = nullptr;
   // backward state (allocated on the first backward call)
   bool bwd_ready = false;
   int grid_bwd = 0;
@@ -258,6 +261,8 @@ extern "C" int sgq_plan_create(const sgq_problem* prob, const int64_t* center,
   e = e ? e : dalloc(p, &p->d_queue, 8);
   e = e ? e : dalloc(p, &p->d_status, 8);
   e = e ? e : dalloc(p, &p->d_enode, (size_t)nq * 8);
+  e = e ? e : dalloc(p, &p->d_tri, (size_t)nq * 2 * p->kmax * 8);
+  e = e ? e : dalloc(p, &p->d_trik, (size_t)nq * 4);
   if (e != hipSuccess) {
     free_all(p);
     delete p;
@@ -335,6 +340,8 @@ static LaunchParams base_params(sgq_plan* p, const double* v_loc, const double* 
   P.queue = p->d_queue;
   P.status = p->d_status;
   P.kmax_out = p->kmax;
+  P.tri = p->d_tri;
+  P.tri_k = p->d_trik;
   return P;
 }
 
@@ -345,6 +352,7 @@ static hipError_t forward_sequence(sgq_plan* p, const LaunchParams& P, const dou
   hipError_t e = launch_setup(P, p->fp64, v_loc, p->d_v, p->d_chi, p->d_g0, p->d_vmax, s);
   if (e == hipSuccess && p->prob.n_nodes > 0)
     e = launch_forward(P, p->fp64, p->grid, p->block, p->kg, s);
+  if (e == hipSuccess) e = launch_gauss_rule(P, s);
   if (e == hipSuccess && omega)
     e = launch_weighted_sum(P.e_node, node_weight, p->prob.n_nodes, omega, s);
   return e;

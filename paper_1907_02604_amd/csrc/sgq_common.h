@@ -64,6 +64,8 @@ struct LaunchParams {
   double* theta_w;            // [Nq*kmax_out*2] or null
   int32_t* k_eff;             // [Nq] or null
   int kmax_out;
+  double* tri;                // [Nq][2*kmax_out]: alpha_0.. then beta_0.. of each node
+  int32_t* tri_k;             // [Nq] K_eff of each node's tridiagonal (-1: node skipped)
   // backward extras
   const double* node_weight;  // [Nq]
   const double* grad_omega;   // device scalar
