@@ -13,10 +13,14 @@
 //        ahat = alphabar_j - rbar.q_j,   ubar_j = rbar + ahat q_j
 //        qbar_j += -alpha_j rbar + ahat u_j + H ubar_j
 //        qbar_{j-1} = -beta_{j-1} rbar,  betabar_{j-1} -= rbar.q_{j-1}
-//      accumulating the node's dV cube P_q = sum_j ubar_j o q_j and the projector
-//      adjoints Ebar_Jl += h^3 (chi.ubar)(chi.q), Rbar_J += h^3 E [(ubar.dchi)(chi.q) +
-//      (ubar.chi)(dchi.q)] (dchi = d chi / d R);
-//   4. a gather kernel sums the node cubes into dV in a fixed order (deterministic,
+//      accumulating the node's dV cube P_q = sum_j ubar_j o q_j; ubar_j replaces u_j in
+//      the workspace once step j is done;
+//   4. the projector adjoints Ebar_Jl = h^3 sum_j (chi.ubar_j)(chi.q_j) and
+//      Rbar_J = h^3 E sum_j [(ubar_j.dchi)(chi.q_j) + (ubar_j.chi)(dchi.q_j)]
+//      (dchi = d chi / d R) come from one dense product per atom,
+//      M = [chi; d chi] (16 x box points) . [ubar_0 .. ubar_K-1 | q_0 .. q_K-1], on the
+//      matrix cores (16x16x4 MFMA, accumulation in the storage precision);
+//   5. a gather kernel sums the node cubes into dV in a fixed order (deterministic,
 //      no floating-point atomics) and a reduction kernel sums the atom adjoints.
 #include "lanczos_device.h"
 
@@ -30,10 +34,118 @@ struct BwdState {
   double abar[kBwdMaxDepth], bbar[kBwdMaxDepth];
   double Fv[kBwdMaxDepth], Fd[kBwdMaxDepth];
   double part[4 * kBwdMaxDepth];
-  double Ebar[kMaxNodeAtoms][4];
-  double Rbar[kMaxNodeAtoms][3];
   double sc[8];
 };
+
+// 16x16x4 matrix-core product of one wave: A (16 x 4) from lane i + 16k, B (4 x 16) from
+// lane j + 16k; output element r of lane l is row row(l, r), column l % 16.
+template <typename T>
+struct Mfma16;
+template <>
+struct Mfma16<float> {
+  using V = float __attribute__((ext_vector_type(4)));
+  __device__ static V op(float a, float b, V c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static int row(int l, int r) { return 4 * (l >> 4) + r; }
+};
+template <>
+struct Mfma16<double> {
+  using V = double __attribute__((ext_vector_type(4)));
+  __device__ static V op(double a, double b, V c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ static int row(int l, int r) { return (l >> 4) + 4 * r; }
+};
+
+// Projector adjoints of one node from its stored vectors: for every node atom (one wave
+// per atom) M = [chi_0..3 ; d chi_l / d d_a] (16 x box points) times the matrix of the
+// box values of [ubar_0 .. ubar_K-1 | q_0 .. q_K-1] on the matrix cores, then
+//   Ebar_l = h^3 sum_j M[l][j] M[l][K+j],
+//   Rbar_a = -h^3 sum_l E_l sum_j (M[4+3l+a][j] M[l][K+j] + M[l][j] M[4+3l+a][K+j]).
+// The waves stage M through `scratch` (LDS), `slots` waves at a time.
+template <typename T, int BLOCK, int MAXB>
+__device__ __noinline__ void projector_gradients(const SGQ_G double* proj_E,
+                                                 SGQ_L NodeState<T, BLOCK>& st, ProjEval<T> pe,
+                                                 const SGQ_G T* W, int wbs, const SGQ_G T* Ub,
+                                                 int npad, int keff, double h3, int B, int B3,
+                                                 SGQ_L T* scratch, int slots, double* dEp,
+                                                 double* dRp) {
+  using M16 = Mfma16<T>;
+  using V = typename M16::V;
+  constexpr int NW = BLOCK / kWave;
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const int ncol = 2 * keff, nblk = (ncol + 15) / 16, ld = 16 * MAXB;
+  const int fr = lane & 15, kk = lane >> 4;   // A row / B column, and the k index of the lane
+  SGQ_L T* Ms = scratch + (size_t)(wave < slots ? wave : 0) * 16 * ld;
+  const int natoms = st.natoms;
+  for (int a0 = 0; a0 < natoms; a0 += slots) {
+    const int a = a0 + wave;
+    const bool mine = wave < slots && a < natoms;
+    if (mine) {
+      V acc[MAXB];
+#pragma unroll
+      for (int jb = 0; jb < MAXB; ++jb) acc[jb] = (V)(T)0;
+      for (int k0 = 0; k0 < B3; k0 += 4) {
+        const int b = k0 + kk;
+        const int bx = b % B, by = (b / B) % B, bz = b / (B * B);
+        const int lp = b < B3 ? box_point(st, a, bx, by, bz) : -1;
+        T c[4], g[12];
+        chi_grad_at(pe, st.afrac[a], bx, by, bz, c, g);
+        T av = (T)0;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) av = fr == r ? (r < 4 ? c[r] : g[r - 4]) : av;
+        av = b < B3 ? av : (T)0;
+#pragma unroll
+        for (int jb = 0; jb < MAXB; ++jb) {
+          if (jb < nblk) {
+            const int col = 16 * jb + fr;
+            T bv = (T)0;
+            if (lp >= 0 && col < ncol) {
+              if (col < keff) bv = Ub[(size_t)col * npad + lp];
+              else bv = W[64 * (col - keff) + bidx(lp, wbs)] * (T)st.scale[col - keff];
+            }
+            acc[jb] = M16::op(av, bv, acc[jb]);
+          }
+        }
+      }
+#pragma unroll
+      for (int jb = 0; jb < MAXB; ++jb)
+        if (jb < nblk)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) Ms[M16::row(lane, r) * ld + 16 * jb + fr] = acc[jb][r];
+    }
+    __syncthreads();
+    if (mine) {
+      const int J = st.atom[a];
+      double El[4];
+#pragma unroll
+      for (int l = 0; l < 4; ++l) El[l] = proj_E[4 * J + l];
+      double eb[4] = {0, 0, 0, 0}, rb[3] = {0, 0, 0};
+      for (int j = lane; j < keff; j += kWave) {
+#pragma unroll
+        for (int l = 0; l < 4; ++l) {
+          const double cu = (double)Ms[l * ld + j], cq = (double)Ms[l * ld + keff + j];
+          eb[l] += cu * cq;
+#pragma unroll
+          for (int ax = 0; ax < 3; ++ax) {
+            const int rr = 4 + 3 * l + ax;
+            rb[ax] += El[l] * ((double)Ms[rr * ld + j] * cq + cu * (double)Ms[rr * ld + keff + j]);
+          }
+        }
+      }
+#pragma unroll
+      for (int l = 0; l < 4; ++l) eb[l] = wave_sum(eb[l]);
+#pragma unroll
+      for (int ax = 0; ax < 3; ++ax) rb[ax] = wave_sum(rb[ax]);
+      if (lane == 0) {
+        for (int l = 0; l < 4; ++l) dEp[4 * a + l] = h3 * eb[l];
+        for (int ax = 0; ax < 3; ++ax) dRp[3 * a + ax] = -h3 * rb[ax];
+      }
+    }
+    __syncthreads();
+  }
+}
 
 // Implicit-shift QR of the tridiagonal (a, b) accumulating all eigenvectors in Z.
 // Run by one whole wave: every lane computes the same rotations from the LDS copies of
@@ -104,73 +216,6 @@ __device__ bool tridiag_eig_wave(SGQ_L double* a, SGQ_L double* b, SGQ_L double*
   return true;
 }
 
-// Projector adjoint dots of ubar and q_j for every node atom (one wave per atom):
-// Ebar and Rbar accumulate, st.acoef receives E h^3 (chi.ubar) for the scatter of V_nl ubar.
-template <typename T, int BLOCK>
-__device__ __noinline__ void projector_adjoint(const SGQ_G double* proj_E,
-                                               SGQ_L NodeState<T, BLOCK>& st, SGQ_L BwdState& bs,
-                                               const SGQ_G T* __restrict__ chi,
-                                               const SGQ_G T* __restrict__ dchi,
-                                               const SGQ_G T* ub, const SGQ_G T* Wj, int wbs, double sj,
-                                               double h3, int B, int B3) {
-  using T4 = T __attribute__((ext_vector_type(4)));
-  constexpr int NW = BLOCK / kWave;
-  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-  for (int a = wave; a < st.natoms; a += NW) {
-    const int J = st.atom[a];
-    T cu[4] = {0, 0, 0, 0}, cq[4] = {0, 0, 0, 0};
-    T du[12], dq[12];
-#pragma unroll
-    for (int c = 0; c < 12; ++c) du[c] = dq[c] = (T)0;
-    for (int b = lane; b < B3; b += kWave) {
-      const int lp = box_point(st, a, b, B);
-      if (lp < 0) continue;
-      const T u = ub[lp];
-      const T qv = Wj[bidx(lp, wbs)] * (T)sj;
-      const T4 c4 = *reinterpret_cast<const SGQ_G T4*>(chi + ((size_t)J * B3 + b) * 4);
-      const SGQ_G T* g = dchi + ((size_t)J * B3 + b) * 12;
-#pragma unroll
-      for (int l = 0; l < 4; ++l) {
-        cu[l] += c4[l] * u;
-        cq[l] += c4[l] * qv;
-      }
-#pragma unroll
-      for (int c = 0; c < 12; ++c) {
-        const T gv = g[c];
-        du[c] += gv * u;
-        dq[c] += gv * qv;
-      }
-    }
-    double Cu[4], Cq[4];
-#pragma unroll
-    for (int l = 0; l < 4; ++l) {
-      Cu[l] = (double)wave_sum(cu[l]);
-      Cq[l] = (double)wave_sum(cq[l]);
-    }
-    double Du[12], Dq[12];
-#pragma unroll
-    for (int c = 0; c < 12; ++c) {
-      Du[c] = (double)wave_sum(du[c]);
-      Dq[c] = (double)wave_sum(dq[c]);
-    }
-    if (lane == 0) {
-      double rb[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-      for (int l = 0; l < 4; ++l) {
-        const double E = proj_E[4 * J + l];
-        bs.Ebar[a][l] += h3 * Cu[l] * Cq[l];
-        st.acoef[a][l] = (T)(E * h3 * Cu[l]);
-#pragma unroll
-        for (int ax = 0; ax < 3; ++ax)   // d chi / d R = -(d chi / d displacement)
-          rb[ax] -= h3 * E * (Du[3 * l + ax] * Cq[l] + Cu[l] * Dq[3 * l + ax]);
-      }
-      bs.Rbar[a][0] += rb[0];
-      bs.Rbar[a][1] += rb[1];
-      bs.Rbar[a][2] += rb[2];
-    }
-  }
-}
-
 template <typename T, int BLOCK, int KG>
 __global__ __launch_bounds__(BLOCK) void lanczos_backward_kernel(LaunchParams P) {
   constexpr int NW = BLOCK / kWave;
@@ -186,10 +231,7 @@ __global__ __launch_bounds__(BLOCK) void lanczos_backward_kernel(LaunchParams P)
   SGQ_G T* __restrict__ Ubase = W + (size_t)kmax * npad;
   SGQ_G T* __restrict__ R[3] = {Ubase + (size_t)kmax * npad, Ubase + (size_t)(kmax + 1) * npad,
                                 Ubase + (size_t)(kmax + 2) * npad};
-  SGQ_G T* __restrict__ UB = Ubase + (size_t)(kmax + 3) * npad;
   const SGQ_G T* __restrict__ V = (const SGQ_G T*)P.v;
-  const SGQ_G T* __restrict__ chi = (const SGQ_G T*)P.chi;
-  const SGQ_G T* __restrict__ dchi = (const SGQ_G T*)P.dchi;
   const ProjEval<T> pe = proj_eval<T>(P);
   const SGQ_G double* proj_E = (const SGQ_G double*)P.proj_E;
   const double h = P.h, h3 = h * h * h;
@@ -216,10 +258,6 @@ __global__ __launch_bounds__(BLOCK) void lanczos_backward_kernel(LaunchParams P)
     const int n = st.n, natoms = st.natoms;
     const int keff = run_lanczos<T, BLOCK, KG>(P, st, W, Ubase, npad, P.depth[q]);
     // ---- eigenvectors of T and the Daleckii-Krein adjoint
-    for (int a = tid; a < natoms; a += BLOCK) {
-      for (int l = 0; l < 4; ++l) bs.Ebar[a][l] = 0.0;
-      for (int c = 0; c < 3; ++c) bs.Rbar[a][c] = 0.0;
-    }
     for (int k = tid; k < keff; k += BLOCK) {
       st.ta[k] = st.alpha[k];
       st.tb[k] = k + 1 < keff ? st.beta[k] : 0.0;
@@ -277,7 +315,7 @@ __global__ __launch_bounds__(BLOCK) void lanczos_backward_kernel(LaunchParams P)
       const SGQ_G T* Wc = W + 64 * j;
       const SGQ_G T* Wn = W + 64 * (j + 1);
       const SGQ_G T* Wp = W + 64 * (j > 0 ? j - 1 : 0);
-      const SGQ_G T* Uj = Ubase + (size_t)j * npad;
+      SGQ_G T* Uj = Ubase + (size_t)j * npad;      // u_j, replaced by ubar_j in pass B
       SGQ_G T* Q0 = R[r0];
       SGQ_G T* Q1 = R[r1];
       SGQ_G T* Q2 = R[r2];
@@ -333,16 +371,17 @@ __global__ __launch_bounds__(BLOCK) void lanczos_backward_kernel(LaunchParams P)
           const double qc = sc_ * (double)Wc[bidx(p, wbs)];
           const double rb = last ? 0.0 : (double)Q0[p] * ib + bb * sn * (double)Wn[bidx(p, wbs)];
           const double ub = rb + ahat * qc;
-          UB[p] = (T)ub;
+          const double uj = (double)Uj[p];
+          Uj[p] = (T)ub;
           Pq[p] = (T)((last ? 0.0 : (double)Pq[p]) + ub * qc);
-          Q1[p] = (T)((last ? 0.0 : (double)Q1[p]) - al * rb + ahat * (double)Uj[p]);
+          Q1[p] = (T)((last ? 0.0 : (double)Q1[p]) - al * rb + ahat * uj);
           if (j > 0) Q2[p] = (T)(-bprev * rb);
         }
       }
       __syncthreads();
-      // pass C: qbar_j += H ubar_j, with the projector adjoints of this step
-      if (natoms > 0) projector_adjoint<T, BLOCK>(proj_E, st, bs, chi, dchi, UB, Wc, wbs, sc_, h3, B, B3);
-      apply_local<T, BLOCK, true>(P, st, V, UB, 64, Q1, (T)1, kin);
+      // pass C: qbar_j += H ubar_j (projector weights E h^3 chi.ubar_j for the scatter)
+      if (natoms > 0) projector_dots<T, BLOCK>(proj_E, st, pe, Uj, 64, 1.0, h3, B, B3);
+      apply_local<T, BLOCK, true>(P, st, V, Uj, 64, Q1, (T)1, kin);
       __syncthreads();
       apply_scatter<T, BLOCK>(P, st, pe, Q1, B, B3);
       __syncthreads();
@@ -351,47 +390,20 @@ __global__ __launch_bounds__(BLOCK) void lanczos_backward_kernel(LaunchParams P)
       r1 = r2;
       r2 = t0;
     }
-    // ---- per-node outputs of the projector adjoints
+    // ---- per-node projector adjoints (matrix cores), staged through the dead Z block
     double* dEp = P.dE_part + (size_t)q * kMaxNodeAtoms * 4;
     double* dRp = P.dR_part + (size_t)q * kMaxNodeAtoms * 3;
-    for (int a = tid; a < natoms; a += BLOCK) {
-      natoms_out[1 + a] = st.atom[a];
-      for (int l = 0; l < 4; ++l) dEp[4 * a + l] = bs.Ebar[a][l];
-      for (int c = 0; c < 3; ++c) dRp[3 * a + c] = bs.Rbar[a][c];
+    if (natoms > 0) {
+      constexpr int MAXB = (2 * kBwdMaxDepth + 15) / 16;
+      constexpr int per_wave = 16 * 16 * MAXB * (int)sizeof(T);
+      constexpr int slots = (int)sizeof(bs.Z) / per_wave < NW ? (int)sizeof(bs.Z) / per_wave : NW;
+      static_assert(slots >= 1, "the Z block must hold one wave's product");
+      projector_gradients<T, BLOCK, MAXB>(proj_E, st, pe, W, wbs, Ubase, (int)npad, keff, h3, B,
+                                          B3, (SGQ_L T*)bs.Z, slots, dEp, dRp);
     }
+    for (int a = tid; a < natoms; a += BLOCK) natoms_out[1 + a] = st.atom[a];
     if (tid == 0) natoms_out[0] = natoms;
     __syncthreads();
-  }
-}
-
-// d chi_l / d(displacement) on the projector box of each atom: [M][B^3][4][3].
-template <typename T>
-__global__ void projector_grad_table_kernel(LaunchParams P, T* __restrict__ dchi) {
-  const int B = 2 * P.box_m + 1, B3 = B * B * B;
-  const int J = blockIdx.x;
-  if (J >= P.n_atoms) return;
-  const double Rx = P.atom_R[3 * J], Ry = P.atom_R[3 * J + 1], Rz = P.atom_R[3 * J + 2];
-  const int gx = (int)rint(Rx / P.h), gy = (int)rint(Ry / P.h), gz = (int)rint(Rz / P.h);
-  const double rg = P.proj_rg, rg2 = rg * rg, rc2 = P.proj_rc * P.proj_rc;
-  for (int b = threadIdx.x; b < B3; b += blockDim.x) {
-    const int bx = b % B - P.box_m, by = (b / B) % B - P.box_m, bz = b / (B * B) - P.box_m;
-    const double d[3] = {(gx + bx) * P.h - Rx, (gy + by) * P.h - Ry, (gz + bz) * P.h - Rz};
-    const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-    double g = 0.0, dg_over_d = 0.0;
-    if (r2 < rc2) {
-      const double t = 1.0 - r2 / rc2, e = exp(-r2 / (2.0 * rg2));
-      g = e * t * t * t;
-      // d g / d d_a = d_a e (-t^3 / rg^2 - 6 t^2 / rc^2)
-      dg_over_d = e * (-(t * t * t) / rg2 - 6.0 * t * t / rc2);
-    }
-    T* out = dchi + ((size_t)J * B3 + b) * 12;
-    for (int a = 0; a < 3; ++a) out[a] = (T)(P.proj_norm_s * dg_over_d * d[a]);
-    for (int l = 0; l < 3; ++l)
-      for (int a = 0; a < 3; ++a) {
-        double v = P.proj_norm_p / rg * d[l] * dg_over_d * d[a];
-        if (l == a) v += P.proj_norm_p / rg * g;
-        out[3 * (l + 1) + a] = (T)v;
-      }
   }
 }
 
@@ -510,9 +522,6 @@ __global__ __launch_bounds__(256) void vloc_backward_kernel(const double* __rest
 // ------------------------------------------------------------------ host launchers
 template <typename T>
 static hipError_t launch_backward_t(const LaunchParams& P, int grid, int kg, hipStream_t s) {
-  if (P.n_proj > 0 && P.n_atoms > 0)
-    hipLaunchKernelGGL(projector_grad_table_kernel<T>, dim3(P.n_atoms), dim3(256), 0, s, P,
-                       (T*)P.dchi);
   switch (kg) {
     case 8:
       hipLaunchKernelGGL((lanczos_backward_kernel<T, 256, 8>), dim3(grid), dim3(256), 0, s, P);

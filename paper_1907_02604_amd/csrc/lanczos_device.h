@@ -94,6 +94,33 @@ __host__ __device__ inline ProjEval<T> proj_eval(const LaunchParams& P) {
 __device__ __forceinline__ float exp_neg(float x) { return __expf(-x); }
 __device__ __forceinline__ double exp_neg(double x) { return exp(-x); }
 
+// The four projectors and their derivatives with respect to the displacement d = x - R
+// of the point from the atom: g[3 l + a] = d chi_l / d d_a (the derivative with respect to
+// the atom position is its negative).
+template <typename T, typename F>
+__device__ __forceinline__ void chi_grad_at(const ProjEval<T>& pe, const F& f, int bx, int by,
+                                            int bz, T (&c)[4], T (&g)[12]) {
+  const T d[3] = {(T)(bx - pe.m) * pe.h + f[0], (T)(by - pe.m) * pe.h + f[1],
+                  (T)(bz - pe.m) * pe.h + f[2]};
+  const T r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+  const T t = (T)1 - r2 * pe.inv_rc2;
+  const bool in = t > (T)0;
+  const T e = in ? exp_neg(r2 * pe.k2) : (T)0;
+  const T gv = e * (t * t * t);                                              // e t^3
+  const T gd = in ? e * (-(T)2 * pe.k2 * (t * t * t) - (T)6 * pe.inv_rc2 * (t * t)) : (T)0;
+  c[0] = pe.ns * gv;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    c[1 + a] = pe.npr * d[a] * gv;
+    g[a] = pe.ns * gd * d[a];
+  }
+#pragma unroll
+  for (int l = 0; l < 3; ++l)
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+      g[3 * (l + 1) + a] = pe.npr * (d[l] * gd * d[a] + (l == a ? gv : (T)0));
+}
+
 template <typename T, typename F>
 __device__ __forceinline__ void chi_at(const ProjEval<T>& pe, const F& f, int bx, int by, int bz,
                                        T (&c)[4]) {

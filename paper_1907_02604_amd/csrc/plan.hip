@@ -83,7 +83,6 @@ struct sgq_plan {
   int grid_bwd = 0;
   size_t bwd_slot_stride = 0;
   void* d_Wb = nullptr;
-  void* d_dchi = nullptr;
   void* d_P = nullptr;
   int64_t* d_cube_off = nullptr;
   double* d_dRp = nullptr;
@@ -688,8 +687,8 @@ static int ensure_backward(sgq_plan* p) {
   p->ncells = ncells;
   // one workgroup per CU (the eigenvector matrix of T lives in LDS)
   p->grid_bwd = std::max(1, std::min(nq, p->ncu));
-  p->bwd_slot_stride = (size_t)(2 * p->kmax + 4) * p->npad;
-  const int B = 2 * p->box_m + 1;
+  // slot: the point-blocked basis (kmax rows), u_j then ubar_j (kmax rows), 3 adjoint rows
+  p->bwd_slot_stride = (size_t)(2 * p->kmax + 3) * p->npad;
   hipError_t e = hipSuccess;
   e = e ? e : dalloc(p, &p->d_Wb, (size_t)p->grid_bwd * p->bwd_slot_stride * es);
   e = e ? e : dalloc(p, &p->d_P, (size_t)std::max<int64_t>(1, off[nq]) * es);
@@ -697,8 +696,6 @@ static int ensure_backward(sgq_plan* p) {
   e = e ? e : dalloc(p, &p->d_dRp, (size_t)nq * kMaxNodeAtoms * 3 * 8);
   e = e ? e : dalloc(p, &p->d_dEp, (size_t)nq * kMaxNodeAtoms * 4 * 8);
   e = e ? e : dalloc(p, &p->d_node_atoms, (size_t)nq * (kMaxNodeAtoms + 1) * 4);
-  if (p->prob.n_proj)
-    e = e ? e : dalloc(p, &p->d_dchi, (size_t)std::max(1, p->prob.n_atoms) * B * B * B * 12 * es);
   if (e != hipSuccess) {
     (void)hipGetLastError();
     return fail(SGQ_ENOMEM, std::string("backward workspace: ") + hipGetErrorString(e));
@@ -735,7 +732,6 @@ extern "C" int band_energy_backward(sgq_plan* plan, const double* v_loc, const d
   P.node_atoms = plan->d_node_atoms;
   P.dE_part = plan->d_dEp;
   P.dR_part = plan->d_dRp;
-  P.dchi = plan->d_dchi;
   HIP_OR_FAIL(launch_setup(P, plan->fp64, v_loc, plan->d_v, plan->d_chi, plan->d_g0, plan->d_vmax, s));
   if (plan->prob.n_nodes > 0)
     HIP_OR_FAIL(launch_backward(P, plan->fp64, plan->grid_bwd, 256, plan->kg, s));

@@ -71,7 +71,6 @@ struct LaunchParams {
   const double* grad_omega;   // device scalar
   void* P_cube;               // [Nq][cube points] per-node dV contribution (storage precision)
   const int64_t* cube_offset; // [Nq] offset of each node's cube in P_cube
-  const void* dchi;           // [M*B^3*12] projector gradients in storage precision
   double* dR_part;            // [Nq][kMaxNodeAtoms][3] node partials of dR (nonlocal)
   double* dE_part;            // [Nq][kMaxNodeAtoms][4] node partials of dE
   int32_t* node_atoms;        // [Nq][1 + kMaxNodeAtoms]: count, then the node's atom ids
