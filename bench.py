@@ -240,9 +240,15 @@ def main():
         torch.cuda.synchronize()
         ta = time.perf_counter() - t0
         assert aplan.status() == sgq.SGQ_OK
+        # algorithmic bytes of one node's adjoint: the forward recompute B(n, K), the adjoint
+        # vectors and their matvec 4n*8K, the node's dV cube 4n
+        abytes = float(sum(alg_bytes((2 * r + 1) ** 3, k) + 4.0 * (2 * r + 1) ** 3 * (8 * k + 1)
+                           for r, k in zip(Q4.half_width, Q4.depth)))
         rec["adjoint"] = {"value": Q4.n_nodes / ta, "unit": "nodes/s", "nodes": Q4.n_nodes,
                           "workload": "48^3 grid, 16 atoms with KB projectors, 33^3 cubes, K=60, "
-                                      "FP32, dOmega/dV + dOmega/dR + dOmega/dE"}
+                                      "FP32, dOmega/dV + dOmega/dR + dOmega/dE",
+                          "alg_bytes": abytes, "achieved_GBs": abytes / ta / 1e9,
+                          "frac_hbm_peak": abytes / ta / 1e9 / HBM_PEAK_GBS}
         aplan.close()
         print(f"[bench] adjoint {Q4.n_nodes / ta:.1f} nodes/s", file=sys.stderr, flush=True)
     if cpu_rec is not None:
