@@ -114,6 +114,8 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--plain-nodes", type=int, default=32)
     ap.add_argument("--adjoint-nodes", type=int, default=2048)
+    ap.add_argument("--no-uneven", action="store_true",
+                    help="skip the uneven-batching measurement (96^3, 20000 nodes, R and K drawn)")
     ap.add_argument("--tune-nodes", type=int, default=2048,
                     help="nodes of the sample the launch-shape autotuner times")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -251,6 +253,38 @@ def main():
                           "frac_hbm_peak": abytes / ta / 1e9 / HBM_PEAK_GBS}
         aplan.close()
         print(f"[bench] adjoint {Q4.n_nodes / ta:.1f} nodes/s", file=sys.stderr, flush=True)
+    if not args.no_uneven:
+        # uneven batching: 20000 nodes with radii U{6..12} bohr and depths U{40..100} in one
+        # persistent, autotuned, graph-replayed launch
+        P3 = synth.make_problem(3)
+        uplan = sgq.Plan.from_problem(P3)
+        v3, R3, E3, _ = sgq.device_inputs(P3)
+        rho3 = torch.empty(P3.n_nodes, dtype=torch.float64, device="cuda")
+        shape3 = uplan.autotune(v3, R3, E3, P3.mu, P3.kT, sample_nodes=args.tune_nodes,
+                                stream=stream.cuda_stream)
+        sgq.rho_quadrature(uplan, v3, R3, E3, P3.mu, P3.kT, rho3, stream=stream.cuda_stream)
+        stream.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        sgq.rho_quadrature(uplan, v3, R3, E3, P3.mu, P3.kT, rho3, stream=stream.cuda_stream)
+        e1.record(stream)
+        stream.synchronize()
+        t3 = e0.elapsed_time(e1) * 1e-3
+        assert uplan.status() == sgq.SGQ_OK
+        b3 = float(sum(alg_bytes((2 * r + 1) ** 3, k) for r, k in zip(P3.half_width, P3.depth)))
+        costs = [alg_bytes((2 * r + 1) ** 3, k) for r, k in zip(P3.half_width, P3.depth)]
+        rec["uneven"] = {"value": P3.n_nodes / t3, "unit": "nodes/s", "nodes": P3.n_nodes,
+                         "workload": "96^3 grid h=0.5, 760 atoms with KB projectors, radii "
+                                     "U{6..12} bohr (cubes 25^3..49^3), depths U{40..100}, "
+                                     "kT=0.005, FP32",
+                         "launch_ms": t3 * 1e3, "alg_bytes": b3, "achieved_GBs": b3 / t3 / 1e9,
+                         "frac_hbm_peak": b3 / t3 / 1e9 / HBM_PEAK_GBS,
+                         "node_cost_spread": max(costs) / min(costs),
+                         "launch": {"lanes_per_node": shape3[0], "workgroups_per_cu": shape3[1],
+                                    "autotuned": True, "hip_graph": True}}
+        uplan.close()
+        print(f"[bench] uneven {P3.n_nodes / t3:.1f} nodes/s", file=sys.stderr, flush=True)
     if cpu_rec is not None:
         got = rho.cpu().numpy()[sample]
         err = float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
