@@ -381,7 +381,7 @@ __global__ __launch_bounds__(BLOCK) void lanczos_backward_kernel(LaunchParams P)
       __syncthreads();
       // pass C: qbar_j += H ubar_j (projector weights E h^3 chi.ubar_j for the scatter)
       if (natoms > 0) projector_dots<T, BLOCK>(proj_E, st, pe, Uj, 64, 1.0, h3, B, B3);
-      apply_local<T, BLOCK, true>(P, st, V, Uj, 64, Q1, (T)1, kin);
+      apply_local<T, BLOCK, true>(P, st, V, Uj, 64, Q1, (T)1, kin, pe, B, false);
       __syncthreads();
       apply_scatter<T, BLOCK>(P, st, pe, Q1, B, B3);
       __syncthreads();

@@ -14,6 +14,13 @@ constexpr int kMarchPad = 1700;  // padded plane (sx + 6)(sy + 6) of the plane m
 template <typename T, int BLOCK>
 struct NodeState {
   static constexpr int NW = BLOCK / kWave;
+  // FP32 nodes add the parallel projector group inside the stencil march (per-plane atom
+  // lists and a double-buffered plane correction); FP64 keeps the separate scatter so that
+  // two FP64 workgroups still fit a CU's LDS
+  static constexpr bool kFuse = sizeof(T) == 4;
+  static constexpr int kPlanes = kFuse ? 35 : 1;   // cube edges of the plane march
+  static constexpr int kPlaneAtoms = 32;           // group atoms crossing one plane
+  static constexpr int kCorr = kFuse ? 35 * 35 : 1;
   int node;
   int sx, sy, sz, ox, oy, oz, periodic, n, start, natoms, abort;
   int atom[kMaxNodeAtoms];
@@ -37,7 +44,17 @@ struct NodeState {
   int redo;
   int wflag[NW];
   T plane[2][kMarchPad];            // z planes of the cube (zero halo of 3) for the march
+  int fuse;                         // the group scatter runs inside the march
+  int pl_count[kPlanes];            // group atoms whose box crosses plane z
+  unsigned char pl_atom[kPlanes][kPlaneAtoms];
+  T corr[2][kCorr];                 // projector term of the next plane, by in-plane index
 };
+
+// Whether the node's stencil runs as the plane march (the condition apply_local uses).
+template <typename S>
+__device__ __forceinline__ bool uses_march(const S& st, int block) {
+  return !st.periodic && st.sx * st.sy <= 5 * block && (st.sx + 6) * (st.sy + 6) <= kMarchPad;
+}
 
 // local linear index -> (x, y, z) of a cube with extents sx, sy
 __device__ __forceinline__ void unflatten(int p, int sx, int sxy, float inv_sx, float inv_sxy,
@@ -161,6 +178,7 @@ __device__ __noinline__ void node_setup(const LaunchParams& P, SGQ_L NodeState<T
     st.n = st.sx * st.sy * st.sz;
     st.natoms = 0;
     st.abort = 0;
+    st.fuse = 0;
   }
   __syncthreads();
   if (P.n_proj == 0) return;
@@ -246,6 +264,33 @@ __device__ __noinline__ void node_setup(const LaunchParams& P, SGQ_L NodeState<T
     st.ngrp = c;
   }
   __syncthreads();
+  if constexpr (NodeState<T, BLOCK>::kFuse) {
+    constexpr int KP = NodeState<T, BLOCK>::kPlanes, KA = NodeState<T, BLOCK>::kPlaneAtoms;
+    const bool march = uses_march(st, BLOCK) && st.sz <= KP;
+    if (march) {
+      for (int z = tid; z < st.sz; z += BLOCK) {
+        int c = 0;
+        for (int i = 0; i < st.ngrp; ++i) {
+          const int a = st.grp[i], z0 = st.abox[a][2];
+          if (z >= z0 && z < z0 + B) {
+            if (c < KA) st.pl_atom[z][c] = (unsigned char)a;
+            ++c;
+          }
+        }
+        st.pl_count[z] = c;
+      }
+    }
+    __syncthreads();
+    if (tid == 0) {
+      int ok = march && st.ngrp > 0;
+      for (int z = 0; ok && z < st.sz; ++z) ok = st.pl_count[z] <= KA;
+      st.fuse = ok;
+    }
+    __syncthreads();
+  } else {
+    if (tid == 0) st.fuse = 0;
+    __syncthreads();
+  }
 }
 
 // Buffer resource over `bytes` bytes from `base` (raw, unswizzled): loads at offsets at
@@ -646,12 +691,33 @@ __device__ __noinline__ double stencil_cube(int gnx, int gny, int gnz,
 // from a double-buffered copy of the plane in LDS with a zero halo three points wide,
 // which makes every neighbour a fixed offset (no clamping, no masks); one barrier per
 // plane.  Returns this thread's part of q_j . u.
-template <typename T, int BLOCK, int PPT, bool ACC = false>
+// Projector term of the parallel group on local plane zc, added into buf (in-plane index
+// x + sx*y): the group's boxes are disjoint, so no two (atom, point) pairs meet.
+template <typename T, int BLOCK>
+__device__ __forceinline__ void plane_group_term(SGQ_L NodeState<T, BLOCK>& st, ProjEval<T> pe,
+                                                 int zc, int B, SGQ_L T* buf) {
+  const int BB = B * B, na = st.pl_count[zc], sx = st.sx, sy = st.sy;
+  for (int t = threadIdx.x; t < na * BB; t += BLOCK) {
+    const int i = t / BB, sp = t - i * BB;
+    const int a = st.pl_atom[zc][i];
+    const int bx = sp % B, by = sp / B, bz = zc - st.abox[a][2];
+    const int x = st.abox[a][0] + bx, y = st.abox[a][1] + by;
+    if (x >= 0 && x < sx && y >= 0 && y < sy) {
+      T c[4];
+      chi_at(pe, st.afrac[a], bx, by, bz, c);
+      buf[x + sx * y] += c[0] * st.acoef[a][0] + c[1] * st.acoef[a][1] + c[2] * st.acoef[a][2] +
+                         c[3] * st.acoef[a][3];
+    }
+  }
+}
+
+template <typename T, int BLOCK, int PPT, bool ACC = false, bool PROJ = false>
 __device__ __noinline__ double stencil_march(int gnx, int gny, int gnz,
                                              SGQ_L NodeState<T, BLOCK>& st,
                                              const SGQ_G T* __restrict__ V,
                                              const SGQ_G T* __restrict__ Wj, int vbs,
-                                             SGQ_G T* __restrict__ U, T sj, T kin) {
+                                             SGQ_G T* __restrict__ U, T sj, T kin,
+                                             ProjEval<T> pe, int B) {
   constexpr int NQ = 8;    // ring of W planes z-3 .. z+4
   constexpr int NV = 4;    // ring of V planes z .. z+3
   static_assert(NQ % NV == 0, "the unrolled z loop indexes both rings by r = z mod NQ");
@@ -661,7 +727,12 @@ __device__ __noinline__ double stencil_march(int gnx, int gny, int gnz,
   const int vplane = gnx * gny;
   const T w0 = (T)(3.0 * kFd0), w1 = (T)kFd1, w2 = (T)kFd2, w3 = (T)kFd3;
   for (int i = tid; i < 2 * kMarchPad; i += BLOCK) (&st.plane[0][0])[i] = (T)0;
+  if (PROJ)
+    for (int i = tid; i < 2 * NodeState<T, BLOCK>::kCorr; i += BLOCK) (&st.corr[0][0])[i] = (T)0;
   __syncthreads();
+  // the group term of a plane is built during the previous plane (plane 0 here) into the
+  // other half of corr; each lane clears its entries after reading them
+  if (PROJ) plane_group_term<T, BLOCK>(st, pe, 0, B, st.corr[0]);
   T ring[PPT][NQ];
   T vring[PPT][NV];
   int li[PPT], vrow[PPT];
@@ -722,10 +793,19 @@ __device__ __noinline__ double stencil_march(int gnx, int gny, int gnz,
           const T u = sj * (kin * lap + vring[k][r % NV] * c);
           if (own[k]) {
             const int p2 = tid + k * BLOCK;
-            if (ACC) U[p2 + z * sxy] += u; else U[p2 + z * sxy] = u;
+            if (ACC) {
+              U[p2 + z * sxy] += u;
+            } else if (PROJ) {
+              SGQ_L T* cz = st.corr[z & 1];
+              U[p2 + z * sxy] = u + cz[p2];
+              cz[p2] = (T)0;
+            } else {
+              U[p2 + z * sxy] = u;
+            }
             apart += (double)(sj * c) * (double)u;
           }
         }
+        if (PROJ && z + 1 < sz) plane_group_term<T, BLOCK>(st, pe, z + 1, B, st.corr[(z + 1) & 1]);
         // refill: plane z+NQ-3 replaces plane z-3, the potential of plane z+NV replaces z
         const int zw = z + NQ - 3, zv = z + NV < sz ? z + NV : sz - 1;
         int gz = gz0 + zv;
@@ -778,23 +858,38 @@ __device__ __noinline__ double stencil_periodic(const SGQ_L NodeState<T, BLOCK>&
 // u = (-1/2 Lap_6 + V) s v for one vector of the node cube (v a row view with block
 // stride vbs, u a plain vector): dispatches the stencil form.  ACC adds into U instead of
 // storing.  Returns this thread's part of (s v) . u.
+// With `group` set and st.fuse on, the march also adds the parallel projector group
+// (weights st.acoef, set by the caller before the call).
 template <typename T, int BLOCK, bool ACC>
 __device__ __forceinline__ double apply_local(const LaunchParams& P, SGQ_L NodeState<T, BLOCK>& st,
                                               const SGQ_G T* V, const SGQ_G T* v, int vbs,
-                                              SGQ_G T* U, T s, T kin) {
+                                              SGQ_G T* U, T s, T kin, ProjEval<T> pe, int B,
+                                              bool group) {
   if (st.periodic) return stencil_periodic<T, BLOCK, ACC>(st, V, v, vbs, U, s, kin);
-  if (st.sx * st.sy <= 5 * BLOCK && (st.sx + 6) * (st.sy + 6) <= kMarchPad)
-    return stencil_march<T, BLOCK, 5, ACC>(P.nx, P.ny, P.nz, st, V, v, vbs, U, s, kin);
+  if (uses_march(st, BLOCK)) {
+    if constexpr (!ACC && NodeState<T, BLOCK>::kFuse) {
+      if (group && st.fuse)
+        return stencil_march<T, BLOCK, 5, false, true>(P.nx, P.ny, P.nz, st, V, v, vbs, U, s,
+                                                       kin, pe, B);
+    }
+    return stencil_march<T, BLOCK, 5, ACC, false>(P.nx, P.ny, P.nz, st, V, v, vbs, U, s, kin,
+                                                  pe, B);
+  }
   return stencil_cube<T, BLOCK, ACC>(P.nx, P.ny, P.nz, st, V, v, vbs, U, s, kin);
 }
 
+// u += V_nl v with the weights st.acoef: the parallel group (unless the march added it,
+// `group` false) and then the remaining atoms one at a time, in atom order.
 template <typename T, int BLOCK>
 __device__ __forceinline__ void apply_scatter(const LaunchParams& P, SGQ_L NodeState<T, BLOCK>& st,
-                                              ProjEval<T> pe, SGQ_G T* U, int B, int B3) {
+                                              ProjEval<T> pe, SGQ_G T* U, int B, int B3,
+                                              bool group = true) {
   const int tid = threadIdx.x;
   if (st.natoms == 0) return;
-  scatter_group<T, BLOCK>(st, pe, U, B, B3);
-  __syncthreads();
+  if (group) {
+    scatter_group<T, BLOCK>(st, pe, U, B, B3);
+    __syncthreads();
+  }
   const bool alias = st.periodic && (P.nx < B || P.ny < B || P.nz < B);
   for (int a = 0; a < st.natoms; ++a) {
     if (!st.aphase[a]) continue;
@@ -849,11 +944,12 @@ __device__ int run_lanczos(const LaunchParams& P, SGQ_L NodeState<T, BLOCK>& st,
     const T sj = (T)sjd;
     // ---- H q_j: projector overlaps, stencil + local potential, projector scatter
     projector_dots<T, BLOCK>(proj_E, st, pe, Wj, bs, sjd, h3, B, B3);
-    double apart = apply_local<T, BLOCK, false>(P, st, V, Wj, bs, U, sj, kin);
+    const bool fused = st.fuse && uses_march(st, BLOCK);
+    double apart = apply_local<T, BLOCK, false>(P, st, V, Wj, bs, U, sj, kin, pe, B, true);
     apart = wave_sum(apart);
     if (lane == 0) st.red[wave][0] = apart;
     __syncthreads();
-    apply_scatter<T, BLOCK>(P, st, pe, U, B, B3);
+    apply_scatter<T, BLOCK>(P, st, pe, U, B, B3, !fused);
     if (tid < kWave) {
       double al = 0.0;
       for (int a = tid; a < natoms; a += kWave) al += st.anl[a];
