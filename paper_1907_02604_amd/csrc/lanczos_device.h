@@ -299,14 +299,19 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_over(const void* base, 
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, bytes, 0x00020000);
 }
 
+// Streaming (non-temporal) load of the basis: each row is read once per Lanczos step and
+// not again before the next step's sweep, so it should not displace the vectors and
+// potential the other phases reuse from L2.
+constexpr int kLoadNT = 2;
+
 template <typename V>
 __device__ __forceinline__ V buffer_load(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
   if constexpr (sizeof(V) == 16)
-    return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+    return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, kLoadNT));
   else if constexpr (sizeof(V) == 8)
-    return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+    return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, kLoadNT));
   else
-    return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+    return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, kLoadNT));
 }
 
 // dst(p) = src(p) - sum_{i<=j} ct_i W_i(p) for every cube point, with the FP64 dots
