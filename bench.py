@@ -113,7 +113,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--plain-nodes", type=int, default=32)
-    ap.add_argument("--adjoint-nodes", type=int, default=2048)
+    ap.add_argument("--adjoint-nodes", type=int, default=8192)
     ap.add_argument("--no-uneven", action="store_true",
                     help="skip the uneven-batching measurement (96^3, 20000 nodes, R and K drawn)")
     ap.add_argument("--tune-nodes", type=int, default=2048,

@@ -26,11 +26,10 @@
 
 namespace sgq {
 
-constexpr int kBwdMaxDepth = 80;   // the eigenvector matrix of T lives in LDS
+constexpr int kBwdMaxDepth = 80;   // largest depth of the adjoint (eigenvector matrix K x K)
 constexpr int kGatherCell = 8;     // dV gather cell edge (points)
 
 struct BwdState {
-  double Z[kBwdMaxDepth * kBwdMaxDepth];   // Z[i*K + k]: component i of eigenvector k
   double abar[kBwdMaxDepth], bbar[kBwdMaxDepth];
   double Fv[kBwdMaxDepth], Fd[kBwdMaxDepth];
   double part[4 * kBwdMaxDepth];
@@ -150,7 +149,10 @@ __device__ __noinline__ void projector_gradients(const SGQ_G double* proj_E,
 // Implicit-shift QR of the tridiagonal (a, b) accumulating all eigenvectors in Z.
 // Run by one whole wave: every lane computes the same rotations from the LDS copies of
 // a and b (lane 0 writes them back) and updates its rows of Z.
-__device__ bool tridiag_eig_wave(SGQ_L double* a, SGQ_L double* b, SGQ_L double* Z, int K) {
+// Z (global, per workgroup slot): Z[i*K + k] is component i of eigenvector k.  Each lane
+// owns rows i = lane (mod 64) of Z, so its updates need no synchronisation with the
+// other lanes.
+__device__ bool tridiag_eig_wave(SGQ_L double* a, SGQ_L double* b, SGQ_G double* Z, int K) {
   const int lane = threadIdx.x & (kWave - 1);
   for (int i = lane; i < K; i += kWave)
     for (int k = 0; k < K; ++k) Z[i * K + k] = (i == k) ? 1.0 : 0.0;
@@ -217,7 +219,7 @@ __device__ bool tridiag_eig_wave(SGQ_L double* a, SGQ_L double* b, SGQ_L double*
 }
 
 template <typename T, int BLOCK, int KG>
-__global__ __launch_bounds__(BLOCK) void lanczos_backward_kernel(LaunchParams P) {
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2, 2))) void lanczos_backward_kernel(LaunchParams P) {
   constexpr int NW = BLOCK / kWave;
   __shared__ NodeState<T, BLOCK> st_shared;
   __shared__ BwdState bs_shared;
@@ -229,6 +231,7 @@ __global__ __launch_bounds__(BLOCK) void lanczos_backward_kernel(LaunchParams P)
   const int wbs = P.wbs;
   SGQ_G T* __restrict__ W = (SGQ_G T*)P.W + (size_t)blockIdx.x * P.slot_stride;
   SGQ_G T* __restrict__ Ubase = W + (size_t)kmax * npad;
+  SGQ_G double* __restrict__ Z = (SGQ_G double*)P.zbuf + (size_t)blockIdx.x * kBwdMaxDepth * kBwdMaxDepth;
   SGQ_G T* __restrict__ R[3] = {Ubase + (size_t)kmax * npad, Ubase + (size_t)(kmax + 1) * npad,
                                 Ubase + (size_t)(kmax + 2) * npad};
   const SGQ_G T* __restrict__ V = (const SGQ_G T*)P.v;
@@ -264,7 +267,7 @@ __global__ __launch_bounds__(BLOCK) void lanczos_backward_kernel(LaunchParams P)
     }
     __syncthreads();
     if (wave == 0) {
-      bool ok = tridiag_eig_wave(st.ta, st.tb, bs.Z, keff);
+      bool ok = tridiag_eig_wave(st.ta, st.tb, Z, keff);
       if (!ok && lane == 0) atomicOr(P.status, kStatusNonFinite);
     }
     __syncthreads();
@@ -282,7 +285,7 @@ __global__ __launch_bounds__(BLOCK) void lanczos_backward_kernel(LaunchParams P)
       double acc = 0.0;
       for (int k = half; k < keff; k += 2) {
         const double tk = st.ta[k];
-        const double ak = bs.Z[j * keff + k] * bs.Z[k];
+        const double ak = Z[j * keff + k] * Z[k];
         double inner = 0.0;
         for (int l = 0; l < keff; ++l) {
           const double tl = st.ta[l];
@@ -295,7 +298,7 @@ __global__ __launch_bounds__(BLOCK) void lanczos_backward_kernel(LaunchParams P)
           } else {
             D = (bs.Fv[k] - bs.Fv[l]) / diff;
           }
-          inner += D * bs.Z[l] * bs.Z[m * keff + l];
+          inner += D * Z[l] * Z[m * keff + l];
         }
         acc += ak * inner;
       }
@@ -390,16 +393,19 @@ __global__ __launch_bounds__(BLOCK) void lanczos_backward_kernel(LaunchParams P)
       r1 = r2;
       r2 = t0;
     }
-    // ---- per-node projector adjoints (matrix cores), staged through the dead Z block
+    // ---- per-node projector adjoints (matrix cores), staged through the march's plane
+    // buffers, which are idle after the reverse recurrence
     double* dEp = P.dE_part + (size_t)q * kMaxNodeAtoms * 4;
     double* dRp = P.dR_part + (size_t)q * kMaxNodeAtoms * 3;
     if (natoms > 0) {
       constexpr int MAXB = (2 * kBwdMaxDepth + 15) / 16;
       constexpr int per_wave = 16 * 16 * MAXB * (int)sizeof(T);
-      constexpr int slots = (int)sizeof(bs.Z) / per_wave < NW ? (int)sizeof(bs.Z) / per_wave : NW;
-      static_assert(slots >= 1, "the Z block must hold one wave's product");
+      constexpr int room = (int)sizeof(st.plane) / per_wave;
+      constexpr int slots = room < NW ? room : NW;
+      static_assert(slots >= 1, "the plane buffers must hold one wave's product");
+      __syncthreads();
       projector_gradients<T, BLOCK, MAXB>(proj_E, st, pe, W, wbs, Ubase, (int)npad, keff, h3, B,
-                                          B3, (SGQ_L T*)bs.Z, slots, dEp, dRp);
+                                          B3, (SGQ_L T*)&st.plane[0][0], slots, dEp, dRp);
     }
     for (int a = tid; a < natoms; a += BLOCK) natoms_out[1 + a] = st.atom[a];
     if (tid == 0) natoms_out[0] = natoms;

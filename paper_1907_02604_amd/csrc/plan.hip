@@ -83,6 +83,7 @@ struct sgq_plan {
   int grid_bwd = 0;
   size_t bwd_slot_stride = 0;
   void* d_Wb = nullptr;
+  double* d_Zb = nullptr;
   void* d_P = nullptr;
   int64_t* d_cube_off = nullptr;
   double* d_dRp = nullptr;
@@ -685,12 +686,14 @@ static int ensure_backward(sgq_plan* p) {
     }
   }
   p->ncells = ncells;
-  // one workgroup per CU (the eigenvector matrix of T lives in LDS)
-  p->grid_bwd = std::max(1, std::min(nq, p->ncu));
+  // two workgroups per CU (node state and adjoint scalars fit twice in a CU's LDS; the
+  // eigenvector matrix of T lives in a global buffer per slot)
+  p->grid_bwd = std::max(1, std::min(nq, 2 * p->ncu));
   // slot: the point-blocked basis (kmax rows), u_j then ubar_j (kmax rows), 3 adjoint rows
   p->bwd_slot_stride = (size_t)(2 * p->kmax + 3) * p->npad;
   hipError_t e = hipSuccess;
   e = e ? e : dalloc(p, &p->d_Wb, (size_t)p->grid_bwd * p->bwd_slot_stride * es);
+  e = e ? e : dalloc(p, &p->d_Zb, (size_t)p->grid_bwd * backward_max_depth() * backward_max_depth() * 8);
   e = e ? e : dalloc(p, &p->d_P, (size_t)std::max<int64_t>(1, off[nq]) * es);
   e = e ? e : dalloc(p, &p->d_cube_off, (size_t)(nq + 1) * 8);
   e = e ? e : dalloc(p, &p->d_dRp, (size_t)nq * kMaxNodeAtoms * 3 * 8);
@@ -723,6 +726,7 @@ extern "C" int band_energy_backward(sgq_plan* plan, const double* v_loc, const d
   hipStream_t s = (hipStream_t)stream;
   LaunchParams P = base_params(plan, v_loc, atom_R, proj_E, mu, kT);
   P.W = plan->d_Wb;
+  P.zbuf = plan->d_Zb;
   P.slot_stride = plan->bwd_slot_stride;
   P.integrand = integrand;
   P.node_weight = node_weight;

@@ -74,6 +74,7 @@ struct LaunchParams {
   double* dR_part;            // [Nq][kMaxNodeAtoms][3] node partials of dR (nonlocal)
   double* dE_part;            // [Nq][kMaxNodeAtoms][4] node partials of dE
   int32_t* node_atoms;        // [Nq][1 + kMaxNodeAtoms]: count, then the node's atom ids
+  double* zbuf;               // [slots][80*80] eigenvector matrix of T per backward slot
 };
 
 // Element index of point p in a vector stored in 64-point blocks with block stride bs
