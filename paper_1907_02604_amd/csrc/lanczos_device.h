@@ -326,31 +326,32 @@ __device__ __forceinline__ V buffer_load(__amdgpu_buffer_rsrc_t r, int voff, int
 // buffer resource: one 32-bit lane offset plus a uniform per-slot offset.  Rows i > j of
 // the last slot are read from row j (finite data) and weighted zero.  src and dst are
 // row views with block strides sbs and bs.
-template <typename T, int BLOCK, int KS, int PU, int VEC>
+template <typename T, int BLOCK, int KS, int PU, int VEC, int G = 4>
 __device__ __noinline__ void fused_sweep_v(SGQ_L NodeState<T, BLOCK>& st,
                                            const SGQ_G T* __restrict__ W, int bs, int wbytes,
                                            const SGQ_G T* src, int sbs, SGQ_G T* dst, int j,
                                            int n) {
   using V = T __attribute__((ext_vector_type(VEC)));
+  static_assert(G == 4 || G == 8, "lane groups of 4 or 8");
   constexpr int ES = (int)sizeof(T);
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
-  const int g = lane & 3;
+  const int g = lane & (G - 1);
   const __amdgpu_buffer_rsrc_t rw = buffer_over((const void*)W, wbytes);
-  const int mlast = j / 4;        // last slot holding a row <= j
-  const int rlast = 4 * mlast + g <= j ? 4 * mlast + g : j;
-  const int dlast = (rlast - g - 4 * mlast) * 64 * ES;
+  const int mlast = j / G;        // last slot holding a row <= j
+  const int rlast = G * mlast + g <= j ? G * mlast + g : j;
+  const int dlast = (rlast - g - G * mlast) * 64 * ES;
   double D[KS];
   T cg[KS];
 #pragma unroll
   for (int m = 0; m < KS; ++m) {
     D[m] = 0.0;
-    const int i = 4 * m + g;
+    const int i = G * m + g;
     cg[m] = (i <= j) ? st.ct[i] : (T)0;
   }
   double n2 = 0.0;
   const int ngroups = (n + VEC - 1) / VEC;
-  constexpr int STRIDE = BLOCK / 4;
-  for (int pg0 = tid >> 2; pg0 < ngroups; pg0 += STRIDE * PU) {
+  constexpr int STRIDE = BLOCK / G;
+  for (int pg0 = tid / G; pg0 < ngroups; pg0 += STRIDE * PU) {
     V qv[PU][KS];
     V sv[PU];
 #pragma unroll
@@ -361,9 +362,9 @@ __device__ __noinline__ void fused_sweep_v(SGQ_L NodeState<T, BLOCK>& st,
 #pragma unroll
       for (int m = 0; m < KS; ++m) {
         if (m < mlast)
-          qv[u][m] = buffer_load<V>(rw, voff, m * 256 * ES);
+          qv[u][m] = buffer_load<V>(rw, voff, m * 64 * G * ES);
         else if (m == mlast)
-          qv[u][m] = buffer_load<V>(rw, voff + dlast, m * 256 * ES);
+          qv[u][m] = buffer_load<V>(rw, voff + dlast, m * 64 * G * ES);
         else
           qv[u][m] = (V)(T)0;
       }
@@ -380,6 +381,7 @@ __device__ __noinline__ void fused_sweep_v(SGQ_L NodeState<T, BLOCK>& st,
       for (int k = 0; k < VEC; ++k) {
         acc[k] += __shfl_xor(acc[k], 1, kWave);
         acc[k] += __shfl_xor(acc[k], 2, kWave);
+        if (G == 8) acc[k] += __shfl_xor(acc[k], 4, kWave);
       }
       V w = sv[u] - acc;
 #pragma unroll
@@ -400,12 +402,12 @@ __device__ __noinline__ void fused_sweep_v(SGQ_L NodeState<T, BLOCK>& st,
 #pragma unroll
   for (int m = 0; m < KS; ++m) {
     double v = D[m];
-    v += __shfl_xor(v, 4, kWave);
+    if (G == 4) v += __shfl_xor(v, 4, kWave);
     v += __shfl_xor(v, 8, kWave);
     v += __shfl_xor(v, 16, kWave);
     v += __shfl_xor(v, 32, kWave);
-    const int i = 4 * m + g;
-    if (lane < 4 && i <= j) st.red[wave][i] = v;
+    const int i = G * m + g;
+    if (lane < G && i <= j) st.red[wave][i] = v;
   }
   n2 = wave_sum(n2);
   if (lane == 0) st.red[wave][kMaxDepth + 1] = n2;
@@ -426,7 +428,10 @@ __device__ __forceinline__ void fused_sweep(SGQ_L NodeState<T, BLOCK>& st,
     if (need <= 8) return fused_sweep_v<T, BLOCK, 8, 1, 4>(st, W, bs, wbytes, src, sbs, dst, j, n);
     if (need <= 12) return fused_sweep_v<T, BLOCK, 12, 1, 4>(st, W, bs, wbytes, src, sbs, dst, j, n);
     if (KG <= 16 || need <= 16) return fused_sweep_v<T, BLOCK, 16, 1, 4>(st, W, bs, wbytes, src, sbs, dst, j, n);
-    return fused_sweep_v<T, BLOCK, 32, 1, 2>(st, W, bs, wbytes, src, sbs, dst, j, n);
+    // deeper steps: eight lanes per point group, rows i = g (mod 8)
+    const int need8 = j / 8 + 1;
+    if (need8 <= 12) return fused_sweep_v<T, BLOCK, 12, 1, 4, 8>(st, W, bs, wbytes, src, sbs, dst, j, n);
+    return fused_sweep_v<T, BLOCK, 16, 1, 4, 8>(st, W, bs, wbytes, src, sbs, dst, j, n);
   } else {
     if (need <= 2) return fused_sweep_v<T, BLOCK, 2, 4, 2>(st, W, bs, wbytes, src, sbs, dst, j, n);
     if (need <= 4) return fused_sweep_v<T, BLOCK, 4, 2, 2>(st, W, bs, wbytes, src, sbs, dst, j, n);
