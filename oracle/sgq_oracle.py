@@ -22,7 +22,10 @@ What it computes (paper: Sec. "Density Functional Theory"):
   (Eq. eq:free_cg);
 * the exact-arithmetic adjoint of Omega with respect to the local potential,
   the projector energies and the atom positions (reverse mode through the
-  Lanczos three-term recurrence and the Daleckii-Krein derivative of F(T)).
+  Lanczos three-term recurrence and the Daleckii-Krein derivative of F(T));
+* the Fermi level: the mu at which the electron count of the stored rules,
+  N(mu) = 2 sum_q n_q sum_k w_k g(theta_k; mu) (Eq. Eqn:LSSGQ:Fermi_level:GQ with
+  the node weights of Eq. eq:free_cg), equals a given N_e.
 
 Everything is float64 and written for readability, not speed: one node at a
 time, numpy array ops for the stencil, a library tridiagonal eigensolver.
@@ -47,6 +50,7 @@ import math
 import numpy as np
 import scipy.integrate
 import scipy.linalg
+import scipy.optimize
 import scipy.sparse
 
 BAND, FREE, GRAND = 0, 1, 2
@@ -520,6 +524,35 @@ def vloc_position_gradient(dV, n, h, atoms, depth, sigma, cutoff):
         out[J, 1] = np.sum(base * dy)
         out[J, 2] = np.sum(base * dz)
     return out
+
+
+# --------------------------------------------------------------------------------------
+# Fermi level (Eq. Eqn:LSSGQ:Fermi_level:GQ, coarse-grained with the node weights of
+# Eq. eq:free_cg)
+# --------------------------------------------------------------------------------------
+def electron_count(theta, w, weight, mu, kT):
+    """N(mu) = 2 sum_q n_q sum_k w_k^q g(theta_k^q; mu) for rules theta, w [Nq, K] (padding
+    entries carry w = 0) and node weights n_q."""
+    theta = np.asarray(theta, dtype=np.float64)
+    w = np.asarray(w, dtype=np.float64)
+    occ = fermi(theta.ravel(), mu, kT).reshape(theta.shape)
+    return 2.0 * float(np.sum(np.asarray(weight, dtype=np.float64)[:, None] * w * occ))
+
+
+def fermi_level(theta, w, weight, n_electrons, kT, xtol=1e-13):
+    """The mu with N(mu) = n_electrons (N increases strictly with mu), by Brent's method on
+    a bracket that spans every node of every rule by 60 kT."""
+    theta = np.asarray(theta, dtype=np.float64)
+    w = np.asarray(w, dtype=np.float64)
+    live = w > 0
+    total = 2.0 * float(np.sum(np.asarray(weight, dtype=np.float64)[:, None] * w))
+    if not (0.0 < n_electrons < total):
+        raise ValueError("n_electrons must lie strictly between 0 and 2 sum_q n_q sum_k w_k")
+    lo = float(theta[live].min()) - 60.0 * kT
+    hi = float(theta[live].max()) + 60.0 * kT
+    f = lambda mu: electron_count(theta, w, weight, mu, kT) - n_electrons
+    return float(scipy.optimize.brentq(f, lo, hi, xtol=xtol, rtol=4.0 * np.finfo(float).eps,
+                                       maxiter=500))
 
 
 # --------------------------------------------------------------------------------------

@@ -515,3 +515,58 @@ def test_projector_centred_on_potential_well():
     assert np.argmax(chi_s) == np.argmin(P.v_loc.ravel())
     iz, iy, ix = np.unravel_index(np.argmax(chi_s), (N, N, N))
     np.testing.assert_allclose([ix * h, iy * h, iz * h], atom[0], atol=h / 2 + 1e-12)
+
+
+# ---------------------------------------------------------------- Fermi level
+def test_fermi_level_one_point_rule_closed_form():
+    """One node whose rule is a single point theta (weight 1): N(mu) = 2 n g(theta; mu), so
+    the level is mu = theta - kT ln(2n/N_e - 1)."""
+    theta, n, kT = 0.3, 2.5, 0.02
+    for ne in (0.2, 1.7, 4.6):
+        mu = O.fermi_level(np.array([[theta]]), np.array([[1.0]]), np.array([n]), ne, kT)
+        assert abs(mu - (theta - kT * np.log(2.0 * n / ne - 1.0))) < 1e-12
+
+
+def test_fermi_level_half_filling_of_symmetric_rules():
+    """Rules symmetric about c (points c +- d with equal weights) are half filled at mu = c,
+    because g(c + d) + g(c - d) = 1; at N_e = sum_q n_q the level is c."""
+    rng = np.random.default_rng(3)
+    c, kT = -0.37, 0.015
+    d = rng.uniform(0.001, 0.5, size=(7, 5))
+    wv = rng.uniform(0.1, 1.0, size=(7, 5))
+    wv /= 2.0 * wv.sum(axis=1, keepdims=True)
+    theta = np.concatenate([c + d, c - d], axis=1)
+    w = np.concatenate([wv, wv], axis=1)
+    n = rng.uniform(0.5, 3.0, size=7)
+    mu = O.fermi_level(theta, w, n, float(n.sum()), kT)
+    assert abs(mu - c) < 1e-12
+
+
+def test_electron_count_limits_and_monotonicity():
+    rng = np.random.default_rng(4)
+    theta = rng.uniform(-1, 3, size=(5, 6))
+    w = rng.uniform(0, 1, size=(5, 6))
+    w /= w.sum(axis=1, keepdims=True)
+    n = rng.uniform(0.5, 2.0, size=5)
+    total = 2.0 * n.sum()
+    assert O.electron_count(theta, w, n, -50.0, 0.01) < 1e-300 + 1e-12
+    assert abs(O.electron_count(theta, w, n, 50.0, 0.01) - total) < 1e-12 * total
+    grid = np.linspace(-1.5, 3.5, 201)
+    counts = [O.electron_count(theta, w, n, m, 0.05) for m in grid]
+    assert np.all(np.diff(counts) > 0)
+
+
+def test_fermi_level_recovers_the_density_level():
+    """sum_q n_q h^3 rho_q(mu0) counts the electrons at mu0 (Eq. Eqn:LSSGQ:Electron_density:GQ
+    against Eq. Eqn:LSSGQ:Fermi_level:GQ), so the level of that count is mu0 again."""
+    P = synth.make_problem(2).subset(np.arange(6))
+    rules = [O.node_rule(P, q) for q in range(P.n_nodes)]
+    K = max(r[2] for r in rules)
+    theta = np.zeros((P.n_nodes, K))
+    w = np.zeros((P.n_nodes, K))
+    for q, (t, ww, k) in enumerate(rules):
+        theta[q, :k], w[q, :k] = t, ww
+    rho, _ = O.rho_quadrature(P)
+    ne = float(np.sum(P.weight * rho) * P.h ** 3)
+    mu = O.fermi_level(theta, w, P.weight, ne, P.kT)
+    assert abs(mu - P.mu) < 1e-9
