@@ -205,6 +205,27 @@ def main():
                      "kernel": f"lanczos_forward_kernel<float,{lanes},16>",
                      "alg_bytes_per_launch": bytes_launch, "avg_launch_ms": t_launch * 1e3},
     }
+    # Fermi level from the stored Gauss rules (no new Lanczos run): the count of the
+    # density at mu = -0.1 is solved for its level again
+    tw = torch.zeros(P.n_nodes * plan.kmax * 2, dtype=torch.float64, device="cuda")
+    rho_f = torch.empty_like(rho)
+    sgq.rho_quadrature(plan, v, R, E, P.mu, P.kT, rho_f, tw, stream=stream.cuda_stream)
+    stream.synchronize()
+    wq = torch.as_tensor(P.weight, dtype=torch.float64, device="cuda")
+    n_el = float((rho_f * wq).sum().item()) * P.h ** 3
+    fres = torch.empty(3, dtype=torch.float64, device="cuda")
+    sgq.fermi_level(plan, tw, wq, n_el, P.kT, fres, stream=stream.cuda_stream)   # warm-up
+    f0 = torch.cuda.Event(enable_timing=True)
+    f1 = torch.cuda.Event(enable_timing=True)
+    f0.record(stream)
+    sgq.fermi_level(plan, tw, wq, n_el, P.kT, fres, stream=stream.cuda_stream)
+    f1.record(stream)
+    stream.synchronize()
+    assert plan.status() == sgq.SGQ_OK
+    fr = fres.cpu().numpy()
+    rec["fermi_level"] = {"n_electrons": n_el, "mu": float(fr[0]), "mu_of_the_count": P.mu,
+                          "steps": int(fr[2]), "ms": f0.elapsed_time(f1),
+                          "rule_points": int(P.n_nodes * plan.kmax)}
     if not args.no_plain:
         # per-node GPU baseline: the plain schedule on a seeded node sample
         idx = np.random.default_rng(7).choice(P.n_nodes, args.plain_nodes, replace=False)

@@ -50,7 +50,8 @@ typedef enum {
   SGQ_EHIP = -3,        /* a HIP runtime call failed */
   SGQ_EPLAN = -4,       /* the call does not match the plan (e.g. no projectors planned) */
   SGQ_ENONFINITE = -5,  /* device status: NaN/Inf in an input */
-  SGQ_ELIMIT = -6       /* device status: a node overlaps more atoms than supported */
+  SGQ_ELIMIT = -6,      /* device status: a node overlaps more atoms than supported */
+  SGQ_ERANGE = -7       /* device status: no Fermi level for the requested electron count */
 } sgq_status;
 
 enum { SGQ_FP64 = 0, SGQ_FP32 = 1 };           /* storage / matvec precision */
@@ -140,6 +141,24 @@ int sgq_vloc_gaussian_backward(sgq_plan* plan, const double* dV, const double* a
  *                        per-node GPU baseline.  Same precision and depth; theta_w must be
  *                        NULL.  Returns SGQ_EINVAL for an unknown schedule. */
 int sgq_plan_set_schedule(sgq_plan* plan, int schedule);
+
+/* Fermi level of stored Gauss rules (Eq. Eqn:LSSGQ:Fermi_level:GQ, with the node weights
+ * of Eq. eq:free_cg): the mu at which the electron count
+ *   N(mu) = 2 sum_q n_q sum_k w_k g(lambda_k; mu),  g = 1/(1 + exp((lambda - mu)/kT)),
+ * equals n_electrons.  The rules are mu- and kT-independent, so this needs no new Lanczos
+ * run: theta_w is the rule output of rho_quadrature on this plan.
+ *   theta_w     [Nq*Kmax*2] double  device: (lambda_k, w_k) per node; entries with w_k = 0
+ *                                   (beyond K_eff) are ignored
+ *   node_weight [Nq]        double  device: n_q
+ *   n_electrons, kT                 > 0; tol > 0: stop when |N(mu) - n_electrons| <=
+ *                                   tol * n_electrons
+ *   result      [3]         double  device out: mu, N(mu), number of Newton/bisection steps
+ * Safeguarded Newton iteration on a bracket spanning every rule point by 60 kT, in one
+ * workgroup with a fixed summation order (bitwise reproducible).  An electron count
+ * outside (0, 2 sum_q n_q sum_k w_k) latches SGQ_ERANGE (result = NaN), a non-finite rule
+ * SGQ_ENONFINITE; both are read with sgq_plan_status.  Asynchronous on `stream`. */
+int sgq_fermi_level(sgq_plan* plan, const double* theta_w, const double* node_weight,
+                    double n_electrons, double kT, double tol, double* result, void* stream);
 
 /* Launch capture.  With enable != 0 (the default), rho_quadrature and band_energy on a
  * stream other than the legacy default stream capture their launch sequence (setup

@@ -210,6 +210,125 @@ __global__ void weighted_sum_kernel(const double* __restrict__ e, const double* 
   if (threadIdx.x == 0) *out = red[0];
 }
 
+// Fermi level of stored Gauss rules (one workgroup): the mu at which
+//   N(mu) = 2 sum_q n_q sum_k w_k g(theta_k; mu)
+// equals ne.  N increases strictly with mu; a first pass brackets the level by every
+// rule point -+ 60 kT, then safeguarded Newton steps (dN/dmu = 2 sum n w g (1 - g) / kT;
+// a step that leaves the bracket is replaced by bisection) run until |N - ne| <= tol ne.
+// Every sum is taken in a fixed order, so the result is reproducible bit for bit.  Points
+// more than 36 kT from mu count as fully occupied or empty (g differs from 0 or 1 by less
+// than 2.4e-16 there), so only the points near the level evaluate an exponential.
+// out[0] = mu, out[1] = N(mu), out[2] = Newton / bisection steps.
+__global__ __launch_bounds__(1024) void fermi_level_kernel(const double* __restrict__ tw,
+                                                           const double* __restrict__ weight,
+                                                           int nq, int kmax, double ne,
+                                                           double kT, double tol, double* out,
+                                                           int* status) {
+  constexpr int NW = 1024 / kWave;
+  __shared__ double red[3][NW];
+  __shared__ double bcast[3];
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+  const unsigned ntot = (unsigned)nq * (unsigned)kmax;   // < 2^31 (checked by the host)
+  if (tid == 0) *status = 0;   // this call's latch (written again only by thread 0 below)
+  // pass 0: bracket and total count
+  double lo = __builtin_inf(), hi = -__builtin_inf(), tot = 0.0;
+  int bad = 0;
+  for (unsigned e = tid; e < ntot; e += 1024) {
+    const double th = tw[2 * e], w = tw[2 * e + 1], n = weight[e / (unsigned)kmax];
+    if (!isfinite(th) || !isfinite(w) || !isfinite(n)) bad = 1;
+    if (w > 0.0) {
+      lo = fmin(lo, th);
+      hi = fmax(hi, th);
+      tot += n * w;
+    }
+  }
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) {
+    lo = fmin(lo, __shfl_xor(lo, off, kWave));
+    hi = fmax(hi, __shfl_xor(hi, off, kWave));
+  }
+  tot = wave_sum(tot);
+  bad = __any(bad);
+  if (lane == 0) {
+    red[0][wave] = lo;
+    red[1][wave] = hi;
+    red[2][wave] = tot + (bad ? __builtin_nan("") : 0.0);
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double l = red[0][0], h = red[1][0], t = red[2][0];
+    for (int w = 1; w < NW; ++w) {
+      l = fmin(l, red[0][w]);
+      h = fmax(h, red[1][w]);
+      t += red[2][w];
+    }
+    bcast[0] = l;
+    bcast[1] = h;
+    bcast[2] = 2.0 * t;
+  }
+  __syncthreads();
+  lo = bcast[0] - 60.0 * kT;
+  hi = bcast[1] + 60.0 * kT;
+  const double total = bcast[2];
+  if (!(isfinite(total) && ne > 0.0 && ne < total)) {
+    if (tid == 0) {
+      atomicOr(status, isfinite(total) ? kStatusRange : kStatusNonFinite);
+      out[0] = out[1] = __builtin_nan("");
+      out[2] = 0.0;
+    }
+    return;
+  }
+  double mu = 0.5 * (lo + hi), N = 0.0;
+  int it = 0;
+  for (;; ++it) {
+    double s = 0.0, d = 0.0;
+    for (unsigned e = tid; e < ntot; e += 1024) {
+      const double w = tw[2 * e + 1];
+      if (w > 0.0) {
+        const double x = (tw[2 * e] - mu) / kT;
+        const double nw = weight[e / (unsigned)kmax] * w;
+        if (x < -36.0) {
+          s += nw;
+        } else if (x <= 36.0) {
+          const double g = fermi_occ(x);
+          s += nw * g;
+          d += nw * g * (1.0 - g);
+        }
+      }
+    }
+    s = wave_sum(s);
+    d = wave_sum(d);
+    __syncthreads();   // red[] of the previous round has been read
+    if (lane == 0) {
+      red[0][wave] = s;
+      red[1][wave] = d;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double S = 0.0, Dd = 0.0;
+      for (int w = 0; w < NW; ++w) {
+        S += red[0][w];
+        Dd += red[1][w];
+      }
+      bcast[0] = 2.0 * S;
+      bcast[1] = 2.0 * Dd / kT;
+    }
+    __syncthreads();
+    N = bcast[0];
+    const double dN = bcast[1], f = N - ne;
+    if (fabs(f) <= tol * ne || it >= 299) break;
+    if (f < 0.0) lo = mu; else hi = mu;
+    if (hi - lo <= 4.0 * 2.220446049250313e-16 * fmax(1.0, fabs(mu))) break;
+    const double cand = mu - f / dN;
+    mu = (dN > 0.0 && cand > lo && cand < hi) ? cand : 0.5 * (lo + hi);
+  }
+  if (tid == 0) {
+    out[0] = mu;
+    out[1] = N;
+    out[2] = (double)(it + 1);
+  }
+}
+
 // ------------------------------------------------------------------ host launchers
 template <typename T, int BLOCK>
 static hipError_t launch_forward_t(const LaunchParams& P, int grid, int kg, hipStream_t s) {
@@ -265,6 +384,14 @@ hipError_t launch_gauss_rule(const LaunchParams& P, hipStream_t s) {
   const int nt = P.kmax_out <= 40 ? 64 : (P.kmax_out <= 80 ? 32 : 16);
   const size_t lds = (size_t)3 * P.kmax_out * nt * sizeof(double);
   hipLaunchKernelGGL(gauss_rule_kernel, dim3((P.n_nodes + nt - 1) / nt), dim3(nt), lds, s, P);
+  return hipGetLastError();
+}
+
+hipError_t launch_fermi_level(const double* tw, const double* weight, int nq, int kmax,
+                              double ne, double kT, double tol, double* out, int* status,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(fermi_level_kernel, dim3(1), dim3(1024), 0, s, tw, weight, nq, kmax, ne, kT,
+                     tol, out, status);
   return hipGetLastError();
 }
 

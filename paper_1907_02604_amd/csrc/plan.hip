@@ -22,6 +22,9 @@ hipError_t launch_setup(const LaunchParams& P, bool fp64, const double* v64, voi
 hipError_t launch_weighted_sum(const double* e, const double* w, int n, double* out,
                                hipStream_t s);
 hipError_t launch_gauss_rule(const LaunchParams& P, hipStream_t s);
+hipError_t launch_fermi_level(const double* tw, const double* weight, int nq, int kmax,
+                              double ne, double kT, double tol, double* out, int* status,
+                              hipStream_t s);
 hipError_t launch_backward(const LaunchParams& P, bool fp64, int grid, int block, int kg,
                            hipStream_t s);
 hipError_t launch_backward_gather(const LaunchParams& P, bool fp64, const int32_t* cell_start,
@@ -444,6 +447,26 @@ extern "C" int sgq_plan_set_schedule(sgq_plan* plan, int schedule) {
   return SGQ_OK;
 }
 
+extern "C" int sgq_fermi_level(sgq_plan* plan, const double* theta_w, const double* node_weight,
+                               double n_electrons, double kT, double tol, double* result,
+                               void* stream) {
+  if (!plan) return fail(SGQ_EINVAL, "plan is null");
+  if (plan->prob.n_nodes < 1) return fail(SGQ_EINVAL, "the plan has no nodes");
+  if (!theta_w || !node_weight || !result) return fail(SGQ_EINVAL, "null argument");
+  if (!(kT > 0.0) || !std::isfinite(kT)) return fail(SGQ_EINVAL, "kT must be finite and > 0");
+  if (!(n_electrons > 0.0) || !std::isfinite(n_electrons))
+    return fail(SGQ_EINVAL, "n_electrons must be finite and > 0");
+  if (!(tol > 0.0) || !std::isfinite(tol)) return fail(SGQ_EINVAL, "tol must be finite and > 0");
+  if ((size_t)plan->prob.n_nodes * plan->kmax >= ((size_t)1 << 31))
+    return fail(SGQ_EINVAL, "too many rule points for the Fermi-level kernel");
+  hipStream_t s = (hipStream_t)stream;
+  HIP_OR_FAIL(hipSetDevice(plan->device));
+  HIP_OR_FAIL(launch_fermi_level(theta_w, node_weight, plan->prob.n_nodes, plan->kmax, n_electrons,
+                                 kT, tol, result, plan->d_status, s));
+  plan->last = s;
+  return SGQ_OK;
+}
+
 extern "C" int sgq_plan_set_graph(sgq_plan* plan, int enable) {
   if (!plan) return fail(SGQ_EINVAL, "plan is null");
   plan->use_graph = enable != 0;
@@ -774,6 +797,7 @@ extern "C" int sgq_plan_status(sgq_plan* plan, int32_t* host_status) {
   HIP_OR_FAIL(hipMemcpy(&bits, plan->d_status, 4, hipMemcpyDeviceToHost));
   *host_status = (bits & kStatusNonFinite) ? SGQ_ENONFINITE
                  : (bits & kStatusLimit)   ? SGQ_ELIMIT
+                 : (bits & kStatusRange)   ? SGQ_ERANGE
                                            : SGQ_OK;
   return SGQ_OK;
 }

@@ -15,6 +15,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("SGQ_LIBRARY") or os.path.join(_HERE, "libsgq.so")
 
 SGQ_OK, SGQ_EINVAL, SGQ_ENOMEM, SGQ_EHIP, SGQ_EPLAN, SGQ_ENONFINITE, SGQ_ELIMIT = 0, -1, -2, -3, -4, -5, -6
+SGQ_ERANGE = -7
 SGQ_FP64, SGQ_FP32 = 0, 1
 SGQ_BAND, SGQ_FREE, SGQ_GRAND = 0, 1, 2
 SGQ_SCHEDULE_BATCHED, SGQ_SCHEDULE_PLAIN = 0, 1
@@ -22,7 +23,7 @@ SGQ_SCHEDULE_BATCHED, SGQ_SCHEDULE_PLAIN = 0, 1
 EXPORTED = ("sgq_plan_create", "sgq_plan_destroy", "rho_quadrature", "band_energy",
             "band_energy_backward", "sgq_vloc_gaussian_backward", "sgq_plan_status",
             "sgq_last_error", "sgq_validate", "sgq_gauss_rule_host", "sgq_plan_set_schedule",
-            "sgq_plan_set_graph", "sgq_plan_autotune")
+            "sgq_plan_set_graph", "sgq_plan_autotune", "sgq_fermi_level")
 
 
 class SgqError(RuntimeError):
@@ -56,6 +57,7 @@ def _load():
         "sgq_gauss_rule_host": (I, [P, P, I, P, P]),
         "sgq_plan_set_schedule": (I, [P, I]),
         "sgq_plan_set_graph": (I, [P, I]),
+        "sgq_fermi_level": (I, [P, P, P, D, D, D, P, P]),
         "sgq_plan_autotune": (I, [P, P, P, P, D, D, I, P, ctypes.POINTER(ctypes.c_int32)]),
     }
     for name, (res, args) in sig.items():
@@ -213,6 +215,13 @@ def band_energy_backward(plan, v_loc, atom_R, proj_E, node_weight, mu, kT, integ
                                      _ptr(node_weight), float(mu), float(kT), int(integrand),
                                      _ptr(grad_omega), _ptr(dV), _ptr(dR_nl), _ptr(dE),
                                      _stream(stream)))
+
+
+def fermi_level(plan, theta_w, node_weight, n_electrons, kT, result, tol=1e-12, stream=None):
+    """sgq_fermi_level: result (device, 3 doubles) <- mu, N(mu), steps."""
+    _check(_lib.sgq_fermi_level(plan.handle, _ptr(theta_w), _ptr(node_weight),
+                                float(n_electrons), float(kT), float(tol), _ptr(result),
+                                _stream(stream)))
 
 
 def vloc_gaussian_backward(plan, dV, atom_R, depth, sigma, cutoff_sigmas, dR, stream=None):

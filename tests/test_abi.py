@@ -86,3 +86,10 @@ def test_host_gauss_rule_rejects_bad_sizes(sgq):
         sgq.gauss_rule_host(np.zeros(0), np.zeros(0))
     with pytest.raises(sgq.SgqError):
         sgq.gauss_rule_host(np.zeros(129), np.ones(128))
+
+
+def test_fermi_level_rejects_bad_arguments_on_the_host():
+    """Argument errors are returned before anything is launched (no plan needed)."""
+    from paper_1907_02604_amd import sgq
+    lib = sgq.lib()
+    assert lib.sgq_fermi_level(None, None, None, 1.0, 0.01, 1e-12, None, None) == sgq.SGQ_EINVAL
