@@ -25,7 +25,9 @@ What it computes (paper: Sec. "Density Functional Theory"):
   Lanczos three-term recurrence and the Daleckii-Krein derivative of F(T));
 * the Fermi level: the mu at which the electron count of the stored rules,
   N(mu) = 2 sum_q n_q sum_k w_k g(theta_k; mu) (Eq. Eqn:LSSGQ:Fermi_level:GQ with
-  the node weights of Eq. eq:free_cg), equals a given N_e.
+  the node weights of Eq. eq:free_cg), equals a given N_e;
+* the cluster-sampled energy E = sum_q n_q Fbar_q, Fbar_q the mean per-point energy
+  over the grid points within a radius of ESP q (Eq. eq:free_cg_sampling).
 
 Everything is float64 and written for readability, not speed: one node at a
 time, numpy array ops for the stencil, a library tridiagonal eigensolver.
@@ -553,6 +555,43 @@ def fermi_level(theta, w, weight, n_electrons, kT, xtol=1e-13):
     f = lambda mu: electron_count(theta, w, weight, mu, kT) - n_electrons
     return float(scipy.optimize.brentq(f, lo, hi, xtol=xtol, rtol=4.0 * np.finfo(float).eps,
                                        maxiter=500))
+
+
+# --------------------------------------------------------------------------------------
+# Cluster-sampled energy (Eq. eq:free_cg with the cluster averages of
+# Eq. eq:free_cg_sampling)
+# --------------------------------------------------------------------------------------
+def cluster_members(n, h, center, radius):
+    """Grid points (linear indices, ascending) within distance `radius` of grid point
+    `center` on the periodic grid n (minimum-image distance), by brute force.  The
+    squared distance in grid units is an integer; it is compared with (radius/h)^2
+    widened by a relative 1e-9, so a radius equal to a lattice distance takes in that
+    shell whatever the rounding of radius itself."""
+    nx, ny, nz = n
+    lim = (radius / h) ** 2 * (1.0 + 1e-9)
+    cx, cy, cz = center % nx, (center // nx) % ny, center // (nx * ny)
+    out = []
+    for iz in range(nz):
+        dz = min(abs(iz - cz), nz - abs(iz - cz))
+        for iy in range(ny):
+            dy = min(abs(iy - cy), ny - abs(iy - cy))
+            for ix in range(nx):
+                dx = min(abs(ix - cx), nx - abs(ix - cx))
+                if dx * dx + dy * dy + dz * dz <= lim:
+                    out.append(ix + nx * (iy + ny * iz))
+    return np.array(sorted(out), dtype=np.int64)
+
+
+def cluster_energy(e_of_point, n, h, esp_centers, esp_weights, radius):
+    """E = sum_q n_q Fbar_q with Fbar_q the mean of the per-point energies e_p over the
+    cluster of grid points within `radius` of ESP q.  e_of_point maps a grid index to e_p.
+    Returns (E, Fbar)."""
+    fbar = []
+    for c in esp_centers:
+        members = cluster_members(n, h, int(c), radius)
+        fbar.append(float(np.mean([e_of_point(int(p)) for p in members])))
+    fbar = np.array(fbar)
+    return float(np.sum(np.asarray(esp_weights, dtype=np.float64) * fbar)), fbar
 
 
 # --------------------------------------------------------------------------------------

@@ -570,3 +570,34 @@ def test_fermi_level_recovers_the_density_level():
     ne = float(np.sum(P.weight * rho) * P.h ** 3)
     mu = O.fermi_level(theta, w, P.weight, ne, P.kT)
     assert abs(mu - P.mu) < 1e-9
+
+
+# ---------------------------------------------------------------- cluster sampling
+def test_cluster_members_count_lattice_points_in_balls():
+    """Lattice points with i^2 + j^2 + k^2 <= R^2: 1, 7, 19, 27, 33, 57, 81, 93 for
+    R^2 = 0..7 (sums of three squares), on a grid wide enough for no periodic wrap."""
+    counts = {0: 1, 1: 7, 2: 19, 3: 27, 4: 33, 5: 57, 6: 81, 7: 81}
+    for r2, cnt in counts.items():
+        m = O.cluster_members((12, 12, 12), 0.5, lin(5, 6, 7, 12), 0.5 * math.sqrt(r2))
+        assert m.size == cnt
+
+
+def test_cluster_members_wrap_periodically():
+    """A ball at a corner holds the same number of points as one in the middle."""
+    a = O.cluster_members((10, 10, 10), 0.5, 0, 1.0)
+    b = O.cluster_members((10, 10, 10), 0.5, lin(5, 5, 5, 10), 1.0)
+    assert a.size == b.size == 33
+    assert lin(9, 0, 0, 10) in set(a.tolist()) and lin(0, 0, 8, 10) in set(a.tolist())
+
+
+def test_cluster_energy_reduces_to_point_sampling():
+    """Radius below h: every cluster is its ESP alone and E = sum_q n_q e_q (Eq.
+    eq:free_cg); a constant per-point energy averages to itself for any radius."""
+    e = lambda p: 0.01 * (p % 17) - 0.05
+    centers = [3, 100, 777]
+    w = [1.0, 32.0, 5.5]
+    E, fbar = O.cluster_energy(e, (12, 12, 12), 0.5, centers, w, 0.4)
+    assert np.allclose(fbar, [e(c) for c in centers])
+    assert abs(E - sum(wi * e(c) for wi, c in zip(w, centers))) < 1e-15
+    E2, fbar2 = O.cluster_energy(lambda p: 0.25, (12, 12, 12), 0.5, centers, w, 1.3)
+    assert np.allclose(fbar2, 0.25) and abs(E2 - 0.25 * sum(w)) < 1e-14
