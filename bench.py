@@ -118,6 +118,8 @@ def main():
     ap.add_argument("--dislocation-nodes", type=int, default=8192,
                     help="nodes of the dislocation-shaped sample (128^3 screw lattice, K=80): "
                          "forward and adjoint; 0 skips it")
+    ap.add_argument("--cluster-esps", type=int, default=256,
+                    help="energy sampling points of the cluster-energy leg (0 skips it)")
     ap.add_argument("--no-uneven", action="store_true",
                     help="skip the uneven-batching measurement (96^3, 20000 nodes, R and K drawn)")
     ap.add_argument("--tune-nodes", type=int, default=2048,
@@ -226,6 +228,50 @@ def main():
     rec["fermi_level"] = {"n_electrons": n_el, "mu": float(fr[0]), "mu_of_the_count": P.mu,
                           "steps": int(fr[2]), "ms": f0.elapsed_time(f1),
                           "rule_points": int(P.n_nodes * plan.kmax)}
+    if args.cluster_esps > 0:
+        # cluster-sampled energy: balls of radius 1 bohr (33 grid points) around C2 nodes
+        # taken as energy sampling points; the band energy of the merged ball nodes, then
+        # the per-cluster means and the weighted total
+        Pc, cl = sgq.cluster_problem(P, np.arange(args.cluster_esps), 1.0)
+        cplan = sgq.Plan.from_problem(Pc)
+        cplan.set_graph(True)
+        cplan.autotune(v, R, E, Pc.mu, Pc.kT, sample_nodes=args.tune_nodes, stream=stream.cuda_stream)
+        wn = torch.as_tensor(Pc.weight, device="cuda")
+        ec = torch.empty(Pc.n_nodes, dtype=torch.float64, device="cuda")
+        omc = torch.empty(1, dtype=torch.float64, device="cuda")
+        off = torch.as_tensor(cl["member_offset"], device="cuda")
+        mem = torch.as_tensor(cl["member_node"], device="cuda")
+        we = torch.as_tensor(cl["esp_weight"], device="cuda")
+        fbar = torch.empty(args.cluster_esps, dtype=torch.float64, device="cuda")
+        en = torch.empty(1, dtype=torch.float64, device="cuda")
+
+        def cluster_pass():
+            sgq.band_energy(cplan, v, R, E, wn, Pc.mu, Pc.kT, sgq.SGQ_FREE, ec, omc,
+                            stream=stream.cuda_stream)
+            sgq.cluster_energy(cplan, ec, off, mem, we, fbar, en, stream=stream.cuda_stream)
+
+        cluster_pass()                                   # warm-up (and graph capture)
+        stream.synchronize()
+        c0 = torch.cuda.Event(enable_timing=True)
+        c1 = torch.cuda.Event(enable_timing=True)
+        c2 = torch.cuda.Event(enable_timing=True)
+        c0.record(stream)
+        cluster_pass()
+        c1.record(stream)
+        sgq.cluster_energy(cplan, ec, off, mem, we, fbar, en, stream=stream.cuda_stream)
+        c2.record(stream)
+        stream.synchronize()
+        assert cplan.status() == sgq.SGQ_OK
+        tc = c0.elapsed_time(c1) * 1e-3
+        rec["cluster_energy"] = {
+            "workload": f"{args.cluster_esps} ESPs of the 64^3 system, balls of radius 1 bohr "
+                        f"(33 points), {Pc.n_nodes} merged nodes, 33^3 cubes, K=60, FP32",
+            "value": args.cluster_esps / tc, "unit": "ESPs/s", "nodes_per_s": Pc.n_nodes / tc,
+            "pass_ms": tc * 1e3, "segmented_mean_ms": c1.elapsed_time(c2),
+            "energy": en.item(), "omega_with_cluster_weights": omc.item()}
+        print(f"[bench] cluster energy {args.cluster_esps / tc:.1f} ESPs/s "
+              f"({Pc.n_nodes / tc:.1f} nodes/s)", file=sys.stderr, flush=True)
+        cplan.close()
     if not args.no_plain:
         # per-node GPU baseline: the plain schedule on a seeded node sample
         idx = np.random.default_rng(7).choice(P.n_nodes, args.plain_nodes, replace=False)

@@ -24,7 +24,8 @@
  *   - Grid arrays are [z][y][x] with x fastest: linear index ix + nx*(iy + ny*iz).
  *   - Every array argument of a compute call is a DEVICE pointer owned by the caller,
  *     contiguous, of the stated type and length.  Host arrays are passed only to
- *     sgq_plan_create.
+ *     sgq_plan_create and the host-only helpers (sgq_cluster_build, sgq_validate,
+ *     sgq_gauss_rule_host).
  *   - Compute calls are asynchronous on `stream` (a hipStream_t; NULL = default
  *     stream).  Inputs must stay valid until the stream reaches the call.
  *   - Every function returns an sgq_status and never throws.  Argument errors found
@@ -51,7 +52,8 @@ typedef enum {
   SGQ_EPLAN = -4,       /* the call does not match the plan (e.g. no projectors planned) */
   SGQ_ENONFINITE = -5,  /* device status: NaN/Inf in an input */
   SGQ_ELIMIT = -6,      /* device status: a node overlaps more atoms than supported */
-  SGQ_ERANGE = -7       /* device status: no Fermi level for the requested electron count */
+  SGQ_ERANGE = -7,      /* device status: no Fermi level for the requested electron count */
+  SGQ_EINDEX = -8       /* device status: a cluster list entry outside the plan's nodes */
 } sgq_status;
 
 enum { SGQ_FP64 = 0, SGQ_FP32 = 1 };           /* storage / matvec precision */
@@ -160,6 +162,55 @@ int sgq_plan_set_schedule(sgq_plan* plan, int schedule);
 int sgq_fermi_level(sgq_plan* plan, const double* theta_w, const double* node_weight,
                     double n_electrons, double kT, double tol, double* result, void* stream);
 
+/* Clusters of the energy sampling (Eq. eq:free_cg_sampling), host only.  C_q is the set
+ * of grid points within distance `radius` (bohr) of energy sampling point (ESP) q on the
+ * periodic grid (minimum-image distance; a point is inside when its squared distance in
+ * grid units is <= (radius/h)^2 (1 + 1e-9), so a radius equal to a lattice distance keeps
+ * that shell).  The clusters are merged into one ascending node list, so a point shared by
+ * several clusters is evaluated once; build a plan on that list and feed its band_energy
+ * e_node to sgq_cluster_energy.  All arrays are HOST arrays.
+ *   n [3], h              grid extents and spacing, as in sgq_problem
+ *   esp_center [n_esp]    int64  linear grid index of each ESP
+ *   radius                >= 0
+ *   esp_weight [n_esp]    double optional: n_q, needed only for node_weight
+ *   node_capacity, member_capacity   lengths of the output arrays below
+ *   node_center [Nn]      int64  out (optional): ascending linear indices of the merged nodes
+ *   node_esp [Nn]         int32  out (optional): lowest ESP whose cluster holds the node
+ *   node_weight [Nn]      double out (optional): sum over clusters q holding the node of
+ *                         n_q / |C_q|, so that sum_p node_weight_p e_p = sum_q n_q Fbar_q
+ *                         and band_energy / band_energy_backward with these weights give
+ *                         the cluster-sampled energy and its gradient
+ *   member_offset [n_esp+1] int64 out (optional): CSR offsets of the clusters
+ *   member_node [Nm]      int32  out (optional): position in node_center of each member,
+ *                         ascending within a cluster
+ *   n_nodes, n_members    int64  out (required): Nn and Nm
+ * Call once with the optional outputs NULL to get the counts.  A capacity below the
+ * count returns SGQ_EINVAL (the counts are still written).  Every cluster holds its ESP,
+ * so no cluster is empty. */
+int sgq_cluster_build(const int32_t n[3], double h, const int64_t* esp_center, int32_t n_esp,
+                      double radius, const double* esp_weight, int64_t node_capacity,
+                      int64_t member_capacity, int64_t* node_center, int32_t* node_esp,
+                      double* node_weight, int64_t* member_offset, int32_t* member_node,
+                      int64_t* n_nodes, int64_t* n_members);
+
+/* Cluster-sampled energy (Eq. eq:free_cg with the cluster averages of Eq.
+ * eq:free_cg_sampling): Fbar_q = (1/|C_q|) sum_{p in C_q} e_p and
+ * energy = sum_q n_q Fbar_q.  Device arrays:
+ *   e_node [Nq]            double  per-node energies of this plan (band_energy output)
+ *   member_offset [n_esp+1] int64, member_node [n_members] int32: clusters as written
+ *                          by sgq_cluster_build (positions in the plan's node list)
+ *   esp_weight [n_esp]     double  n_q (optional, NULL only together with energy)
+ *   fbar [n_esp]           double  out
+ *   energy [1]             double  out (optional)
+ * One wavefront per cluster and a one-workgroup weighted sum, both in a fixed order
+ * (bitwise reproducible).  An empty cluster, offsets that decrease or pass n_members, or
+ * a member outside [0, Nq) latches SGQ_EINDEX (that cluster's fbar = NaN); a non-finite
+ * energy
+ * SGQ_ENONFINITE; both are read with sgq_plan_status.  Asynchronous on `stream`. */
+int sgq_cluster_energy(sgq_plan* plan, const double* e_node, const int64_t* member_offset,
+                       const int32_t* member_node, int64_t n_members, int32_t n_esp,
+                       const double* esp_weight, double* fbar, double* energy, void* stream);
+
 /* Launch capture.  With enable != 0 (the default), rho_quadrature and band_energy on a
  * stream other than the legacy default stream capture their launch sequence (setup
  * kernels, the persistent Lanczos-Gauss kernel, the weighted sum) into a HIP graph on the
@@ -183,7 +234,8 @@ int sgq_plan_autotune(sgq_plan* plan, const double* v_loc, const double* atom_R,
                       void* stream, int32_t* chosen);
 
 /* Wait for the plan's last call and report a latched device-side error (SGQ_OK,
- * SGQ_ENONFINITE or SGQ_ELIMIT); the latch is cleared by the next compute call. */
+ * SGQ_ENONFINITE, SGQ_ELIMIT, SGQ_ERANGE or SGQ_EINDEX); the latch is cleared by the
+ * next compute call. */
 int sgq_plan_status(sgq_plan* plan, int32_t* host_status);
 
 /* Message of the last error raised on the calling thread ("" if none). */

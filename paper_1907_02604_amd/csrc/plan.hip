@@ -22,6 +22,10 @@ hipError_t launch_setup(const LaunchParams& P, bool fp64, const double* v64, voi
 hipError_t launch_weighted_sum(const double* e, const double* w, int n, double* out,
                                hipStream_t s);
 hipError_t launch_gauss_rule(const LaunchParams& P, hipStream_t s);
+hipError_t launch_cluster_energy(const double* e_node, int nq, const int64_t* offset,
+                                 const int32_t* member, int64_t n_members, int n_esp,
+                                 const double* esp_weight, double* fbar, double* energy,
+                                 int* status, hipStream_t s);
 hipError_t launch_fermi_level(const double* tw, const double* weight, int nq, int kmax,
                               double ne, double kT, double tol, double* out, int* status,
                               hipStream_t s);
@@ -49,6 +53,11 @@ static int fail(int code, const std::string& msg) {
   g_error = msg;
   return code;
 }
+
+namespace sgq {
+// Error reporting for entry points defined in other sources of the library.
+int report_error(int code, const std::string& msg) { return fail(code, msg); }
+}  // namespace sgq
 
 #define HIP_OR_FAIL(expr)                                                             \
   do {                                                                                \
@@ -467,6 +476,25 @@ extern "C" int sgq_fermi_level(sgq_plan* plan, const double* theta_w, const doub
   return SGQ_OK;
 }
 
+extern "C" int sgq_cluster_energy(sgq_plan* plan, const double* e_node,
+                                  const int64_t* member_offset, const int32_t* member_node,
+                                  int64_t n_members, int32_t n_esp, const double* esp_weight,
+                                  double* fbar, double* energy, void* stream) {
+  if (!plan) return fail(SGQ_EINVAL, "plan is null");
+  if (plan->prob.n_nodes < 1) return fail(SGQ_EINVAL, "the plan has no nodes");
+  if (n_esp < 1) return fail(SGQ_EINVAL, "n_esp must be >= 1");
+  if (n_members < 1) return fail(SGQ_EINVAL, "n_members must be >= 1");
+  if (!e_node || !member_offset || !member_node || !fbar) return fail(SGQ_EINVAL, "null argument");
+  if (!energy != !esp_weight) return fail(SGQ_EINVAL, "energy and esp_weight go together");
+  hipStream_t s = (hipStream_t)stream;
+  HIP_OR_FAIL(hipSetDevice(plan->device));
+  HIP_OR_FAIL(launch_cluster_energy(e_node, plan->prob.n_nodes, member_offset, member_node,
+                                    n_members, n_esp, esp_weight, fbar, energy, plan->d_status,
+                                    s));
+  plan->last = s;
+  return SGQ_OK;
+}
+
 extern "C" int sgq_plan_set_graph(sgq_plan* plan, int enable) {
   if (!plan) return fail(SGQ_EINVAL, "plan is null");
   plan->use_graph = enable != 0;
@@ -798,6 +826,7 @@ extern "C" int sgq_plan_status(sgq_plan* plan, int32_t* host_status) {
   *host_status = (bits & kStatusNonFinite) ? SGQ_ENONFINITE
                  : (bits & kStatusLimit)   ? SGQ_ELIMIT
                  : (bits & kStatusRange)   ? SGQ_ERANGE
+                 : (bits & kStatusIndex)   ? SGQ_EINDEX
                                            : SGQ_OK;
   return SGQ_OK;
 }

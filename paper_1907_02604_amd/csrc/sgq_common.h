@@ -20,6 +20,7 @@ constexpr int kMaxNodeAtoms = 256;   // atoms whose projector box meets one node
 constexpr int kStatusNonFinite = 1;
 constexpr int kStatusLimit = 2;
 constexpr int kStatusRange = 4;
+constexpr int kStatusIndex = 8;
 
 // Sixth-order central weights of d^2/dx^2 at offsets 0, 1, 2, 3 (symmetric).
 constexpr double kFd0 = -49.0 / 18.0;

@@ -15,7 +15,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("SGQ_LIBRARY") or os.path.join(_HERE, "libsgq.so")
 
 SGQ_OK, SGQ_EINVAL, SGQ_ENOMEM, SGQ_EHIP, SGQ_EPLAN, SGQ_ENONFINITE, SGQ_ELIMIT = 0, -1, -2, -3, -4, -5, -6
-SGQ_ERANGE = -7
+SGQ_ERANGE, SGQ_EINDEX = -7, -8
 SGQ_FP64, SGQ_FP32 = 0, 1
 SGQ_BAND, SGQ_FREE, SGQ_GRAND = 0, 1, 2
 SGQ_SCHEDULE_BATCHED, SGQ_SCHEDULE_PLAIN = 0, 1
@@ -23,7 +23,8 @@ SGQ_SCHEDULE_BATCHED, SGQ_SCHEDULE_PLAIN = 0, 1
 EXPORTED = ("sgq_plan_create", "sgq_plan_destroy", "rho_quadrature", "band_energy",
             "band_energy_backward", "sgq_vloc_gaussian_backward", "sgq_plan_status",
             "sgq_last_error", "sgq_validate", "sgq_gauss_rule_host", "sgq_plan_set_schedule",
-            "sgq_plan_set_graph", "sgq_plan_autotune", "sgq_fermi_level")
+            "sgq_plan_set_graph", "sgq_plan_autotune", "sgq_fermi_level", "sgq_cluster_build",
+            "sgq_cluster_energy")
 
 
 class SgqError(RuntimeError):
@@ -59,6 +60,9 @@ def _load():
         "sgq_plan_set_graph": (I, [P, I]),
         "sgq_fermi_level": (I, [P, P, P, D, D, D, P, P]),
         "sgq_plan_autotune": (I, [P, P, P, P, D, D, I, P, ctypes.POINTER(ctypes.c_int32)]),
+        "sgq_cluster_build": (I, [P, D, P, ctypes.c_int32, D, P, ctypes.c_int64, ctypes.c_int64,
+                                  P, P, P, P, P, P, P]),
+        "sgq_cluster_energy": (I, [P, P, P, P, ctypes.c_int64, ctypes.c_int32, P, P, P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -224,6 +228,49 @@ def fermi_level(plan, theta_w, node_weight, n_electrons, kT, result, tol=1e-12, 
                                 _stream(stream)))
 
 
+def cluster_build(n, h, esp_center, radius, esp_weight=None):
+    """sgq_cluster_build on host arrays.  Returns a dict of numpy arrays: node_center,
+    node_esp, member_offset, member_node and (with esp_weight) node_weight."""
+    dims = np.ascontiguousarray([int(v) for v in n], dtype=np.int32)
+    c = np.ascontiguousarray(esp_center, dtype=np.int64)
+    w = None if esp_weight is None else np.ascontiguousarray(esp_weight, dtype=np.float64)
+    nn, nm = ctypes.c_int64(0), ctypes.c_int64(0)
+    args = (dims.ctypes.data, float(h), c.ctypes.data if c.size else None, int(c.size),
+            float(radius), _ptr(w))
+    _check(_lib.sgq_cluster_build(*args, 0, 0, None, None, None, None, None,
+                                  ctypes.byref(nn), ctypes.byref(nm)))
+    out = {"node_center": np.zeros(nn.value, np.int64), "node_esp": np.zeros(nn.value, np.int32),
+           "member_offset": np.zeros(c.size + 1, np.int64),
+           "member_node": np.zeros(nm.value, np.int32)}
+    if w is not None:
+        out["node_weight"] = np.zeros(nn.value, np.float64)
+    _check(_lib.sgq_cluster_build(*args, nn.value, nm.value, out["node_center"].ctypes.data,
+                                  out["node_esp"].ctypes.data, _ptr(out.get("node_weight")),
+                                  out["member_offset"].ctypes.data, out["member_node"].ctypes.data,
+                                  ctypes.byref(nn), ctypes.byref(nm)))
+    return out
+
+
+def torch_int64():
+    import torch
+    return torch.int64
+
+
+def torch_int32():
+    import torch
+    return torch.int32
+
+
+def cluster_energy(plan, e_node, member_offset, member_node, esp_weight, fbar, energy=None,
+                   stream=None):
+    """sgq_cluster_energy: fbar[q] <- mean of e_node over cluster q; energy <- sum n_q fbar_q."""
+    n_esp = int(member_offset.numel()) - 1
+    assert member_offset.dtype == torch_int64() and member_node.dtype == torch_int32()
+    _check(_lib.sgq_cluster_energy(plan.handle, _ptr(e_node), _ptr(member_offset),
+                                   _ptr(member_node), int(member_node.numel()), n_esp,
+                                   _ptr(esp_weight), _ptr(fbar), _ptr(energy), _stream(stream)))
+
+
 def vloc_gaussian_backward(plan, dV, atom_R, depth, sigma, cutoff_sigmas, dR, stream=None):
     _check(_lib.sgq_vloc_gaussian_backward(plan.handle, _ptr(dV), _ptr(atom_R), float(depth),
                                            float(sigma), float(cutoff_sigmas), _ptr(dR),
@@ -239,6 +286,25 @@ def device_inputs(prob, device="cuda"):
     E = torch.as_tensor(np.ascontiguousarray(prob.proj_E), dtype=torch.float64, device=device)
     w = torch.as_tensor(np.ascontiguousarray(prob.weight), dtype=torch.float64, device=device)
     return v, R, E, w
+
+
+def cluster_problem(prob, esp, radius, esp_weight=None):
+    """Node problem of the cluster sampling around the nodes ``esp`` of a ``synth.Problem``.
+
+    Returns (node problem, cluster lists).  The node problem holds the merged cluster
+    nodes (sgq_cluster_build), each with the cube half-width and depth of the lowest ESP
+    whose cluster holds it and the node weight sum_q n_q / |C_q| (n_q = esp_weight,
+    default the ESPs' own node weights)."""
+    import dataclasses
+    esp = np.asarray(esp, dtype=np.int64)
+    w = prob.weight[esp] if esp_weight is None else np.asarray(esp_weight, dtype=np.float64)
+    cl = cluster_build(prob.n, prob.h, prob.centers[esp], radius, esp_weight=w)
+    src = esp[cl["node_esp"]]
+    nodes = dataclasses.replace(prob, centers=cl["node_center"].copy(),
+                                half_width=prob.half_width[src].copy(),
+                                depth=prob.depth[src].copy(), weight=cl["node_weight"].copy())
+    cl["esp_weight"] = w
+    return nodes, cl
 
 
 def rho(prob, plan=None, want_rule=False, device="cuda"):

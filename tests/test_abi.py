@@ -93,3 +93,59 @@ def test_fermi_level_rejects_bad_arguments_on_the_host():
     from paper_1907_02604_amd import sgq
     lib = sgq.lib()
     assert lib.sgq_fermi_level(None, None, None, 1.0, 0.01, 1e-12, None, None) == sgq.SGQ_EINVAL
+
+
+def test_cluster_energy_rejects_bad_arguments_on_the_host():
+    from paper_1907_02604_amd import sgq
+    lib = sgq.lib()
+    assert lib.sgq_cluster_energy(None, None, None, None, 1, 1, None, None, None, None) == sgq.SGQ_EINVAL
+
+
+# ------------------------------------------------------------------ cluster geometry (host)
+@pytest.mark.parametrize("n,radius", [((12, 10, 9), 0.0), ((12, 10, 9), 0.5), ((12, 10, 9), 0.71),
+                                      ((12, 10, 9), 1.2), ((12, 10, 9), 3.0), ((7, 16, 5), 1.5)])
+def test_cluster_build_matches_the_oracle_balls(sgq, n, radius):
+    """Each cluster of the CSR list is the oracle's brute-force ball (periodic wrap
+    included: a radius of 3 bohr reaches past half of a 9-point axis)."""
+    import oracle as O
+    h = 0.5
+    rng = np.random.default_rng(3)
+    c = rng.choice(int(np.prod(n)), 6, replace=False)
+    c[1] = c[0] + 1 if (c[0] + 1) % n[0] else c[0] - 1      # two overlapping clusters
+    out = sgq.cluster_build(n, h, c, radius, esp_weight=np.arange(1.0, 7.0))
+    nc, off, mem = out["node_center"], out["member_offset"], out["member_node"]
+    assert np.all(np.diff(nc) > 0)
+    for q in range(c.size):
+        ref = O.cluster_members(n, h, int(c[q]), radius)
+        assert np.array_equal(nc[mem[off[q]:off[q + 1]]], ref)
+    union = np.unique(np.concatenate([O.cluster_members(n, h, int(x), radius) for x in c]))
+    assert np.array_equal(nc, union)
+    # node_esp: the lowest cluster holding each node
+    for k, p in enumerate(nc):
+        holders = [q for q in range(c.size) if p in set(nc[mem[off[q]:off[q + 1]]].tolist())]
+        assert out["node_esp"][k] == holders[0]
+    # node weights carry sum_q n_q Fbar_q for any per-node energy
+    e = rng.normal(size=nc.size)
+    fbar = np.array([e[mem[off[q]:off[q + 1]]].mean() for q in range(c.size)])
+    assert abs(np.dot(out["node_weight"], e) - np.dot(np.arange(1.0, 7.0), fbar)) < 1e-12
+
+
+def test_cluster_build_reports_counts_and_capacity(sgq):
+    lib = sgq.lib()
+    dims = np.array([10, 10, 10], np.int32)
+    c = np.array([0, 555], np.int64)
+    nn, nm = ctypes.c_int64(0), ctypes.c_int64(0)
+    args = (dims.ctypes.data, 0.5, c.ctypes.data, 2, 1.0, None)
+    assert lib.sgq_cluster_build(*args, 0, 0, None, None, None, None, None,
+                                 ctypes.byref(nn), ctypes.byref(nm)) == sgq.SGQ_OK
+    assert (nn.value, nm.value) == (66, 66)       # two disjoint 33-point balls
+    nodes = np.zeros(65, np.int64)
+    assert lib.sgq_cluster_build(*args, 65, 66, nodes.ctypes.data, None, None, None, None,
+                                 ctypes.byref(nn), ctypes.byref(nm)) == sgq.SGQ_EINVAL
+    bad = (dims.ctypes.data, 0.5, c.ctypes.data, 2, -1.0, None)
+    assert lib.sgq_cluster_build(*bad, 0, 0, None, None, None, None, None,
+                                 ctypes.byref(nn), ctypes.byref(nm)) == sgq.SGQ_EINVAL
+    outside = np.array([1000], np.int64)
+    assert lib.sgq_cluster_build(dims.ctypes.data, 0.5, outside.ctypes.data, 1, 1.0, None, 0, 0,
+                                 None, None, None, None, None, ctypes.byref(nn),
+                                 ctypes.byref(nm)) == sgq.SGQ_EINVAL
