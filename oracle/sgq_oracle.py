@@ -27,7 +27,10 @@ What it computes (paper: Sec. "Density Functional Theory"):
   N(mu) = 2 sum_q n_q sum_k w_k g(theta_k; mu) (Eq. Eqn:LSSGQ:Fermi_level:GQ with
   the node weights of Eq. eq:free_cg), equals a given N_e;
 * the cluster-sampled energy E = sum_q n_q Fbar_q, Fbar_q the mean per-point energy
-  over the grid points within a radius of ESP q (Eq. eq:free_cg_sampling).
+  over the grid points within a radius of ESP q (Eq. eq:free_cg_sampling);
+* the predictor + corrector reconstruction of fields on the fine grid: the corrector
+  at the ESPs interpolated by the linear shape functions of a tetrahedral mesh over
+  the ESPs and added to the predictor (Eq. eq:pc, Eq. phi_approx_scheme).
 
 Everything is float64 and written for readability, not speed: one node at a
 time, numpy array ops for the stencil, a library tridiagonal eigensolver.
@@ -592,6 +595,78 @@ def cluster_energy(e_of_point, n, h, esp_centers, esp_weights, radius):
         fbar.append(float(np.mean([e_of_point(int(p)) for p in members])))
     fbar = np.array(fbar)
     return float(np.sum(np.asarray(esp_weights, dtype=np.float64) * fbar)), fbar
+
+
+# --------------------------------------------------------------------------------------
+# Predictor + corrector reconstruction on the fine grid (Eq. eq:pc with the FE
+# interpolation of the correctors, Eq. phi_approx_scheme)
+# --------------------------------------------------------------------------------------
+def esp_coords(n, esp_center):
+    """Unwrapped integer grid coordinates (M, 3) of the ESPs (linear grid indices)."""
+    nx, ny, _ = n
+    c = np.asarray(esp_center, dtype=np.int64)
+    return np.stack([c % nx, (c // nx) % ny, c // (nx * ny)], axis=1)
+
+
+def _det3(a, b, c):
+    """Exact integer determinant of the rows a, b, c (arrays (..., 3) of int64)."""
+    return (a[..., 0] * (b[..., 1] * c[..., 2] - b[..., 2] * c[..., 1])
+            - a[..., 1] * (b[..., 0] * c[..., 2] - b[..., 2] * c[..., 0])
+            + a[..., 2] * (b[..., 0] * c[..., 1] - b[..., 1] * c[..., 0]))
+
+
+def fe_locate(n, esp_center, tets, points):
+    """For every integer point (P, 3), the lowest-numbered tetrahedron of the ESP mesh
+    that contains it (closed: faces, edges and vertices included), -1 if none.
+
+    A point x lies in the tetrahedron (v0, v1, v2, v3) when, with D the signed volume
+    det[v1-v0, v2-v0, v3-v0], each of the four volumes obtained by putting x in place of
+    one vertex has the sign of D or is zero.  All coordinates are integers, so the test
+    is exact.  Tetrahedra of zero volume hold no interior and are skipped.  Brute force
+    over all tetrahedra, a few points at a time."""
+    X = esp_coords(n, esp_center)
+    V = X[np.asarray(tets, dtype=np.int64)]                  # (T, 4, 3)
+    D = _det3(V[:, 1] - V[:, 0], V[:, 2] - V[:, 0], V[:, 3] - V[:, 0])
+    good = D != 0
+    sgn = np.sign(D)
+    pts = np.asarray(points, dtype=np.int64)
+    out = np.full(pts.shape[0], -1, dtype=np.int64)
+    step = max(1, (1 << 21) // max(1, V.shape[0]))
+    for s0 in range(0, pts.shape[0], step):
+        x = pts[s0:s0 + step, None, :]                           # (p, 1, 3)
+        inside = np.broadcast_to(good, (x.shape[0], V.shape[0])).copy()
+        for i in range(4):
+            W = [V[None, :, j] if j != i else x for j in range(4)]
+            Di = _det3(W[1] - W[0], W[2] - W[0], W[3] - W[0])
+            inside &= Di * sgn[None, :] >= 0
+        hit = inside.any(axis=1)
+        out[s0:s0 + step] = np.where(hit, inside.argmax(axis=1), -1)
+    return out
+
+
+def fe_reconstruct(n, esp_center, tets, esp_values, predictor, points=None):
+    """Fields on the fine grid from their predictors and the ESP values (Eq. eq:pc):
+    f_p = f0_p + sum_q gamma(r_p, r_q) fc_q with the corrector fc_q = f_q - f0(r_q) at
+    the ESPs and gamma the linear (barycentric) shape functions of the tetrahedron that
+    holds r_p (Eq. phi_approx_scheme); points outside every tetrahedron keep the
+    predictor.  esp_values (F, M), predictor (F, nz, ny, nx) or (F, npts).  Returns the
+    fields at `points` (linear grid indices; default every grid point), shape (F, P).
+    The barycentric coordinates solve the 4x4 system [v_i; 1] lam = [x; 1]."""
+    nx, ny, nz = n
+    pred = np.asarray(predictor, dtype=np.float64).reshape(len(esp_values), -1)
+    vals = np.asarray(esp_values, dtype=np.float64)
+    idx = np.arange(nx * ny * nz) if points is None else np.asarray(points, dtype=np.int64)
+    xyz = np.stack([idx % nx, (idx // nx) % ny, idx // (nx * ny)], axis=1)
+    loc = fe_locate(n, esp_center, tets, xyz)
+    X = esp_coords(n, esp_center).astype(np.float64)
+    corr = vals - pred[:, np.asarray(esp_center, dtype=np.int64)]   # (F, M)
+    out = pred[:, idx].copy()
+    for k in np.nonzero(loc >= 0)[0]:
+        t = np.asarray(tets[loc[k]], dtype=np.int64)
+        A = np.vstack([X[t].T, np.ones(4)])
+        lam = np.linalg.solve(A, np.append(xyz[k].astype(np.float64), 1.0))
+        out[:, k] += corr[:, t] @ lam
+    return out
 
 
 # --------------------------------------------------------------------------------------

@@ -215,3 +215,46 @@ def grid_coords(linear, n):
     nx, ny, _ = n
     linear = np.asarray(linear, dtype=np.int64)
     return linear % nx, (linear // nx) % ny, linear // (nx * ny)
+
+
+# ------------------------------------------------------------------ coarse-grained inputs
+def coarse_esps(n, seed, n_sampled, zone_radius):
+    """Energy/electronic sampling points of a coarse-grained run: every grid point within
+    `zone_radius` grid points of the box-centre line along z (the full-resolution zone
+    around a dislocation core) plus `n_sampled` seeded uniform grid points.  Ascending
+    unique linear indices."""
+    nx, ny, nz = n
+    ix, iy = np.meshgrid(np.arange(nx), np.arange(ny), indexing="xy")
+    disk = ((ix - nx // 2) ** 2 + (iy - ny // 2) ** 2 <= zone_radius ** 2).ravel()
+    plane = np.nonzero(disk)[0].astype(np.int64)           # ix + nx*iy
+    zone = (plane[None, :] + nx * ny * np.arange(nz, dtype=np.int64)[:, None]).ravel()
+    rng = np.random.default_rng(seed)
+    sampled = rng.choice(nx * ny * nz, size=n_sampled, replace=False).astype(np.int64)
+    return np.unique(np.concatenate([zone, sampled]))
+
+
+def esp_mesh(n, esp_center):
+    """Tetrahedral mesh over the ESPs: the Delaunay tetrahedralisation (qhull through
+    scipy) of their unwrapped grid coordinates, with the zero-volume tetrahedra that
+    degenerate (coplanar / cospherical) lattice points produce removed.  The kept
+    tetrahedra tile the convex hull; their orientations are mixed, as qhull returns them.
+    int32 (T, 4) ESP indices."""
+    from scipy.spatial import Delaunay
+    nx, ny, _ = n
+    c = np.asarray(esp_center, dtype=np.int64)
+    xyz = np.stack([c % nx, (c // nx) % ny, c // (nx * ny)], axis=1)
+    tets = Delaunay(xyz.astype(np.float64)).simplices.astype(np.int64)
+    v = xyz[tets]
+    a, b, d = v[:, 1] - v[:, 0], v[:, 2] - v[:, 0], v[:, 3] - v[:, 0]
+    vol6 = np.einsum("ij,ij->i", a, np.cross(b, d))
+    return tets[vol6 != 0].astype(np.int32)
+
+
+def predictor_fields(n, h, sites, sigma=1.2):
+    """Two smooth synthetic predictor fields on the grid, (2, nz, ny, nx) FP64: a
+    density-like sum of Gaussians 0.05 exp(-r^2/2 sigma^2) at `sites` (the undisplaced
+    lattice of the defect-free crystal) and a potential-like sum -0.8 exp(-r^2/2 s^2)
+    with s = 1.5 sigma."""
+    rho0 = gaussian_vloc(n, h, sites, depth=0.05, sigma=sigma)
+    phi0 = gaussian_vloc(n, h, sites, depth=-0.8, sigma=1.5 * sigma)
+    return np.stack([rho0, phi0])

@@ -601,3 +601,90 @@ def test_cluster_energy_reduces_to_point_sampling():
     assert abs(E - sum(wi * e(c) for wi, c in zip(w, centers))) < 1e-15
     E2, fbar2 = O.cluster_energy(lambda p: 0.25, (12, 12, 12), 0.5, centers, w, 1.3)
     assert np.allclose(fbar2, 0.25) and abs(E2 - 0.25 * sum(w)) < 1e-14
+
+
+# ---------------------------------------------------------------- predictor + corrector
+def _lin_n(x, y, z, n):
+    return x + n[0] * (y + n[1] * z)
+
+
+def test_fe_locate_counts_lattice_points_of_a_corner_tetrahedron():
+    """The closed tetrahedron 0, a e_x, a e_y, a e_z holds the C(a+3, 3) integer points with
+    x, y, z >= 0 and x + y + z <= a; the rest of the box is outside."""
+    n = (7, 7, 7)
+    for a in (1, 2, 4, 6):
+        esp = [_lin_n(0, 0, 0, n), _lin_n(a, 0, 0, n), _lin_n(0, a, 0, n), _lin_n(0, 0, a, n)]
+        for tet in ([0, 1, 2, 3], [1, 0, 2, 3]):           # either orientation
+            pts = np.array([(x, y, z) for z in range(7) for y in range(7) for x in range(7)])
+            loc = O.fe_locate(n, esp, [tet], pts)
+            inside = pts.sum(axis=1) <= a
+            assert np.array_equal(loc == 0, inside) and np.all(loc[~inside] == -1)
+            assert int(inside.sum()) == math.comb(a + 3, 3)
+
+
+def test_fe_locate_kuhn_cube_and_lowest_index_rule():
+    """The six tetrahedra (0, e_i, e_i + e_j, 1) of a cube along its main diagonal cover
+    every lattice point of the cube once or more; points on the diagonal lie in all six and
+    take tetrahedron 0; a zero-volume tetrahedron placed first is skipped."""
+    import itertools
+    a, n = 4, (6, 6, 6)
+    corners = {}
+    for c in itertools.product((0, a), repeat=3):
+        corners[c] = len(corners)
+    esp = [_lin_n(x, y, z, n) for (x, y, z) in corners]
+    tets = [[corners[(0, 0, 0)], corners[(0, 0, a)], corners[(a, a, a)], corners[(a, 0, 0)]]]
+    for p in itertools.permutations(range(3)):
+        v1 = [0, 0, 0]; v1[p[0]] = a
+        v2 = list(v1); v2[p[1]] = a
+        tets.append([corners[(0, 0, 0)], corners[tuple(v1)], corners[tuple(v2)], corners[(a, a, a)]])
+    tets[0] = [corners[(0, 0, 0)], corners[(a, 0, 0)], corners[(a, a, 0)], corners[(0, a, 0)]]  # flat
+    pts = np.array([(x, y, z) for z in range(6) for y in range(6) for x in range(6)])
+    loc = O.fe_locate(n, esp, tets, pts)
+    in_cube = np.all(pts <= a, axis=1)
+    assert np.all(loc[in_cube] >= 1) and np.all(loc[~in_cube] == -1)
+    diag = in_cube & (pts[:, 0] == pts[:, 1]) & (pts[:, 1] == pts[:, 2])
+    assert np.all(loc[diag] == 1)
+
+
+def _small_mesh_case(seed=3, n=(14, 13, 12), m=60):
+    rng = np.random.default_rng(seed)
+    esp = np.sort(rng.choice(int(np.prod(n)), m, replace=False))
+    tets = synth.esp_mesh(n, esp)
+    return n, esp, tets, rng
+
+
+def test_fe_reconstruct_reproduces_linear_correctors():
+    """Linear shape functions reproduce a linear corrector exactly: with ESP values
+    f0(r_q) + a + b.r_q, every point inside the mesh gets f0_p + a + b.r_p; points
+    outside keep f0_p; every ESP gets its own value."""
+    n, esp, tets, rng = _small_mesh_case()
+    F = 2
+    pred = rng.normal(size=(F, int(np.prod(n))))
+    X = O.esp_coords(n, esp).astype(np.float64)
+    coef = rng.normal(size=(F, 4))
+    lin = lambda xyz: coef[:, :1] + coef[:, 1:] @ xyz.T          # (F, P)
+    vals = pred[:, esp] + lin(X)
+    out = O.fe_reconstruct(n, esp, tets, vals, pred)
+    allp = np.arange(int(np.prod(n)))
+    xyz = np.stack([allp % n[0], (allp // n[0]) % n[1], allp // (n[0] * n[1])], 1)
+    loc = O.fe_locate(n, esp, tets, xyz)
+    inside = loc >= 0
+    assert inside.sum() > 0.3 * allp.size and (~inside).sum() > 0
+    assert np.max(np.abs(out[:, inside] - (pred[:, inside] + lin(xyz[inside].astype(float))))) < 1e-11
+    assert np.array_equal(out[:, ~inside], pred[:, ~inside])
+    assert np.max(np.abs(out[:, esp] - vals)) < 1e-11
+
+
+def test_fe_mesh_tiles_the_hull_and_zero_corrector_keeps_the_predictor():
+    """The generated mesh tiles the ESPs' convex hull (volumes add up to the hull's), and
+    ESP values equal to the predictor there leave the predictor unchanged everywhere."""
+    from scipy.spatial import ConvexHull
+    n, esp, tets, rng = _small_mesh_case(seed=4)
+    X = O.esp_coords(n, esp)
+    V = X[tets.astype(np.int64)]
+    vol6 = np.abs(np.einsum("ij,ij->i", V[:, 1] - V[:, 0], np.cross(V[:, 2] - V[:, 0], V[:, 3] - V[:, 0])))
+    assert np.all(vol6 > 0)
+    assert abs(vol6.sum() / 6.0 - ConvexHull(X.astype(float)).volume) < 1e-9
+    pred = rng.normal(size=(1, int(np.prod(n))))
+    out = O.fe_reconstruct(n, esp, tets, pred[:, esp], pred)
+    assert np.max(np.abs(out - pred)) < 1e-13

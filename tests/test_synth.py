@@ -54,3 +54,17 @@ def test_screw_displacement():
     s = np.array([[40.0, 32.0, 5.0], [32.0, 40.0, 5.0], [24.0, 32.0 - 1e-9, 5.0]])
     d = synth.screw_displace(s, L)
     np.testing.assert_allclose(d[:, 2] - 5.0, [0.0, 6.06 / 4, -6.06 / 2], atol=1e-8)
+
+
+def test_coarse_esps_zone_and_sample():
+    """The full-resolution zone holds every point of the disk on every z plane; the
+    seeded sample adds points; the result is sorted, unique and reproducible."""
+    n = (20, 20, 6)
+    a = synth.coarse_esps(n, 9, 50, 3)
+    assert np.array_equal(a, synth.coarse_esps(n, 9, 50, 3))
+    assert np.all(np.diff(a) > 0)
+    disk = sum(1 for x in range(20) for y in range(20) if (x - 10) ** 2 + (y - 10) ** 2 <= 9)
+    x, y, z = a % 20, (a // 20) % 20, a // 400
+    in_zone = (x - 10) ** 2 + (y - 10) ** 2 <= 9
+    assert disk == 29 and in_zone.sum() == 6 * disk
+    assert disk * 6 < a.size <= disk * 6 + 50
