@@ -120,6 +120,8 @@ def main():
                          "forward and adjoint; 0 skips it")
     ap.add_argument("--cluster-esps", type=int, default=256,
                     help="energy sampling points of the cluster-energy leg (0 skips it)")
+    ap.add_argument("--no-fe", action="store_true",
+                    help="skip the fine-grid predictor + corrector reconstruction leg")
     ap.add_argument("--no-uneven", action="store_true",
                     help="skip the uneven-batching measurement (96^3, 20000 nodes, R and K drawn)")
     ap.add_argument("--tune-nodes", type=int, default=2048,
@@ -272,6 +274,49 @@ def main():
         print(f"[bench] cluster energy {args.cluster_esps / tc:.1f} ESPs/s "
               f"({Pc.n_nodes / tc:.1f} nodes/s)", file=sys.stderr, flush=True)
         cplan.close()
+    if not args.no_fe:
+        # predictor + corrector reconstruction of two fields (density, potential) on the
+        # 128^3 fine grid from the ESPs of a coarse-grained dislocation run: the cylinder of
+        # radius 4 points around the core line plus 65536 seeded points, Delaunay mesh
+        n5 = (128, 128, 128)
+        esp5 = synth.coarse_esps(n5, 5, 65536, 4)
+        tets5 = synth.esp_mesh(n5, esp5)
+        pred5 = synth.predictor_fields(n5, 0.5, synth.hcp_sites((64.0, 64.0, 64.0))).reshape(2, -1)
+        ex, ey = esp5 % 128 - 64, (esp5 // 128) % 128 - 64
+        decay = np.exp(-np.sqrt(ex * ex + ey * ey) / 6.0)
+        vals5 = pred5[:, esp5] + np.stack([0.02 * decay, -0.3 * decay])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        mesh = sgq.FeMesh(n5, esp5, tets5, max_fields=2)
+        t_mesh = time.perf_counter() - t0
+        pd = torch.as_tensor(np.ascontiguousarray(pred5), device="cuda")
+        vd = torch.as_tensor(np.ascontiguousarray(vals5), device="cuda")
+        od = torch.empty_like(pd)
+        mesh.reconstruct(vd, pd, od, stream=stream.cuda_stream)       # warm-up
+        stream.synchronize()
+        reps = 50
+        f0 = torch.cuda.Event(enable_timing=True)
+        f1 = torch.cuda.Event(enable_timing=True)
+        f0.record(stream)
+        for _ in range(reps):
+            mesh.reconstruct(vd, pd, od, stream=stream.cuda_stream)
+        f1.record(stream)
+        stream.synchronize()
+        t_fe = f0.elapsed_time(f1) * 1e-3 / reps
+        npts5 = 128 ** 3
+        fe_bytes = npts5 * (4 + 2 * 16) + esp5.size * 2 * 24
+        info = mesh.info()
+        rec["fe_reconstruct"] = {
+            "workload": f"128^3 fine grid, {esp5.size} ESPs (radius-4 core cylinder + 65536 "
+                        f"seeded points), {info['kept']} Delaunay tetrahedra, 2 fields (rho, phi)",
+            "value": npts5 / t_fe, "unit": "fine points/s", "us_per_call": t_fe * 1e6,
+            "alg_bytes_per_call": fe_bytes, "achieved_GBs": fe_bytes / t_fe / 1e9,
+            "frac_hbm_peak": fe_bytes / t_fe / 1e9 / HBM_PEAK_GBS,
+            "mesh_create_s": t_mesh, "location_bucket": info["bucket"]}
+        print(f"[bench] fe reconstruct {t_fe * 1e6:.1f} us/call, "
+              f"{fe_bytes / t_fe / 1e9:.0f} GB/s; mesh + location {t_mesh:.2f} s",
+              file=sys.stderr, flush=True)
+        mesh.close()
     if not args.no_plain:
         # per-node GPU baseline: the plain schedule on a seeded node sample
         idx = np.random.default_rng(7).choice(P.n_nodes, args.plain_nodes, replace=False)

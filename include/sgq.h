@@ -24,8 +24,8 @@
  *   - Grid arrays are [z][y][x] with x fastest: linear index ix + nx*(iy + ny*iz).
  *   - Every array argument of a compute call is a DEVICE pointer owned by the caller,
  *     contiguous, of the stated type and length.  Host arrays are passed only to
- *     sgq_plan_create and the host-only helpers (sgq_cluster_build, sgq_validate,
- *     sgq_gauss_rule_host).
+ *     sgq_plan_create, sgq_fe_mesh_create and the host-only helpers (sgq_cluster_build,
+ *     sgq_validate, sgq_gauss_rule_host).
  *   - Compute calls are asynchronous on `stream` (a hipStream_t; NULL = default
  *     stream).  Inputs must stay valid until the stream reaches the call.
  *   - Every function returns an sgq_status and never throws.  Argument errors found
@@ -210,6 +210,50 @@ int sgq_cluster_build(const int32_t n[3], double h, const int64_t* esp_center, i
 int sgq_cluster_energy(sgq_plan* plan, const double* e_node, const int64_t* member_offset,
                        const int32_t* member_node, int64_t n_members, int32_t n_esp,
                        const double* esp_weight, double* fbar, double* energy, void* stream);
+
+/* Predictor + corrector reconstruction on the fine grid (Eq. eq:pc, with the correctors
+ * interpolated from the ESPs by linear finite-element shape functions, Eq.
+ * phi_approx_scheme).  A mesh object holds a tetrahedral mesh over ESPs that sit on grid
+ * points, and, for every point of the grid (the fine grid), the tetrahedron holding it.
+ *
+ * sgq_fe_mesh_create: HOST arrays; synchronous; uses the current device.
+ *   n [3]               grid extents, each in [1, 65536], product < 2^31
+ *   esp_center [n_esp]  int64  linear grid index of each ESP; its integer grid coordinates
+ *                       (unwrapped: the mesh lives in the box [0, n-1]^3) are the vertex
+ *   tets [n_tets*4]     int32  ESP indices of each tetrahedron (any orientation); the
+ *                       tetrahedra should tile a region without overlap (a Delaunay
+ *                       tetrahedralisation does); zero-volume tetrahedra are ignored
+ *   max_fields          1..4: the most fields one sgq_fe_reconstruct call may carry
+ * A grid point lies in a tetrahedron when each barycentric coordinate is >= 0 (faces,
+ * edges and vertices included), decided exactly (integer volumes).  Each point takes the
+ * lowest-numbered tetrahedron that holds it, or none.  Returns SGQ_EINVAL for a bad
+ * argument (a vertex index out of range, an ESP outside the grid, ...), SGQ_EHIP when a
+ * device call fails.
+ *
+ * sgq_fe_reconstruct: fields f = 0..n_fields-1, device arrays, asynchronous on `stream`:
+ *   esp_values [n_fields][n_esp] double  the full field value f_q at each ESP (e.g. the
+ *                                        rho_quadrature density of a plan on the ESPs)
+ *   predictor  [n_fields][npts]  double  the predictor f0 on the grid ([z][y][x])
+ *   out        [n_fields][npts]  double  f_p = f0_p + sum_i lambda_i (f_{v_i} - f0(r_{v_i}))
+ *                                        over the vertices v_i of the point's tetrahedron
+ *                                        (lambda its barycentric coordinates); points in no
+ *                                        tetrahedron get f0_p; out must not alias the inputs
+ * Non-finite inputs propagate to the outputs they touch.  Calls on one mesh must be
+ * serialised (they share its corrector scratch).
+ *
+ * sgq_fe_mesh_location: copies the tetrahedron of every grid point (int32 [npts], -1 for
+ * none) into the device array loc, asynchronously on `stream`.
+ * sgq_fe_mesh_info: info [5] host int64 out: npts, n_esp, n_tets, kept (non-zero-volume)
+ * tetrahedra, bucket edge of the location search. */
+typedef struct sgq_fe_mesh sgq_fe_mesh;
+int sgq_fe_mesh_create(const int32_t n[3], const int64_t* esp_center, int32_t n_esp,
+                       const int32_t* tets, int32_t n_tets, int32_t max_fields,
+                       sgq_fe_mesh** out);
+int sgq_fe_mesh_destroy(sgq_fe_mesh* mesh);
+int sgq_fe_reconstruct(sgq_fe_mesh* mesh, int32_t n_fields, const double* esp_values,
+                       const double* predictor, double* out, void* stream);
+int sgq_fe_mesh_location(sgq_fe_mesh* mesh, int32_t* loc, void* stream);
+int sgq_fe_mesh_info(const sgq_fe_mesh* mesh, int64_t* info);
 
 /* Launch capture.  With enable != 0 (the default), rho_quadrature and band_energy on a
  * stream other than the legacy default stream capture their launch sequence (setup

@@ -24,7 +24,8 @@ EXPORTED = ("sgq_plan_create", "sgq_plan_destroy", "rho_quadrature", "band_energ
             "band_energy_backward", "sgq_vloc_gaussian_backward", "sgq_plan_status",
             "sgq_last_error", "sgq_validate", "sgq_gauss_rule_host", "sgq_plan_set_schedule",
             "sgq_plan_set_graph", "sgq_plan_autotune", "sgq_fermi_level", "sgq_cluster_build",
-            "sgq_cluster_energy")
+            "sgq_cluster_energy", "sgq_fe_mesh_create", "sgq_fe_mesh_destroy",
+            "sgq_fe_reconstruct", "sgq_fe_mesh_location", "sgq_fe_mesh_info")
 
 
 class SgqError(RuntimeError):
@@ -63,6 +64,12 @@ def _load():
         "sgq_cluster_build": (I, [P, D, P, ctypes.c_int32, D, P, ctypes.c_int64, ctypes.c_int64,
                                   P, P, P, P, P, P, P]),
         "sgq_cluster_energy": (I, [P, P, P, P, ctypes.c_int64, ctypes.c_int32, P, P, P, P]),
+        "sgq_fe_mesh_create": (I, [P, P, ctypes.c_int32, P, ctypes.c_int32, ctypes.c_int32,
+                                   ctypes.POINTER(P)]),
+        "sgq_fe_mesh_destroy": (I, [P]),
+        "sgq_fe_reconstruct": (I, [P, ctypes.c_int32, P, P, P, P]),
+        "sgq_fe_mesh_location": (I, [P, P, P]),
+        "sgq_fe_mesh_info": (I, [P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -269,6 +276,53 @@ def cluster_energy(plan, e_node, member_offset, member_node, esp_weight, fbar, e
     _check(_lib.sgq_cluster_energy(plan.handle, _ptr(e_node), _ptr(member_offset),
                                    _ptr(member_node), int(member_node.numel()), n_esp,
                                    _ptr(esp_weight), _ptr(fbar), _ptr(energy), _stream(stream)))
+
+
+class FeMesh:
+    """sgq_fe_mesh: a tetrahedral mesh over ESPs on the grid and the location of every grid
+    point in it (built on the current device at creation)."""
+
+    def __init__(self, n, esp_center, tets, max_fields=2):
+        dims = np.ascontiguousarray([int(v) for v in n], dtype=np.int32)
+        c = np.ascontiguousarray(esp_center, dtype=np.int64)
+        t = np.ascontiguousarray(tets, dtype=np.int32).reshape(-1, 4)
+        self.n = tuple(int(v) for v in n)
+        self.n_esp = int(c.size)
+        self._h = ctypes.c_void_p()
+        _check(_lib.sgq_fe_mesh_create(dims.ctypes.data, c.ctypes.data, int(c.size),
+                                       t.ctypes.data if t.size else None, int(t.shape[0]),
+                                       int(max_fields), ctypes.byref(self._h)))
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self):
+        out = np.zeros(5, np.int64)
+        _check(_lib.sgq_fe_mesh_info(self._h, out.ctypes.data))
+        return dict(zip(("npts", "n_esp", "n_tets", "kept", "bucket"), out.tolist()))
+
+    def location(self, loc, stream=None):
+        _check(_lib.sgq_fe_mesh_location(self._h, _ptr(loc), _stream(stream)))
+
+    def reconstruct(self, esp_values, predictor, out, stream=None):
+        """esp_values (F, n_esp), predictor and out (F, npts): contiguous FP64 device tensors."""
+        F = int(esp_values.shape[0])
+        assert esp_values.numel() == F * self.n_esp
+        assert predictor.numel() == out.numel() == F * int(np.prod(self.n))
+        _check(_lib.sgq_fe_reconstruct(self._h, F, _ptr(esp_values), _ptr(predictor), _ptr(out),
+                                       _stream(stream)))
+
+    def close(self):
+        if self._h:
+            _lib.sgq_fe_mesh_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def vloc_gaussian_backward(plan, dV, atom_R, depth, sigma, cutoff_sigmas, dR, stream=None):

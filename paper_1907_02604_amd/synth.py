@@ -254,7 +254,7 @@ def predictor_fields(n, h, sites, sigma=1.2):
     """Two smooth synthetic predictor fields on the grid, (2, nz, ny, nx) FP64: a
     density-like sum of Gaussians 0.05 exp(-r^2/2 sigma^2) at `sites` (the undisplaced
     lattice of the defect-free crystal) and a potential-like sum -0.8 exp(-r^2/2 s^2)
-    with s = 1.5 sigma."""
-    rho0 = gaussian_vloc(n, h, sites, depth=0.05, sigma=sigma)
-    phi0 = gaussian_vloc(n, h, sites, depth=-0.8, sigma=1.5 * sigma)
+    with s = 1.5 sigma; each Gaussian is cut at 4 of its widths."""
+    rho0 = gaussian_vloc(n, h, sites, depth=0.05, sigma=sigma, cutoff=4.0)
+    phi0 = gaussian_vloc(n, h, sites, depth=-0.8, sigma=1.5 * sigma, cutoff=4.0)
     return np.stack([rho0, phi0])
