@@ -31,6 +31,10 @@ What it computes (paper: Sec. "Density Functional Theory"):
 * the predictor + corrector reconstruction of fields on the fine grid: the corrector
   at the ESPs interpolated by the linear shape functions of a tetrahedral mesh over
   the ESPs and added to the predictor (Eq. eq:pc, Eq. phi_approx_scheme).
+* the self-consistency ingredients: the LDA exchange-correlation energy and potential
+  (Eq. eq:xc, Perdew-Wang correlation) and the periodic Poisson solve for the
+  electrostatic potential with the FD Laplacian (Eq. eq:poisson), and their sum, the
+  potential of the Hamiltonian (Eq. Eqn:Hamiltonian).
 
 Everything is float64 and written for readability, not speed: one node at a
 time, numpy array ops for the stencil, a library tridiagonal eigensolver.
@@ -667,6 +671,85 @@ def fe_reconstruct(n, esp_center, tets, esp_values, predictor, points=None):
         lam = np.linalg.solve(A, np.append(xyz[k].astype(np.float64), 1.0))
         out[:, k] += corr[:, t] @ lam
     return out
+
+
+# --------------------------------------------------------------------------------------
+# Self-consistency ingredients: the LDA exchange-correlation potential (Eq. eq:xc) and the
+# electrostatic potential of the periodic Poisson problem (Eq. eq:poisson)
+# --------------------------------------------------------------------------------------
+# Perdew-Wang (1992) parametrisation of the unpolarised correlation energy per electron
+# (Hartree):  eps_c(rs) = -2A (1 + a1 rs) ln(1 + 1 / (2A (b1 rs^1/2 + b2 rs + b3 rs^3/2 + b4 rs^2)))
+PW92_A, PW92_A1 = 0.031091, 0.21370
+PW92_B = (7.5957, 3.5876, 1.6382, 0.49294)
+
+
+def pw92_correlation(rs):
+    """(eps_c, d eps_c / d rs) of the Perdew-Wang form above, rs > 0 (array)."""
+    rs = np.asarray(rs, dtype=np.float64)
+    b1, b2, b3, b4 = PW92_B
+    sq = np.sqrt(rs)
+    Q = 2.0 * PW92_A * (b1 * sq + b2 * rs + b3 * rs * sq + b4 * rs * rs)
+    dQ = 2.0 * PW92_A * (0.5 * b1 / sq + b2 + 1.5 * b3 * sq + 2.0 * b4 * rs)
+    L = np.log1p(1.0 / Q)
+    eps = -2.0 * PW92_A * (1.0 + PW92_A1 * rs) * L
+    deps = -2.0 * PW92_A * PW92_A1 * L + 2.0 * PW92_A * (1.0 + PW92_A1 * rs) * dQ / (Q * (Q + 1.0))
+    return eps, deps
+
+
+def lda_xc(rho):
+    """LDA exchange-correlation energy per volume e_xc(rho) = -3/4 (3/pi)^(1/3) rho^(4/3)
+    + rho eps_c(rho) and its potential u = d e_xc / d rho (Eq. eq:xc), elementwise; zero where
+    rho <= 0.  The correlation part is the Perdew-Wang form in the Wigner-Seitz radius
+    rs = (3 / (4 pi rho))^(1/3); its potential is eps_c - rs/3 d eps_c/d rs."""
+    rho = np.asarray(rho, dtype=np.float64)
+    e = np.zeros_like(rho)
+    u = np.zeros_like(rho)
+    pos = rho > 0.0
+    r = rho[pos]
+    cx = (3.0 / math.pi) ** (1.0 / 3.0)
+    ex = -0.75 * cx * r ** (4.0 / 3.0)
+    ux = -cx * r ** (1.0 / 3.0)
+    rs = (3.0 / (4.0 * math.pi * r)) ** (1.0 / 3.0)
+    ec, dec = pw92_correlation(rs)
+    e[pos] = ex + r * ec
+    u[pos] = ux + ec - rs / 3.0 * dec
+    return e, u
+
+
+def fd_laplacian_symbol(n, h):
+    """Eigenvalues of the periodic sixth-order FD Laplacian on the grid n (per-axis sums),
+    (nz, ny, nx): sum over axes of (w0 + 2 sum_m w_m cos(2 pi m k / n_a)) / h^2."""
+    nx, ny, nz = n
+    def axis(na):
+        k = np.arange(na)
+        return sum((FD2_WEIGHTS[0] if m == 0 else 2.0 * FD2_WEIGHTS[m] * np.cos(2.0 * math.pi * m * k / na))
+                   for m in range(4)) / (h * h)
+    return axis(nz)[:, None, None] + axis(ny)[None, :, None] + axis(nx)[None, None, :]
+
+
+def poisson_periodic(source, h):
+    """phi with -(1/4 pi) Lap_6 phi = s - mean(s) on the periodic grid (Eq. eq:poisson, the
+    FD Laplacian of the Hamiltonian), mean(phi) = 0; by FFT, dividing by the FD symbol.
+    source (nz, ny, nx).  Returns (phi, mean(s))."""
+    s = np.asarray(source, dtype=np.float64)
+    nz, ny, nx = s.shape
+    lam = fd_laplacian_symbol((nx, ny, nz), h)
+    sk = np.fft.fftn(s)
+    # every FD eigenvalue but the k = 0 one is strictly negative; the k = 0 mode (the mean)
+    # is dropped by its index (its computed eigenvalue is a rounding residue, not 0)
+    lam[0, 0, 0] = 1.0
+    phik = -4.0 * math.pi * sk / lam
+    phik[0, 0, 0] = 0.0
+    return np.real(np.fft.ifftn(phik)), float(np.mean(s))
+
+
+def effective_potential(rho, b, h):
+    """V = phi[rho + b] + u(rho): the electrostatic and exchange-correlation parts of the
+    Hamiltonian's potential (Eq. Eqn:Hamiltonian) from the electron density rho and the
+    nuclear charge density b on the grid.  Returns (V, e_xc, phi, mean(rho + b))."""
+    phi, mean = poisson_periodic(np.asarray(rho) + np.asarray(b), h)
+    e, u = lda_xc(rho)
+    return phi + u, e, phi, mean
 
 
 # --------------------------------------------------------------------------------------

@@ -688,3 +688,61 @@ def test_fe_mesh_tiles_the_hull_and_zero_corrector_keeps_the_predictor():
     pred = rng.normal(size=(1, int(np.prod(n))))
     out = O.fe_reconstruct(n, esp, tets, pred[:, esp], pred)
     assert np.max(np.abs(out - pred)) < 1e-13
+
+
+# ---------------------------------------------------------------- xc and Poisson
+def test_lda_exchange_is_the_dirac_form():
+    """Without correlation, e_x = -(3 k_F / 4 pi) rho with k_F = (3 pi^2 rho)^(1/3) (the
+    exchange energy per electron of the uniform electron gas)."""
+    rho = np.array([1e-4, 0.003, 0.05, 0.4, 7.0])
+    e, _ = O.lda_xc(rho)
+    rs = (3.0 / (4.0 * math.pi * rho)) ** (1.0 / 3.0)
+    ec, _ = O.pw92_correlation(rs)
+    kf = (3.0 * math.pi ** 2 * rho) ** (1.0 / 3.0)
+    np.testing.assert_allclose(e - rho * ec, -0.75 * kf / math.pi * rho, rtol=1e-14)
+
+
+def test_pw92_high_density_logarithm():
+    """As rs -> 0 the correlation energy per electron goes as c0 ln rs with the exact
+    high-density coefficient c0 = (1 - ln 2) / pi^2; at low density it falls off as
+    1/rs, within 2 % of Wigner's -0.44 / rs."""
+    ec, _ = O.pw92_correlation(np.array([1e-12, 1e-11]))
+    slope = (ec[1] - ec[0]) / math.log(10.0)
+    assert abs(slope - (1.0 - math.log(2.0)) / math.pi ** 2) < 1e-4 * 0.0311
+    ec_far, _ = O.pw92_correlation(np.array([1e6]))
+    assert abs(ec_far[0] * 1e6 / -0.44 - 1.0) < 0.02
+
+
+def test_lda_potential_is_the_density_derivative():
+    """u = d e_xc / d rho, against central differences of e_xc; zero for rho <= 0."""
+    rho = np.array([2e-4, 0.002, 0.03, 0.25, 1.5, 12.0])
+    _, u = O.lda_xc(rho)
+    for r, ui in zip(rho, u):
+        d = 1e-5 * r
+        ep, _ = O.lda_xc(np.array([r + d]))
+        em, _ = O.lda_xc(np.array([r - d]))
+        assert abs((ep[0] - em[0]) / (2 * d) - ui) < 1e-8 * abs(ui)
+    e0, u0 = O.lda_xc(np.array([0.0, -1e-3]))
+    assert np.all(e0 == 0.0) and np.all(u0 == 0.0)
+
+
+def test_poisson_solution_satisfies_the_stencil():
+    """-(1/4 pi) Lap_6 phi = s - mean(s), with Lap_6 applied as the real-space periodic
+    stencil of the Hamiltonian's kinetic term (independent of the Fourier symbol); phi has
+    zero mean; a single Fourier mode comes back divided by its FD eigenvalue."""
+    rng = np.random.default_rng(4)
+    for shape in ((12, 10, 8), (9, 15, 6), (16, 16, 16)):
+        s = rng.normal(size=shape)
+        h = 0.37
+        phi, mean = O.poisson_periodic(s, h)
+        lap = -2.0 * O.kinetic_apply(phi, h, periodic=True)
+        assert np.max(np.abs(-lap / (4.0 * math.pi) - (s - s.mean()))) < 1e-11 * np.max(np.abs(s))
+        assert abs(phi.mean()) < 1e-13 and abs(mean - s.mean()) < 1e-15
+    nz, ny, nx = 8, 12, 10
+    x = np.arange(nx)[None, None, :]
+    s = np.cos(2.0 * math.pi * 3 * x / nx) * np.ones((nz, ny, nx))
+    h = 0.5
+    lam = sum((O.FD2_WEIGHTS[0] if m == 0 else 2 * O.FD2_WEIGHTS[m] * math.cos(2 * math.pi * m * 3 / nx))
+              for m in range(4)) / h ** 2
+    phi, _ = O.poisson_periodic(s, h)
+    np.testing.assert_allclose(phi, -4.0 * math.pi * s / lam, atol=1e-12)
