@@ -692,7 +692,7 @@ def pw92_correlation(rs):
     dQ = 2.0 * PW92_A * (0.5 * b1 / sq + b2 + 1.5 * b3 * sq + 2.0 * b4 * rs)
     L = np.log1p(1.0 / Q)
     eps = -2.0 * PW92_A * (1.0 + PW92_A1 * rs) * L
-    deps = -2.0 * PW92_A * PW92_A1 * L + 2.0 * PW92_A * (1.0 + PW92_A1 * rs) * dQ / (Q * (Q + 1.0))
+    deps = -2.0 * PW92_A * PW92_A1 * L + 2.0 * PW92_A * (1.0 + PW92_A1 * rs) * (dQ / Q) / (Q + 1.0)
     return eps, deps
 
 
