@@ -255,6 +255,35 @@ int sgq_fe_reconstruct(sgq_fe_mesh* mesh, int32_t n_fields, const double* esp_va
 int sgq_fe_mesh_location(sgq_fe_mesh* mesh, int32_t* loc, void* stream);
 int sgq_fe_mesh_info(const sgq_fe_mesh* mesh, int64_t* info);
 
+/* Self-consistency ingredients of the potential in the Hamiltonian (Eq. Eqn:Hamiltonian).
+ *
+ * sgq_lda_xc: the LDA exchange-correlation energy per volume and potential (Eq. eq:xc),
+ *   e_xc = -3/4 (3/pi)^(1/3) rho^(4/3) + rho eps_c(rho) with the Perdew-Wang (1992)
+ *   correlation eps_c, and u = d e_xc / d rho; both zero where rho <= 0.  Device arrays of
+ *   n doubles: rho in, exc out (optional), vxc out.  Asynchronous on `stream`.
+ *
+ * sgq_potential_create: a periodic Poisson solver for the grid n (each extent in [1, 1024]
+ *   and a product of 2, 3 and 5; fewer than 2^31 points) and spacing h; holds a complex
+ *   workspace of 16 bytes per grid point.  Uses the current device.
+ * sgq_poisson: phi with -(1/4 pi) L phi = s - mean(s) and mean(phi) = 0 (Eq. eq:poisson),
+ *   L the sixth-order FD Laplacian of the Hamiltonian on the periodic grid, solved exactly
+ *   for that operator by FFT.  Device arrays [nz][ny][nx] double: source in, phi out;
+ *   mean [1] out (optional): mean(s), the uniform part the periodic problem cannot hold.
+ * sgq_effective_potential: from the electron density rho and the nuclear charge density b
+ *   (optional, NULL = 0): v = phi[rho + b] + u(rho); phi, exc and mean are optional outputs
+ *   as above.  One FFT pass sequence with the exchange-correlation term fused into its last
+ *   pass.
+ * Outputs must not alias inputs.  Calls on one solver must be serialised (they share its
+ * workspace); all are asynchronous on `stream`. */
+typedef struct sgq_potential sgq_potential;
+int sgq_lda_xc(const double* rho, int64_t n, double* exc, double* vxc, void* stream);
+int sgq_potential_create(const int32_t n[3], double h, sgq_potential** out);
+int sgq_potential_destroy(sgq_potential* pot);
+int sgq_poisson(sgq_potential* pot, const double* source, double* phi, double* mean,
+                void* stream);
+int sgq_effective_potential(sgq_potential* pot, const double* rho, const double* b, double* v,
+                            double* phi, double* exc, double* mean, void* stream);
+
 /* Launch capture.  With enable != 0 (the default), rho_quadrature and band_energy on a
  * stream other than the legacy default stream capture their launch sequence (setup
  * kernels, the persistent Lanczos-Gauss kernel, the weighted sum) into a HIP graph on the

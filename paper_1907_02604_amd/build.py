@@ -6,7 +6,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = ["plan.hip", "forward.hip", "backward.hip", "plain.hip", "cluster.hip", "fe.hip"]
+SOURCES = ["plan.hip", "forward.hip", "backward.hip", "plain.hip", "cluster.hip", "fe.hip", "potential.hip"]
 LIB = os.path.join(HERE, "libsgq.so")
 
 

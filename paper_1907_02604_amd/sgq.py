@@ -25,7 +25,9 @@ EXPORTED = ("sgq_plan_create", "sgq_plan_destroy", "rho_quadrature", "band_energ
             "sgq_last_error", "sgq_validate", "sgq_gauss_rule_host", "sgq_plan_set_schedule",
             "sgq_plan_set_graph", "sgq_plan_autotune", "sgq_fermi_level", "sgq_cluster_build",
             "sgq_cluster_energy", "sgq_fe_mesh_create", "sgq_fe_mesh_destroy",
-            "sgq_fe_reconstruct", "sgq_fe_mesh_location", "sgq_fe_mesh_info")
+            "sgq_fe_reconstruct", "sgq_fe_mesh_location", "sgq_fe_mesh_info", "sgq_lda_xc",
+            "sgq_potential_create", "sgq_potential_destroy", "sgq_poisson",
+            "sgq_effective_potential")
 
 
 class SgqError(RuntimeError):
@@ -70,6 +72,11 @@ def _load():
         "sgq_fe_reconstruct": (I, [P, ctypes.c_int32, P, P, P, P]),
         "sgq_fe_mesh_location": (I, [P, P, P]),
         "sgq_fe_mesh_info": (I, [P, P]),
+        "sgq_lda_xc": (I, [P, ctypes.c_int64, P, P, P]),
+        "sgq_potential_create": (I, [P, D, ctypes.POINTER(P)]),
+        "sgq_potential_destroy": (I, [P]),
+        "sgq_poisson": (I, [P, P, P, P, P]),
+        "sgq_effective_potential": (I, [P, P, P, P, P, P, P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -316,6 +323,39 @@ class FeMesh:
     def close(self):
         if self._h:
             _lib.sgq_fe_mesh_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def lda_xc(rho, vxc, exc=None, stream=None):
+    """sgq_lda_xc on contiguous FP64 device tensors of equal size."""
+    _check(_lib.sgq_lda_xc(_ptr(rho), int(rho.numel()), _ptr(exc), _ptr(vxc), _stream(stream)))
+
+
+class Potential:
+    """sgq_potential: the periodic Poisson solver (and effective potential) of a grid."""
+
+    def __init__(self, n, h):
+        dims = np.ascontiguousarray([int(v) for v in n], dtype=np.int32)
+        self.n = tuple(int(v) for v in n)
+        self._h = ctypes.c_void_p()
+        _check(_lib.sgq_potential_create(dims.ctypes.data, float(h), ctypes.byref(self._h)))
+
+    def poisson(self, source, phi, mean=None, stream=None):
+        _check(_lib.sgq_poisson(self._h, _ptr(source), _ptr(phi), _ptr(mean), _stream(stream)))
+
+    def effective(self, rho, v, b=None, phi=None, exc=None, mean=None, stream=None):
+        _check(_lib.sgq_effective_potential(self._h, _ptr(rho), _ptr(b), _ptr(v), _ptr(phi),
+                                            _ptr(exc), _ptr(mean), _stream(stream)))
+
+    def close(self):
+        if self._h:
+            _lib.sgq_potential_destroy(self._h)
             self._h = ctypes.c_void_p()
 
     def __del__(self):

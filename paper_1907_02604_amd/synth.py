@@ -258,3 +258,11 @@ def predictor_fields(n, h, sites, sigma=1.2):
     rho0 = gaussian_vloc(n, h, sites, depth=0.05, sigma=sigma, cutoff=4.0)
     phi0 = gaussian_vloc(n, h, sites, depth=-0.8, sigma=1.5 * sigma, cutoff=4.0)
     return np.stack([rho0, phi0])
+
+
+def nuclear_charge(n, h, atoms, Z=2.0, sigma=0.8):
+    """Regularised nuclear charge density b(x) = -Z sum_J g(x - R_J) on the grid, (nz, ny, nx)
+    FP64, with g the unit-mass Gaussian of width sigma (bohr), periodic images within 6
+    widths.  Z = 2 stands for the two valence electrons of magnesium."""
+    norm = -Z / ((2.0 * math.pi) ** 1.5 * sigma ** 3)
+    return gaussian_vloc(n, h, atoms, depth=norm, sigma=sigma, cutoff=6.0)

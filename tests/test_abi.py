@@ -149,3 +149,25 @@ def test_cluster_build_reports_counts_and_capacity(sgq):
     assert lib.sgq_cluster_build(dims.ctypes.data, 0.5, outside.ctypes.data, 1, 1.0, None, 0, 0,
                                  None, None, None, None, None, ctypes.byref(nn),
                                  ctypes.byref(nm)) == sgq.SGQ_EINVAL
+
+
+def test_potential_and_fe_reject_bad_arguments_on_the_host(sgq):
+    """Grid and mesh validation happens before any device call."""
+    lib = sgq.lib()
+    h = ctypes.c_void_p()
+    for n, hh in (((7, 8, 8), 0.5), ((8, 8, 8), -1.0), ((2048, 1, 1), 0.5), ((0, 4, 4), 0.5)):
+        dims = np.array(n, np.int32)
+        assert lib.sgq_potential_create(dims.ctypes.data, hh, ctypes.byref(h)) == sgq.SGQ_EINVAL
+    assert lib.sgq_lda_xc(None, -1, None, None, None) == sgq.SGQ_EINVAL
+    assert lib.sgq_lda_xc(None, 0, None, None, None) == sgq.SGQ_OK
+    dims = np.array([8, 8, 8], np.int32)
+    esp = np.array([0, 7, 56, 448], np.int64)
+    bad = np.array([[0, 1, 2, 4]], np.int32)
+    assert lib.sgq_fe_mesh_create(dims.ctypes.data, esp.ctypes.data, 4, bad.ctypes.data, 1, 2,
+                                  ctypes.byref(h)) == sgq.SGQ_EINVAL
+    ok = np.array([[0, 1, 2, 3]], np.int32)
+    assert lib.sgq_fe_mesh_create(dims.ctypes.data, esp.ctypes.data, 4, ok.ctypes.data, 1, 5,
+                                  ctypes.byref(h)) == sgq.SGQ_EINVAL      # max_fields > 4
+    big = np.array([70000, 2, 2], np.int32)
+    assert lib.sgq_fe_mesh_create(big.ctypes.data, esp.ctypes.data, 4, ok.ctypes.data, 1, 2,
+                                  ctypes.byref(h)) == sgq.SGQ_EINVAL
