@@ -144,6 +144,7 @@ def main():
         cpu_rec, sample, ref = cpu_baseline(cfg, P.n_nodes)
         print(f"[bench] cpu baseline {cpu_rec['value']:.2f} nodes/s on {cpu_rec['cores']} cores",
               file=sys.stderr, flush=True)
+        import oracle as O          # the oracle timed beside the next-work legs
 
     import torch
     from paper_1907_02604_amd import sgq
@@ -230,6 +231,16 @@ def main():
     rec["fermi_level"] = {"n_electrons": n_el, "mu": float(fr[0]), "mu_of_the_count": P.mu,
                           "steps": int(fr[2]), "ms": f0.elapsed_time(f1),
                           "rule_points": int(P.n_nodes * plan.kmax)}
+    oracle_rows = {}
+    if cpu_rec is not None:
+        cpu_rec["next_rows"] = oracle_rows
+        # the oracle's Brent solve on the same rules, on the host
+        twh = tw.cpu().numpy().reshape(P.n_nodes, plan.kmax, 2)
+        t0 = time.perf_counter()
+        mu_o = O.fermi_level(twh[:, :, 0], twh[:, :, 1], P.weight, n_el, P.kT)
+        oracle_rows["fermi_level"] = {"ms": (time.perf_counter() - t0) * 1e3,
+                                      "mu_diff": abs(mu_o - float(fr[0])),
+                                      "sample": "the same 491520 rule points, 1 thread"}
     if args.cluster_esps > 0:
         # cluster-sampled energy: balls of radius 1 bohr (33 grid points) around C2 nodes
         # taken as energy sampling points; the band energy of the merged ball nodes, then
@@ -317,6 +328,16 @@ def main():
               f"{fe_bytes / t_fe / 1e9:.0f} GB/s; mesh + location {t_mesh:.2f} s",
               file=sys.stderr, flush=True)
         mesh.close()
+        if cpu_rec is not None:
+            # the oracle's brute-force location and 4x4 solves on 100 sampled fine points
+            pts = np.random.default_rng(21).choice(npts5, 100, replace=False)
+            t0 = time.perf_counter()
+            ref_fe = O.fe_reconstruct(n5, esp5, tets5, vals5, pred5, points=pts)
+            t_o = time.perf_counter() - t0
+            err_fe = float(np.max(np.abs(od[:, pts].cpu().numpy() - ref_fe)) / np.max(np.abs(ref_fe)))
+            oracle_rows["fe_reconstruct"] = {"value": 100 / t_o, "unit": "fine points/s",
+                                             "max_rel_err_of_gpu": err_fe,
+                                             "sample": "100 seeded fine points, 1 thread"}
         # the potential of the next self-consistency step from the reconstructed density:
         # V = phi[rho + b] + u(rho) on the same 128^3 grid (periodic FFT Poisson solve with the
         # FD Laplacian, LDA exchange-correlation fused into its last pass)
@@ -345,6 +366,16 @@ def main():
             "frac_hbm_peak": pot_bytes / t_pot / 1e9 / HBM_PEAK_GBS}
         print(f"[bench] effective potential {t_pot * 1e6:.1f} us/call, "
               f"{pot_bytes / t_pot / 1e9:.0f} GB/s", file=sys.stderr, flush=True)
+        if cpu_rec is not None:
+            t0 = time.perf_counter()
+            ref_v, _, _, _ = O.effective_potential(rho5.cpu().numpy().reshape(128, 128, 128),
+                                                   bq.cpu().numpy().reshape(128, 128, 128), 0.5)
+            t_o = time.perf_counter() - t0
+            got_v = vpot.cpu().numpy().reshape(128, 128, 128)
+            oracle_rows["effective_potential"] = {
+                "value": npts5 / t_o, "unit": "grid points/s",
+                "max_rel_err_of_gpu": float(np.max(np.abs(got_v - ref_v)) / np.max(np.abs(ref_v))),
+                "sample": "the whole 128^3 grid, numpy FFT"}
         pot.close()
     if not args.no_plain:
         # per-node GPU baseline: the plain schedule on a seeded node sample
