@@ -624,27 +624,42 @@ def fe_locate(n, esp_center, tets, points):
     that contains it (closed: faces, edges and vertices included), -1 if none.
 
     A point x lies in the tetrahedron (v0, v1, v2, v3) when, with D the signed volume
-    det[v1-v0, v2-v0, v3-v0], each of the four volumes obtained by putting x in place of
-    one vertex has the sign of D or is zero.  All coordinates are integers, so the test
-    is exact.  Tetrahedra of zero volume hold no interior and are skipped.  Brute force
-    over all tetrahedra, a few points at a time."""
+    det[v1-v0, v2-v0, v3-v0], each of the four volumes D_i(x) obtained by putting x in
+    place of vertex i has the sign of D or is zero.  Tetrahedra of zero volume hold no
+    interior and are skipped.  D_i is affine in x; its coefficients are read off the
+    determinant itself at x = 0 and x = e_x, e_y, e_z (exact integers), and D_i at all
+    points is then one matrix product per tetrahedron block, exact in FP64 because every
+    value stays below 2^53 for grid coordinates below 2^16.  Brute force over all
+    tetrahedra."""
     X = esp_coords(n, esp_center)
     V = X[np.asarray(tets, dtype=np.int64)]                  # (T, 4, 3)
     D = _det3(V[:, 1] - V[:, 0], V[:, 2] - V[:, 0], V[:, 3] - V[:, 0])
     good = D != 0
     sgn = np.sign(D)
+
+    def volume_with(i, x):                                    # D_i at one point x (3,)
+        W = [V[:, j] if j != i else np.broadcast_to(x, V[:, 0].shape) for j in range(4)]
+        return _det3(W[1] - W[0], W[2] - W[0], W[3] - W[0])
+
+    coef = np.zeros((4, V.shape[0], 4), dtype=np.int64)       # (i, T, [c0, cx, cy, cz])
+    for i in range(4):
+        c0 = volume_with(i, np.zeros(3, dtype=np.int64))
+        coef[i, :, 0] = c0
+        for a in range(3):
+            e = np.zeros(3, dtype=np.int64)
+            e[a] = 1
+            coef[i, :, 1 + a] = volume_with(i, e) - c0
+    coef = coef * sgn[None, :, None]                          # orient: inside <=> all >= 0
     pts = np.asarray(points, dtype=np.int64)
+    P1 = np.hstack([np.ones((pts.shape[0], 1)), pts.astype(np.float64)])   # (P, 4)
     out = np.full(pts.shape[0], -1, dtype=np.int64)
-    step = max(1, (1 << 21) // max(1, V.shape[0]))
-    for s0 in range(0, pts.shape[0], step):
-        x = pts[s0:s0 + step, None, :]                           # (p, 1, 3)
-        inside = np.broadcast_to(good, (x.shape[0], V.shape[0])).copy()
+    step = max(1, (1 << 22) // max(1, pts.shape[0]))
+    for t0 in range(0, V.shape[0], step):
+        inside = np.broadcast_to(good[None, t0:t0 + step], (pts.shape[0], min(step, V.shape[0] - t0))).copy()
         for i in range(4):
-            W = [V[None, :, j] if j != i else x for j in range(4)]
-            Di = _det3(W[1] - W[0], W[2] - W[0], W[3] - W[0])
-            inside &= Di * sgn[None, :] >= 0
-        hit = inside.any(axis=1)
-        out[s0:s0 + step] = np.where(hit, inside.argmax(axis=1), -1)
+            inside &= (P1 @ coef[i, t0:t0 + step].T.astype(np.float64)) >= 0.0
+        hit = inside.any(axis=1) & (out < 0)
+        out[hit] = t0 + inside[hit].argmax(axis=1)
     return out
 
 
@@ -665,11 +680,13 @@ def fe_reconstruct(n, esp_center, tets, esp_values, predictor, points=None):
     X = esp_coords(n, esp_center).astype(np.float64)
     corr = vals - pred[:, np.asarray(esp_center, dtype=np.int64)]   # (F, M)
     out = pred[:, idx].copy()
-    for k in np.nonzero(loc >= 0)[0]:
-        t = np.asarray(tets[loc[k]], dtype=np.int64)
-        A = np.vstack([X[t].T, np.ones(4)])
-        lam = np.linalg.solve(A, np.append(xyz[k].astype(np.float64), 1.0))
-        out[:, k] += corr[:, t] @ lam
+    k = np.nonzero(loc >= 0)[0]
+    if k.size:
+        T = np.asarray(tets, dtype=np.int64)[loc[k]]                # (P, 4)
+        A = np.concatenate([np.transpose(X[T], (0, 2, 1)), np.ones((k.size, 1, 4))], axis=1)
+        rhs = np.hstack([xyz[k].astype(np.float64), np.ones((k.size, 1))])
+        lam = np.linalg.solve(A, rhs[:, :, None])[:, :, 0]          # (P, 4)
+        out[:, k] += np.einsum("fpi,pi->fp", corr[:, T], lam)
     return out
 
 
