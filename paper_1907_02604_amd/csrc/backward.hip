@@ -241,6 +241,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2, 2))) v
   const T kin = (T)(-0.5 / (h * h));
   const int B = 2 * P.box_m + 1, B3 = B * B * B;
   const double gomega = *P.grad_omega;
+  constexpr int VW = 16 / (int)sizeof(T);                    // points per 16-byte access
+  typedef T VT __attribute__((ext_vector_type(VW)));
   if (tid == 0) st.orth_tol = sizeof(T) == 4 ? 3.4526698300124393e-4 : 1.4901161193847656e-8;
 
   for (;;) {
@@ -326,19 +328,30 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2, 2))) v
       const double sn = (j + 1 < keff) ? st.scale[j + 1] : 0.0;
       const double sp = j > 0 ? st.scale[j - 1] : 0.0;
       const bool last = (j == keff - 1);
-      // pass A: the dot products the recurrence needs (FP64)
+      // pass A: the dot products the recurrence needs (FP64).  Every row involved starts
+      // 16-byte aligned and VW consecutive points of a basis row are adjacent in the
+      // point-blocked layout, so each lane takes VW points per 16-byte load; points past
+      // n read as zero.
       if (!last) {
         double d[5] = {0, 0, 0, 0, 0};
-        for (int p = tid; p < n; p += BLOCK) {
-          const double qb = (double)Q0[p];
-          const double qn = sn * (double)Wn[bidx(p, wbs)];
-          const double qc = sc_ * (double)Wc[bidx(p, wbs)];
-          const double qp = sp * (double)Wp[bidx(p, wbs)];
-          d[0] += qb * qn;
-          d[1] += qb * qc;
-          d[2] += qb * qp;
-          d[3] += qn * qc;
-          d[4] += qn * qp;
+        for (int p = tid * VW; p < n; p += BLOCK * VW) {
+          const VT q0 = *(const SGQ_G VT*)(Q0 + p);
+          const VT wn = *(const SGQ_G VT*)(Wn + bidx(p, wbs));
+          const VT wc = *(const SGQ_G VT*)(Wc + bidx(p, wbs));
+          const VT wp = *(const SGQ_G VT*)(Wp + bidx(p, wbs));
+#pragma unroll
+          for (int k = 0; k < VW; ++k) {
+            const bool in = p + k < n;
+            const double qb = in ? (double)q0[k] : 0.0;
+            const double qn = in ? sn * (double)wn[k] : 0.0;
+            const double qc = in ? sc_ * (double)wc[k] : 0.0;
+            const double qp = in ? sp * (double)wp[k] : 0.0;
+            d[0] += qb * qn;
+            d[1] += qb * qc;
+            d[2] += qb * qp;
+            d[3] += qn * qc;
+            d[4] += qn * qp;
+          }
         }
 #pragma unroll
         for (int c = 0; c < 5; ++c) {
@@ -365,20 +378,38 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2, 2))) v
         bs.sc[2] = bs.abar[j];
       }
       __syncthreads();
-      // pass B: ubar_j, the node dV cube, and the adjoint rows
+      // pass B: ubar_j, the node dV cube, and the adjoint rows (VW points per lane as in
+      // pass A; the padding past n, inside every row and cube, receives zeros)
       {
         const double ib = bs.sc[0], bb = bs.sc[1], ahat = bs.sc[2];
         const double al = st.alpha[j];
         const double bprev = j > 0 ? st.beta[j - 1] : 0.0;
-        for (int p = tid; p < n; p += BLOCK) {
-          const double qc = sc_ * (double)Wc[bidx(p, wbs)];
-          const double rb = last ? 0.0 : (double)Q0[p] * ib + bb * sn * (double)Wn[bidx(p, wbs)];
-          const double ub = rb + ahat * qc;
-          const double uj = (double)Uj[p];
-          Uj[p] = (T)ub;
-          Pq[p] = (T)((last ? 0.0 : (double)Pq[p]) + ub * qc);
-          Q1[p] = (T)((last ? 0.0 : (double)Q1[p]) - al * rb + ahat * uj);
-          if (j > 0) Q2[p] = (T)(-bprev * rb);
+        for (int p = tid * VW; p < n; p += BLOCK * VW) {
+          const VT wc = *(const SGQ_G VT*)(Wc + bidx(p, wbs));
+          const VT uj = *(const SGQ_G VT*)(Uj + p);
+          VT q0 = {}, wn = {}, pq = {}, q1 = {};
+          if (!last) {
+            q0 = *(const SGQ_G VT*)(Q0 + p);
+            wn = *(const SGQ_G VT*)(Wn + bidx(p, wbs));
+            pq = *(const SGQ_G VT*)(Pq + p);
+            q1 = *(const SGQ_G VT*)(Q1 + p);
+          }
+          VT o_u, o_p, o_q1, o_q2;
+#pragma unroll
+          for (int k = 0; k < VW; ++k) {
+            const bool in = p + k < n;
+            const double qc = sc_ * (double)wc[k];
+            const double rb = (double)q0[k] * ib + bb * sn * (double)wn[k];
+            const double ub = rb + ahat * qc;
+            o_u[k] = in ? (T)ub : (T)0;
+            o_p[k] = in ? (T)((double)pq[k] + ub * qc) : (T)0;
+            o_q1[k] = in ? (T)((double)q1[k] - al * rb + ahat * (double)uj[k]) : (T)0;
+            o_q2[k] = in ? (T)(-bprev * rb) : (T)0;
+          }
+          *(SGQ_G VT*)(Uj + p) = o_u;
+          *(SGQ_G VT*)(Pq + p) = o_p;
+          *(SGQ_G VT*)(Q1 + p) = o_q1;
+          if (j > 0) *(SGQ_G VT*)(Q2 + p) = o_q2;
         }
       }
       __syncthreads();

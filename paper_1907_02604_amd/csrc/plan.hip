@@ -676,11 +676,12 @@ static int ensure_backward(sgq_plan* p) {
   const int nq = p->prob.n_nodes;
   const size_t es = p->fp64 ? 8 : 4;
   const int nx = p->prob.n[0], ny = p->prob.n[1], nz = p->prob.n[2];
-  // node cubes of the per-node dV contributions
+  // node cubes of the per-node dV contributions, each rounded up to 4 values so that every
+  // cube starts 16-byte aligned (the reverse recurrence updates it with vector accesses)
   std::vector<int64_t> off(nq + 1, 0);
   for (int q = 0; q < nq; ++q) {
     int64_t n = p->h_hw[q] < 0 ? (int64_t)p->n_grid : (int64_t)std::pow(2 * p->h_hw[q] + 1, 3);
-    off[q + 1] = off[q] + n;
+    off[q + 1] = off[q] + (n + 3) / 4 * 4;
   }
   // gather lists: for every cell of the grid, the nodes (ascending) whose cube meets it
   const int C = gather_cell();
