@@ -414,10 +414,13 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2, 2))) v
       }
       __syncthreads();
       // pass C: qbar_j += H ubar_j (projector weights E h^3 chi.ubar_j for the scatter)
+      // (in the FP32 march the projector group's term is added plane by plane, as in the
+      // forward step, and the scatter then covers the remaining atoms)
       if (natoms > 0) projector_dots<T, BLOCK>(proj_E, st, pe, Uj, 64, 1.0, h3, B, B3);
-      apply_local<T, BLOCK, true>(P, st, V, Uj, 64, Q1, (T)1, kin, pe, B, false);
+      const bool fused = st.fuse && uses_march(st, BLOCK);
+      apply_local<T, BLOCK, true>(P, st, V, Uj, 64, Q1, (T)1, kin, pe, B, fused);
       __syncthreads();
-      apply_scatter<T, BLOCK>(P, st, pe, Q1, B, B3);
+      apply_scatter<T, BLOCK>(P, st, pe, Q1, B, B3, !fused);
       __syncthreads();
       const int t0 = r0;
       r0 = r1;

@@ -804,7 +804,13 @@ __device__ __noinline__ double stencil_march(int gnx, int gny, int gnz,
           if (own[k]) {
             const int p2 = tid + k * BLOCK;
             if (ACC) {
-              U[p2 + z * sxy] += u;
+              T add = u;
+              if (PROJ) {
+                SGQ_L T* cz = st.corr[z & 1];
+                add += cz[p2];
+                cz[p2] = (T)0;
+              }
+              U[p2 + z * sxy] += add;
             } else if (PROJ) {
               SGQ_L T* cz = st.corr[z & 1];
               U[p2 + z * sxy] = u + cz[p2];
@@ -877,10 +883,10 @@ __device__ __forceinline__ double apply_local(const LaunchParams& P, SGQ_L NodeS
                                               bool group) {
   if (st.periodic) return stencil_periodic<T, BLOCK, ACC>(st, V, v, vbs, U, s, kin);
   if (uses_march(st, BLOCK)) {
-    if constexpr (!ACC && NodeState<T, BLOCK>::kFuse) {
+    if constexpr (NodeState<T, BLOCK>::kFuse) {
       if (group && st.fuse)
-        return stencil_march<T, BLOCK, 5, false, true>(P.nx, P.ny, P.nz, st, V, v, vbs, U, s,
-                                                       kin, pe, B);
+        return stencil_march<T, BLOCK, 5, ACC, true>(P.nx, P.ny, P.nz, st, V, v, vbs, U, s,
+                                                     kin, pe, B);
     }
     return stencil_march<T, BLOCK, 5, ACC, false>(P.nx, P.ny, P.nz, st, V, v, vbs, U, s, kin,
                                                   pe, B);
