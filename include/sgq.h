@@ -155,8 +155,9 @@ int sgq_plan_set_schedule(sgq_plan* plan, int schedule);
  *   n_electrons, kT                 > 0; tol > 0: stop when |N(mu) - n_electrons| <=
  *                                   tol * n_electrons
  *   result      [3]         double  device out: mu, N(mu), number of Newton/bisection steps
- * Safeguarded Newton iteration on a bracket spanning every rule point by 60 kT, in one
- * workgroup with a fixed summation order (bitwise reproducible).  An electron count
+ * Safeguarded Newton iteration (at most 64 steps) on a bracket spanning every rule point by
+ * 60 kT; every step sums over the rule points on the whole device, in a fixed order (bitwise
+ * reproducible), through the plan's own small workspace.  An electron count
  * outside (0, 2 sum_q n_q sum_k w_k) latches SGQ_ERANGE (result = NaN), a non-finite rule
  * SGQ_ENONFINITE; both are read with sgq_plan_status.  Asynchronous on `stream`. */
 int sgq_fermi_level(sgq_plan* plan, const double* theta_w, const double* node_weight,

@@ -28,7 +28,7 @@ hipError_t launch_cluster_energy(const double* e_node, int nq, const int64_t* of
                                  int* status, hipStream_t s);
 hipError_t launch_fermi_level(const double* tw, const double* weight, int nq, int kmax,
                               double ne, double kT, double tol, double* out, int* status,
-                              hipStream_t s);
+                              double* ws, hipStream_t s);
 hipError_t launch_backward(const LaunchParams& P, bool fp64, int grid, int block, int kg,
                            hipStream_t s);
 hipError_t launch_backward_gather(const LaunchParams& P, bool fp64, const int32_t* cell_start,
@@ -90,6 +90,7 @@ struct sgq_plan {
   double* d_enode = nullptr;
   double* d_tri = nullptr;
   int32_t* d_trik = nullptr;
+  double* d_fermi = nullptr;   // Fermi-level state and per-workgroup partial sums
   // backward state (allocated on the first backward call)
   bool bwd_ready = false;
   int grid_bwd = 0;
@@ -275,6 +276,7 @@ extern "C" int sgq_plan_create(const sgq_problem* prob, const int64_t* center,
   e = e ? e : dalloc(p, &p->d_enode, (size_t)nq * 8);
   e = e ? e : dalloc(p, &p->d_tri, (size_t)nq * 2 * p->kmax * 8);
   e = e ? e : dalloc(p, &p->d_trik, (size_t)nq * 4);
+  e = e ? e : dalloc(p, &p->d_fermi, (size_t)(16 + 4 * kFermiBlocks) * 8);
   if (e != hipSuccess) {
     free_all(p);
     delete p;
@@ -471,7 +473,7 @@ extern "C" int sgq_fermi_level(sgq_plan* plan, const double* theta_w, const doub
   hipStream_t s = (hipStream_t)stream;
   HIP_OR_FAIL(hipSetDevice(plan->device));
   HIP_OR_FAIL(launch_fermi_level(theta_w, node_weight, plan->prob.n_nodes, plan->kmax, n_electrons,
-                                 kT, tol, result, plan->d_status, s));
+                                 kT, tol, result, plan->d_status, plan->d_fermi, s));
   plan->last = s;
   return SGQ_OK;
 }

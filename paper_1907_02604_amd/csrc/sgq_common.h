@@ -13,6 +13,9 @@
 namespace sgq {
 
 constexpr int kWave = 64;            // CDNA wavefront
+constexpr int kFermiBlocks = 512;    // Fermi-level passes: partial sums per pass
+constexpr int kFermiThreads = 256;   //   lanes per workgroup of a pass
+constexpr int kFermiSteps = 64;      //   Newton / bisection steps enqueued per call
 constexpr int kMaxDepth = 128;       // largest Lanczos depth K
 constexpr int kMaxNodeAtoms = 256;   // atoms whose projector box meets one node cube
 
