@@ -354,10 +354,11 @@ def main():
         f1.record(stream)
         stream.synchronize()
         t_pot = f0.elapsed_time(f1) * 1e-3 / reps
-        # five line passes: X forward reads rho and b and writes the complex grid (32 B), the
-        # Y, Z (solve) and Y inverse passes read and write it (32 B each), the X inverse pass
-        # reads it, reads rho and writes V (32 B)
-        pot_bytes = npts5 * 160
+        # five line passes over the half-spectrum complex grid (65 x 128 x 128, 16 B each): X
+        # forward reads rho and b and writes the grid, the Y, Z (solve) and Y inverse passes
+        # read and write it, the X inverse pass reads it and rho and writes V
+        cpts5 = (128 // 2 + 1) * 128 * 128
+        pot_bytes = npts5 * 32 + cpts5 * 16 * 8
         rec["effective_potential"] = {
             "workload": "128^3 grid, V = phi[rho + b] + u_xc(rho) from the reconstructed density "
                         "and Gaussian nuclear charges (Z = 2) at the lattice sites, FP64",

@@ -8,7 +8,9 @@
 // into LDS (the tile groups lines adjacent in x, or in y for the x axis, so that global
 // accesses are contiguous runs), runs a mixed-radix (4, 2, 3, 5) Stockham FFT on them in
 // LDS (one buffer: each stage reads its inputs into registers before writing), and writes
-// the lines back in place.  Five passes solve the problem:
+// the lines back in place.  The work grid holds the half spectrum along x (nx/2 + 1
+// complex columns): the X passes carry two real lines per complex transform.  Five passes
+// solve the problem:
 //   X forward, reading the real source rho + b;
 //   Y forward;
 //   Z forward, multiply by -4 pi / (N lambda(k)), Z inverse (one LDS tile, one HBM round
@@ -50,7 +52,7 @@ struct sgq_potential {
   int64_t npts = 0;
   double h = 1.0;
   AxisPlan axis[3];
-  double2* d_work = nullptr;    // complex grid, [z][y][x]
+  double2* d_work = nullptr;    // half-spectrum complex grid, [z][y][nx/2 + 1]
   double2* d_tw[3] = {};        // exp(-2 pi i m / n_a), m < n_a
   double* d_lam[3] = {};        // per-axis FD eigenvalues
 };
@@ -229,8 +231,9 @@ enum PassMode { kFwdReal = 0, kFwd = 1, kSolve = 2, kInv = 3, kInvReal = 4 };
 struct PassArgs {
   AxisPlan ap;
   int axis, tl, nx, ny, nz;
+  int nxc;               // complex row length of the work grid, nx/2 + 1
   int64_t npts;
-  double2* work;
+  double2* work;         // [nz][ny][nxc] complex
   const double2* tw;
   const double* src_a;   // kFwdReal: rho (or the source)
   const double* src_b;   // kFwdReal: b (optional)
@@ -245,125 +248,165 @@ struct PassArgs {
   double* exc;
 };
 
+// X passes (MODE kFwdReal, kInvReal): a tile is TL = 2 * pairs consecutive y lines at
+// fixed z.  Two real lines a, b travel as one complex line a + i b; forward, its transform Z
+// unpacks into the half spectra A(k) = (Z(k) + conj Z(N-k)) / 2 and B(k) = (Z(k) -
+// conj Z(N-k)) / 2i, k <= N/2; inverse, A + i B (continued to k > N/2 by conjugate
+// symmetry) transforms back to a + i b.  Y and Z passes (kFwd, kSolve, kInv): a tile is TL
+// consecutive complex columns.
 template <int MODE>
 __global__ __launch_bounds__(kPassBlock) void fft_pass_kernel(PassArgs a) {
   extern __shared__ double2 lds[];
+  constexpr bool XPASS = MODE == kFwdReal || MODE == kInvReal;
   const int N = a.ap.n, TL = a.tl;
-  double2* buf = lds;
-  double2* twl = lds + TL * N;   // the twiddle table, read by every stage
-  for (int m = threadIdx.x; m < N; m += blockDim.x) twl[m] = a.tw[m];
-  // tile -> base address, line stride, element stride, lines in this tile
-  int64_t base;
-  int64_t sl, sj;
-  int nl;
-  const int nx = a.nx, ny = a.ny;
-  const int64_t nxy = (int64_t)nx * ny;
-  int line0 = 0, fixed1 = 0;   // first line index along the tile axis, and the fixed coordinate
-  if (a.axis == 0) {           // lines along x; tile = TL consecutive y at fixed z
+  const int nx = a.nx, ny = a.ny, nxc = a.nxc;
+  const int64_t nxy = (int64_t)nx * ny, nxyc = (int64_t)nxc * ny;
+  const double sign = (MODE == kFwdReal || MODE == kFwd || MODE == kSolve) ? -1.0 : 1.0;
+  if constexpr (XPASS) {
+    const int pairs = TL / 2;
+    double2* buf = lds;
+    double2* twl = lds + pairs * N;
+    for (int m = threadIdx.x; m < N; m += blockDim.x) twl[m] = a.tw[m];
     const int tiles_y = (ny + TL - 1) / TL;
     const int z = blockIdx.x / tiles_y;
-    line0 = (blockIdx.x % tiles_y) * TL;
-    fixed1 = z;
-    nl = min(TL, ny - line0);
-    base = (int64_t)line0 * nx + z * nxy;
-    sl = nx;
-    sj = 1;
-  } else {                     // lines along y or z; tile = TL consecutive x
-    const int tiles_x = (nx + TL - 1) / TL;
-    const int other = blockIdx.x / tiles_x;   // z for the y axis, y for the z axis
-    line0 = (blockIdx.x % tiles_x) * TL;
-    fixed1 = other;
-    nl = min(TL, nx - line0);
-    if (a.axis == 1) {
-      base = line0 + other * nxy;
-      sj = nx;
-    } else {
-      base = line0 + (int64_t)other * nx;
-      sj = nxy;
-    }
-    sl = 1;
-  }
-  const int total = nl * N;
-  // load
-  for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
-    int l, j;
-    if (a.axis == 0) {
-      l = idx / N;
-      j = idx - l * N;
-    } else {
-      j = idx / nl;
-      l = idx - j * nl;
-    }
-    const int64_t g = base + l * sl + j * sj;
-    double2 v;
-    if constexpr (MODE == kFwdReal) v = make_double2(a.src_a[g] + (a.src_b ? a.src_b[g] : 0.0), 0.0);
-    else v = a.work[g];
-    buf[l * N + j] = v;
-  }
-  __syncthreads();
-  const double sign = (MODE == kFwdReal || MODE == kFwd || MODE == kSolve) ? -1.0 : 1.0;
-  lds_fft(buf, a.ap, nl, twl, sign);
-  if constexpr (MODE == kSolve) {
-    // lines along z at fixed (kx = line0 + l, ky = fixed1)
-    for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
-      const int l = idx / N, kz = idx - l * N;
-      const int kx = line0 + l, ky = fixed1;
-      double2 c = buf[l * N + kz];
-      if (kx == 0 && ky == 0 && kz == 0) {
-        if (a.mean) *a.mean = c.x / (double)a.npts;
-        c = make_double2(0.0, 0.0);
-      } else {
-        const double g = a.scale / (a.lx[kx] + a.ly[ky] + a.lz[kz]);
-        c = make_double2(c.x * g, c.y * g);
+    const int y0 = (blockIdx.x % tiles_y) * TL;
+    const int nl = min(TL, ny - y0);
+    const int np = (nl + 1) / 2;
+    const int64_t rbase = (int64_t)y0 * nx + z * nxy;     // real grid, line y0
+    const int64_t cbase = (int64_t)y0 * nxc + z * nxyc;   // complex grid, line y0
+    const int total = np * N;
+    if constexpr (MODE == kFwdReal) {
+      for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+        const int p = idx / N, j = idx - p * N;
+        const int64_t g0 = rbase + (int64_t)(2 * p) * nx + j;
+        const double re = a.src_a[g0] + (a.src_b ? a.src_b[g0] : 0.0);
+        double im = 0.0;
+        if (2 * p + 1 < nl) im = a.src_a[g0 + nx] + (a.src_b ? a.src_b[g0 + nx] : 0.0);
+        buf[p * N + j] = make_double2(re, im);
       }
-      buf[l * N + kz] = c;
+    } else {
+      const int half = N / 2;
+      for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+        const int p = idx / N, k = idx - p * N;
+        const bool lo = k <= half;
+        const int src = lo ? k : N - k;
+        const int64_t g0 = cbase + (int64_t)(2 * p) * nxc + src;
+        double2 A = a.work[g0];
+        double2 B = 2 * p + 1 < nl ? a.work[g0 + nxc] : make_double2(0.0, 0.0);
+        if (!lo) {
+          A.y = -A.y;
+          B.y = -B.y;
+        }
+        buf[p * N + k] = make_double2(A.x - B.y, A.y + B.x);   // A + i B
+      }
     }
     __syncthreads();
-    lds_fft(buf, a.ap, nl, twl, 1.0);
-  }
-  // store
-  for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
-    int l, j;
-    if (a.axis == 0) {
-      l = idx / N;
-      j = idx - l * N;
-    } else {
-      j = idx / nl;
-      l = idx - j * nl;
-    }
-    const int64_t g = base + l * sl + j * sj;
-    const double2 c = buf[l * N + j];
-    if constexpr (MODE == kInvReal) {
-      const double ph = c.x;
-      if (a.phi) a.phi[g] = ph;
-      if (a.v) {
-        double e = 0.0, u = 0.0;
-        if (a.rho) lda_xc(a.rho[g], e, u);
-        a.v[g] = ph + u;
-        if (a.exc) a.exc[g] = e;
+    lds_fft(buf, a.ap, np, twl, sign);
+    if constexpr (MODE == kFwdReal) {
+      const int ntot = np * nxc;
+      for (int idx = threadIdx.x; idx < ntot; idx += blockDim.x) {
+        const int p = idx / nxc, k = idx - p * nxc;
+        const double2 Zk = buf[p * N + k];
+        const double2 Zm = buf[p * N + (k == 0 ? 0 : N - k)];
+        // A = (Zk + conj Zm) / 2, B = (Zk - conj Zm) / 2i
+        const double2 A = make_double2(0.5 * (Zk.x + Zm.x), 0.5 * (Zk.y - Zm.y));
+        const double2 B = make_double2(0.5 * (Zk.y + Zm.y), -0.5 * (Zk.x - Zm.x));
+        const int64_t g0 = cbase + (int64_t)(2 * p) * nxc + k;
+        a.work[g0] = A;
+        if (2 * p + 1 < nl) a.work[g0 + nxc] = B;
       }
     } else {
-      a.work[g] = c;
+      for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+        const int p = idx / N, j = idx - p * N;
+        const double2 c = buf[p * N + j];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          if (2 * p + h >= nl) break;
+          const int64_t g = rbase + (int64_t)(2 * p + h) * nx + j;
+          const double ph = h == 0 ? c.x : c.y;
+          if (a.phi) a.phi[g] = ph;
+          if (a.v) {
+            double e = 0.0, u = 0.0;
+            if (a.rho) lda_xc(a.rho[g], e, u);
+            a.v[g] = ph + u;
+            if (a.exc) a.exc[g] = e;
+          }
+        }
+      }
+    }
+    return;
+  } else {
+    double2* buf = lds;
+    double2* twl = lds + TL * N;   // the twiddle table, read by every stage
+    for (int m = threadIdx.x; m < N; m += blockDim.x) twl[m] = a.tw[m];
+    // lines along y or z; tile = TL consecutive complex columns
+    const int tiles_x = (nxc + TL - 1) / TL;
+    const int other = blockIdx.x / tiles_x;   // z for the y axis, y for the z axis
+    const int line0 = (blockIdx.x % tiles_x) * TL;
+    const int nl = min(TL, nxc - line0);
+    int64_t base, sj;
+    if (a.axis == 1) {
+      base = line0 + other * nxyc;
+      sj = nxc;
+    } else {
+      base = line0 + (int64_t)other * nxc;
+      sj = nxyc;
+    }
+    const int total = nl * N;
+    for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+      const int j = idx / nl, l = idx - j * nl;
+      buf[l * N + j] = a.work[base + l + j * sj];
+    }
+    __syncthreads();
+    lds_fft(buf, a.ap, nl, twl, sign);
+    if constexpr (MODE == kSolve) {
+      // lines along z at fixed (kx = line0 + l, ky = other)
+      for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+        const int l = idx / N, kz = idx - l * N;
+        const int kx = line0 + l, ky = other;
+        double2 c = buf[l * N + kz];
+        if (kx == 0 && ky == 0 && kz == 0) {
+          if (a.mean) *a.mean = c.x / (double)a.npts;
+          c = make_double2(0.0, 0.0);
+        } else {
+          const double g = a.scale / (a.lx[kx] + a.ly[ky] + a.lz[kz]);
+          c = make_double2(c.x * g, c.y * g);
+        }
+        buf[l * N + kz] = c;
+      }
+      __syncthreads();
+      lds_fft(buf, a.ap, nl, twl, 1.0);
+    }
+    for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+      const int j = idx / nl, l = idx - j * nl;
+      a.work[base + l + j * sj] = buf[l * N + j];
     }
   }
 }
 
-int pass_tl(int n) { return std::max(1, std::min(16, kLdsComplex / std::max(n, 1))); }
+// Lines per tile: complex lines of the Y and Z passes, real lines (an even count) of the
+// X passes, so that every tile's LDS stays within kLdsComplex complex values.
+int pass_tl(int n, bool xpass) {
+  if (xpass) return 2 * std::max(1, std::min(8, kLdsComplex / std::max(n, 1)));
+  return std::max(1, std::min(16, kLdsComplex / std::max(n, 1)));
+}
 
 int pass_tiles(const sgq_potential* P, int axis, int tl) {
-  const int nx = P->n[0], ny = P->n[1], nz = P->n[2];
+  const int nxc = P->n[0] / 2 + 1, ny = P->n[1], nz = P->n[2];
   if (axis == 0) return ((ny + tl - 1) / tl) * nz;
-  if (axis == 1) return ((nx + tl - 1) / tl) * nz;
-  return ((nx + tl - 1) / tl) * ny;
+  if (axis == 1) return ((nxc + tl - 1) / tl) * nz;
+  return ((nxc + tl - 1) / tl) * ny;
 }
 
 template <int MODE>
 hipError_t launch_pass(const sgq_potential* P, int axis, PassArgs a, hipStream_t s) {
+  constexpr bool XPASS = MODE == kFwdReal || MODE == kInvReal;
   a.ap = P->axis[axis];
   a.axis = axis;
-  a.tl = pass_tl(P->axis[axis].n);
+  a.tl = pass_tl(P->axis[axis].n, XPASS);
   a.tw = P->d_tw[axis];
-  const size_t lds = sizeof(double2) * ((size_t)a.tl + 1) * P->axis[axis].n;
+  const size_t lines = XPASS ? (size_t)a.tl / 2 : (size_t)a.tl;
+  const size_t lds = sizeof(double2) * (lines + 1) * P->axis[axis].n;
   hipLaunchKernelGGL(fft_pass_kernel<MODE>, dim3(pass_tiles(P, axis, a.tl)), dim3(kPassBlock), lds,
                      s, a);
   return hipGetLastError();
@@ -377,6 +420,7 @@ hipError_t solve(const sgq_potential* P, const double* src_a, const double* src_
   a.nx = P->n[0];
   a.ny = P->n[1];
   a.nz = P->n[2];
+  a.nxc = P->n[0] / 2 + 1;
   a.npts = P->npts;
   a.work = P->d_work;
   a.src_a = src_a;
@@ -454,7 +498,7 @@ extern "C" int sgq_potential_create(const int32_t n[3], double h, sgq_potential*
   P->npts = npts;
   P->h = h;
   POT_HIP(hipGetDevice(&P->device));
-  POT_HIP(hipMalloc(&P->d_work, sizeof(double2) * npts));
+  POT_HIP(hipMalloc(&P->d_work, sizeof(double2) * (size_t)(n[0] / 2 + 1) * n[1] * n[2]));
   // sixth-order FD weights of the Laplacian (per axis, over h^2)
   const double w[4] = {-49.0 / 18.0, 3.0 / 2.0, -3.0 / 20.0, 1.0 / 90.0};
   for (int a = 0; a < 3; ++a) {
