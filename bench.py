@@ -428,8 +428,33 @@ def main():
                                       "FP32, dOmega/dV + dOmega/dR + dOmega/dE",
                           "alg_bytes": abytes, "achieved_GBs": abytes / ta / 1e9,
                           "frac_hbm_peak": abytes / ta / 1e9 / HBM_PEAK_GBS}
-        aplan.close()
         print(f"[bench] adjoint {Q4.n_nodes / ta:.1f} nodes/s", file=sys.stderr, flush=True)
+        # the same adjoint after a forward call that retained its bases (per-node storage of
+        # the Lanczos vectors and u_j rows, 141 GB here), so the backward skips the recompute
+        dV_re = dV.clone()
+        aplan.set_retain(True)
+        e4 = torch.empty(Q4.n_nodes, dtype=torch.float64, device="cuda")
+        om4 = torch.empty(1, dtype=torch.float64, device="cuda")
+        sgq.band_energy(aplan, v4, R4, E4, w4, Q4.mu, Q4.kT, sgq.SGQ_FREE, e4, om4)   # warm-up
+        sgq.band_energy_backward(aplan, v4, R4, E4, w4, Q4.mu, Q4.kT, sgq.SGQ_FREE, g, dV, dR, dE)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sgq.band_energy(aplan, v4, R4, E4, w4, Q4.mu, Q4.kT, sgq.SGQ_FREE, e4, om4)
+        torch.cuda.synchronize()
+        tf = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        sgq.band_energy_backward(aplan, v4, R4, E4, w4, Q4.mu, Q4.kT, sgq.SGQ_FREE, g, dV, dR, dE)
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - t0
+        assert aplan.status() == sgq.SGQ_OK
+        rec["adjoint"]["retained_bases"] = {
+            "value": Q4.n_nodes / tb, "unit": "nodes/s", "forward_s": tf, "backward_s": tb,
+            "forward_plus_backward_nodes_per_s": Q4.n_nodes / (tf + tb),
+            "forward_plus_recompute_backward_nodes_per_s": Q4.n_nodes / (tf + ta),
+            "dV_bitwise_equal_to_recompute": bool(torch.equal(dV, dV_re))}
+        aplan.close()
+        print(f"[bench] adjoint with retained bases {Q4.n_nodes / tb:.1f} nodes/s "
+              f"(forward + backward {Q4.n_nodes / (tf + tb):.1f} nodes/s)", file=sys.stderr, flush=True)
     if not args.no_uneven:
         # uneven batching: 20000 nodes with radii U{6..12} bohr and depths U{40..100} in one
         # persistent, autotuned, graph-replayed launch

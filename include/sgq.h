@@ -285,6 +285,20 @@ int sgq_poisson(sgq_potential* pot, const double* source, double* phi, double* m
 int sgq_effective_potential(sgq_potential* pot, const double* rho, const double* b, double* v,
                             double* phi, double* exc, double* mean, void* stream);
 
+/* Retained forward bases.  With enable != 0, the plan allocates per-node storage for every
+ * node's Lanczos basis and its u_j = H q_j rows (2 Nq K_max n_pad values of the storage
+ * precision: 141 GB for 8192 nodes of 33^3 points at K = 60 in FP32; SGQ_ENOMEM if they do
+ * not fit), and rho_quadrature / band_energy write them there.  The next
+ * band_energy_backward call with the same v_loc, atom_R and proj_E pointers then takes the
+ * retained bases instead of recomputing the forward Lanczos (bitwise the same result).
+ * The backward consumes them (it overwrites the u_j rows), and any other call that runs a
+ * forward launch (sgq_plan_autotune, the plain schedule) invalidates them; an invalid or
+ * mismatched retention falls back to the recompute.  The caller must not change the
+ * contents of those inputs between the forward and the backward call.  enable = 0 stops
+ * using the storage (it stays allocated until the plan is destroyed).  Returns SGQ_EINVAL
+ * for a null plan. */
+int sgq_plan_set_retain(sgq_plan* plan, int enable);
+
 /* Launch capture.  With enable != 0 (the default), rho_quadrature and band_energy on a
  * stream other than the legacy default stream capture their launch sequence (setup
  * kernels, the persistent Lanczos-Gauss kernel, the weighted sum) into a HIP graph on the

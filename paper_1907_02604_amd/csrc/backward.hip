@@ -261,7 +261,29 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2, 2))) v
       continue;
     }
     const int n = st.n, natoms = st.natoms;
-    const int keff = run_lanczos<T, BLOCK, KG>(P, st, W, Ubase, npad, P.depth[q]);
+    // the node's basis and u_j rows: retained by the forward call, or recomputed here
+    SGQ_G T* __restrict__ Wq = W;
+    SGQ_G T* __restrict__ Uq = Ubase;
+    int keff;
+    if (P.use_retained) {
+      const size_t roff = (size_t)q * kmax * npad;
+      Wq = (SGQ_G T*)P.Wr + roff;
+      Uq = (SGQ_G T*)P.Ur + roff;
+      keff = P.tri_k[q];
+      const double* tri = P.tri + (size_t)q * 2 * kmax;
+      for (int k = tid; k < keff; k += BLOCK) {
+        st.alpha[k] = tri[k];
+        if (k + 1 < keff) {
+          const double b = tri[kmax + k];
+          st.beta[k] = b;
+          st.scale[k + 1] = b > 0.0 ? 1.0 / b : 0.0;   // as the forward's sweep sets it
+        }
+      }
+      if (tid == 0) st.scale[0] = 1.0;
+      __syncthreads();
+    } else {
+      keff = run_lanczos<T, BLOCK, KG>(P, st, W, Ubase, npad, P.depth[q]);
+    }
     // ---- eigenvectors of T and the Daleckii-Krein adjoint
     for (int k = tid; k < keff; k += BLOCK) {
       st.ta[k] = st.alpha[k];
@@ -317,10 +339,10 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2, 2))) v
     int r0 = 0, r1 = 1, r2 = 2;
     for (int j = keff - 1; j >= 0; --j) {
       // rows of the point-blocked basis (block stride wbs)
-      const SGQ_G T* Wc = W + 64 * j;
-      const SGQ_G T* Wn = W + 64 * (j + 1);
-      const SGQ_G T* Wp = W + 64 * (j > 0 ? j - 1 : 0);
-      SGQ_G T* Uj = Ubase + (size_t)j * npad;      // u_j, replaced by ubar_j in pass B
+      const SGQ_G T* Wc = Wq + 64 * j;
+      const SGQ_G T* Wn = Wq + 64 * (j + 1);
+      const SGQ_G T* Wp = Wq + 64 * (j > 0 ? j - 1 : 0);
+      SGQ_G T* Uj = Uq + (size_t)j * npad;      // u_j, replaced by ubar_j in pass B
       SGQ_G T* Q0 = R[r0];
       SGQ_G T* Q1 = R[r1];
       SGQ_G T* Q2 = R[r2];
@@ -438,7 +460,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2, 2))) v
       constexpr int slots = room < NW ? room : NW;
       static_assert(slots >= 1, "the plane buffers must hold one wave's product");
       __syncthreads();
-      projector_gradients<T, BLOCK, MAXB>(proj_E, st, pe, W, wbs, Ubase, (int)npad, keff, h3, B,
+      projector_gradients<T, BLOCK, MAXB>(proj_E, st, pe, Wq, wbs, Uq, (int)npad, keff, h3, B,
                                           B3, (SGQ_L T*)&st.plane[0][0], slots, dEp, dRp);
     }
     for (int a = tid; a < natoms; a += BLOCK) natoms_out[1 + a] = st.atom[a];

@@ -44,7 +44,11 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2, 2))) v
       __syncthreads();
       continue;
     }
-    const int keff = run_lanczos<T, BLOCK, KG>(P, st, W, U, 0, K);
+    // with retention the node's basis and its u_j rows go to its own storage
+    const size_t roff = (size_t)q * P.kmax_out * P.npad;
+    const int keff = P.Wr ? run_lanczos<T, BLOCK, KG>(P, st, (SGQ_G T*)P.Wr + roff,
+                                                      (SGQ_G T*)P.Ur + roff, P.npad, K)
+                          : run_lanczos<T, BLOCK, KG>(P, st, W, U, 0, K);
     // ---- the tridiagonal of the node, for the Gauss-rule kernel
     double* tri = P.tri + (size_t)q * 2 * P.kmax_out;
     for (int k = tid; k < keff; k += BLOCK) {

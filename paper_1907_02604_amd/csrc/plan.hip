@@ -91,6 +91,12 @@ struct sgq_plan {
   double* d_tri = nullptr;
   int32_t* d_trik = nullptr;
   double* d_fermi = nullptr;   // Fermi-level state and per-workgroup partial sums
+  // retained forward bases (sgq_plan_set_retain): valid after a forward call with these
+  // input pointers, consumed by the next backward call
+  bool retain = false, ret_valid = false;
+  const void* ret_key[3] = {nullptr, nullptr, nullptr};
+  void* d_Wr = nullptr;
+  void* d_Ur = nullptr;
   // backward state (allocated on the first backward call)
   bool bwd_ready = false;
   int grid_bwd = 0;
@@ -356,6 +362,8 @@ static LaunchParams base_params(sgq_plan* p, const double* v_loc, const double* 
   P.kmax_out = p->kmax;
   P.tri = p->d_tri;
   P.tri_k = p->d_trik;
+  P.Wr = p->retain ? p->d_Wr : nullptr;
+  P.Ur = p->retain ? p->d_Ur : nullptr;
   return P;
 }
 
@@ -376,14 +384,24 @@ static hipError_t forward_sequence(sgq_plan* p, const LaunchParams& P, const dou
 // stream and not already being captured, the sequence is captured once into a HIP graph
 // and replayed while the call arguments (pointers, scalars, launch shape) are unchanged;
 // a changed argument re-captures it.  The sequence holds kernels only (no memset nodes).
+// After a forward launch with retention on, the retained bases belong to these inputs.
+static void mark_retained(sgq_plan* p, const double* v_loc, const LaunchParams& P) {
+  p->ret_valid = p->retain;
+  p->ret_key[0] = v_loc;
+  p->ret_key[1] = P.atom_R;
+  p->ret_key[2] = P.proj_E;
+}
+
 static int run_forward(sgq_plan* p, int kind, LaunchParams& P, const double* v_loc,
                        const double* node_weight, double* omega, hipStream_t s) {
+  p->ret_valid = false;
   HIP_OR_FAIL(hipSetDevice(p->device));
   p->last = s;
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
   if (s) HIP_OR_FAIL(hipStreamIsCapturing(s, &cap));
   if (!p->use_graph || !s || cap != hipStreamCaptureStatusNone) {
     HIP_OR_FAIL(forward_sequence(p, P, v_loc, node_weight, omega, s));
+    mark_retained(p, v_loc, P);
     return SGQ_OK;
   }
   auto bits = [](double d) { uint64_t u; std::memcpy(&u, &d, 8); return u; };
@@ -392,7 +410,7 @@ static int run_forward(sgq_plan* p, int kind, LaunchParams& P, const double* v_l
       (uint64_t)(uintptr_t)P.proj_E, (uint64_t)(uintptr_t)P.rho, (uint64_t)(uintptr_t)P.theta_w,
       (uint64_t)(uintptr_t)P.k_eff, (uint64_t)(uintptr_t)P.e_node,
       (uint64_t)(uintptr_t)node_weight, (uint64_t)(uintptr_t)omega, bits(P.mu), bits(P.kT),
-      (uint64_t)P.integrand, (uint64_t)p->block, (uint64_t)p->grid};
+      (uint64_t)P.integrand, (uint64_t)p->block, (uint64_t)p->grid, (uint64_t)(uintptr_t)P.Wr};
   GraphCache& g = p->graphs[kind];
   if (!g.exec || g.key != key) {
     if (g.exec) {
@@ -415,6 +433,7 @@ static int run_forward(sgq_plan* p, int kind, LaunchParams& P, const double* v_l
     g.key = key;
   }
   HIP_OR_FAIL(hipGraphLaunch(g.exec, s));
+  mark_retained(p, v_loc, P);
   return SGQ_OK;
 }
 
@@ -442,6 +461,7 @@ extern "C" int rho_quadrature(sgq_plan* plan, const double* v_loc, const double*
     }
     P.slot_stride = (size_t)plan->kmax * plan->npad;
     HIP_OR_FAIL(launch_setup(P, plan->fp64, v_loc, plan->d_v, plan->d_chi, plan->d_g0, plan->d_vmax, s));
+    plan->ret_valid = false;
     HIP_OR_FAIL(launch_plain(P, plan->fp64, plan->h_center.data(), plan->h_hw.data(),
                              plan->h_depth.data(), plan->d_plain, s));
     plan->last = s;
@@ -494,6 +514,30 @@ extern "C" int sgq_cluster_energy(sgq_plan* plan, const double* e_node,
                                     n_members, n_esp, esp_weight, fbar, energy, plan->d_status,
                                     s));
   plan->last = s;
+  return SGQ_OK;
+}
+
+extern "C" int sgq_plan_set_retain(sgq_plan* plan, int enable) {
+  if (!plan) return fail(SGQ_EINVAL, "plan is null");
+  plan->ret_valid = false;
+  if (enable && !plan->d_Wr) {
+    const size_t es = plan->fp64 ? 8 : 4;
+    const size_t bytes = (size_t)std::max(1, plan->prob.n_nodes) * plan->kmax * plan->npad * es;
+    HIP_OR_FAIL(hipSetDevice(plan->device));
+    hipError_t e = dalloc(plan, &plan->d_Wr, bytes);
+    e = e ? e : dalloc(plan, &plan->d_Ur, bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      if (plan->d_Wr) {
+        (void)hipFree(plan->d_Wr);
+        plan->allocs.erase(std::remove(plan->allocs.begin(), plan->allocs.end(), plan->d_Wr),
+                           plan->allocs.end());
+      }
+      plan->d_Wr = plan->d_Ur = nullptr;
+      return fail(SGQ_ENOMEM, std::string("retained bases: ") + hipGetErrorString(e));
+    }
+  }
+  plan->retain = enable != 0;
   return SGQ_OK;
 }
 
@@ -579,6 +623,7 @@ extern "C" int sgq_plan_autotune(sgq_plan* plan, const double* v_loc, const doub
   if (st != SGQ_OK) return st;
   if (sample_nodes < 1) return fail(SGQ_EINVAL, "sample_nodes must be >= 1");
   HIP_OR_FAIL(hipSetDevice(plan->device));
+  plan->ret_valid = false;   // the timing launches overwrite sampled nodes' retained bases
   hipStream_t s = (hipStream_t)stream;
   const int nq = plan->prob.n_nodes;
   std::vector<std::pair<int, int>> cand;
@@ -790,6 +835,11 @@ extern "C" int band_energy_backward(sgq_plan* plan, const double* v_loc, const d
   P.node_atoms = plan->d_node_atoms;
   P.dE_part = plan->d_dEp;
   P.dR_part = plan->d_dRp;
+  // the bases retained by the last forward call, when it had these inputs (the backward
+  // overwrites their u_j rows, so they serve one backward call)
+  P.use_retained = plan->retain && plan->ret_valid && plan->ret_key[0] == v_loc &&
+                   plan->ret_key[1] == atom_R && plan->ret_key[2] == proj_E;
+  plan->ret_valid = false;
   HIP_OR_FAIL(launch_setup(P, plan->fp64, v_loc, plan->d_v, plan->d_chi, plan->d_g0, plan->d_vmax, s));
   if (plan->prob.n_nodes > 0)
     HIP_OR_FAIL(launch_backward(P, plan->fp64, plan->grid_bwd, 256, plan->kg, s));

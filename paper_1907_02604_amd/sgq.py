@@ -27,7 +27,7 @@ EXPORTED = ("sgq_plan_create", "sgq_plan_destroy", "rho_quadrature", "band_energ
             "sgq_cluster_energy", "sgq_fe_mesh_create", "sgq_fe_mesh_destroy",
             "sgq_fe_reconstruct", "sgq_fe_mesh_location", "sgq_fe_mesh_info", "sgq_lda_xc",
             "sgq_potential_create", "sgq_potential_destroy", "sgq_poisson",
-            "sgq_effective_potential")
+            "sgq_effective_potential", "sgq_plan_set_retain")
 
 
 class SgqError(RuntimeError):
@@ -61,6 +61,7 @@ def _load():
         "sgq_gauss_rule_host": (I, [P, P, I, P, P]),
         "sgq_plan_set_schedule": (I, [P, I]),
         "sgq_plan_set_graph": (I, [P, I]),
+        "sgq_plan_set_retain": (I, [P, I]),
         "sgq_fermi_level": (I, [P, P, P, D, D, D, P, P]),
         "sgq_plan_autotune": (I, [P, P, P, P, D, D, I, P, ctypes.POINTER(ctypes.c_int32)]),
         "sgq_cluster_build": (I, [P, D, P, ctypes.c_int32, D, P, ctypes.c_int64, ctypes.c_int64,
@@ -184,6 +185,10 @@ class Plan:
     def set_schedule(self, schedule):
         """SGQ_SCHEDULE_BATCHED (default) or SGQ_SCHEDULE_PLAIN (per-node baseline)."""
         _check(_lib.sgq_plan_set_schedule(self._h, int(schedule)))
+
+    def set_retain(self, enable):
+        """sgq_plan_set_retain: keep the forward bases for the next backward call."""
+        _check(_lib.sgq_plan_set_retain(self._h, 1 if enable else 0))
 
     def set_graph(self, enable):
         """Capture and replay the forward launches as a HIP graph (default on)."""
