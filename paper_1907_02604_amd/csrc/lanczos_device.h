@@ -11,6 +11,9 @@ namespace sgq {
 
 constexpr int kMarchPad = 1700;  // padded plane (sx + 6)(sy + 6) of the plane march (sx <= 35)
 
+constexpr int kFnzBlocks = 2048;   // 64-point blocks tracked per node (cubes up to 131072 points)
+constexpr int kNoRow = 255;        // no nonzero row in the block yet
+
 template <typename T, int BLOCK>
 struct NodeState {
   static constexpr int NW = BLOCK / kWave;
@@ -48,6 +51,11 @@ struct NodeState {
   int pl_count[kPlanes];            // group atoms whose box crosses plane z
   unsigned char pl_atom[kPlanes][kPlaneAtoms];
   T corr[2][kCorr];                 // projector term of the next plane, by in-plane index
+  // first basis row with a nonzero value in each 64-point block (kNoRow: none yet); a
+  // Krylov vector is exactly zero outside the reach of the earlier ones, so the sweep skips
+  // the leading rows of a block that are still zero there
+  unsigned char fnz[kFnzBlocks];
+  int fnz_on;                       // the node's blocks fit fnz
 };
 
 // Whether the node's stencil runs as the plane march (the condition apply_local uses).
@@ -351,6 +359,9 @@ __device__ __noinline__ void fused_sweep_v(SGQ_L NodeState<T, BLOCK>& st,
   double n2 = 0.0;
   const int ngroups = (n + VEC - 1) / VEC;
   constexpr int STRIDE = BLOCK / G;
+  // A wave's point groups lie in one 64-point block (all of it, or half of it when a wave
+  // covers 32 points), so the first nonzero row of the block is uniform over the wave.
+  const bool skip = st.fnz_on;
   for (int pg0 = tid / G; pg0 < ngroups; pg0 += STRIDE * PU) {
     V qv[PU][KS];
     V sv[PU];
@@ -359,9 +370,13 @@ __device__ __noinline__ void fused_sweep_v(SGQ_L NodeState<T, BLOCK>& st,
       const int pg = pg0 + u * STRIDE;
       const int p0 = (pg < ngroups ? pg : 0) * VEC;
       const int voff = (bidx(p0, bs) + 64 * g) * ES;
+      // slots whose G rows all precede the block's first nonzero row hold zeros there
+      const int mfirst = skip ? (int)st.fnz[p0 >> 6] / G : 0;
 #pragma unroll
       for (int m = 0; m < KS; ++m) {
-        if (m < mlast)
+        if (m < mfirst)
+          qv[u][m] = (V)(T)0;
+        else if (m < mlast)
           qv[u][m] = buffer_load<V>(rw, voff, m * 64 * G * ES);
         else if (m == mlast)
           qv[u][m] = buffer_load<V>(rw, voff + dlast, m * 64 * G * ES);
@@ -387,11 +402,19 @@ __device__ __noinline__ void fused_sweep_v(SGQ_L NodeState<T, BLOCK>& st,
 #pragma unroll
       for (int k = 0; k < VEC; ++k)
         if (pg >= ngroups || p0 + k >= n) w[k] = (T)0;
+      bool nz = false;
       if (g == 0 && pg < ngroups) {
         *reinterpret_cast<SGQ_G V*>(dst + bidx(p0, bs)) = w;
 #pragma unroll
-        for (int k = 0; k < VEC; ++k) n2 += (double)w[k] * (double)w[k];
+        for (int k = 0; k < VEC; ++k) {
+          n2 += (double)w[k] * (double)w[k];
+          nz = nz || w[k] != (T)0;
+        }
       }
+      // record the first nonzero row j + 1 of the block (the same value from every wave
+      // that covers part of it; rows up to j stay zero there either way)
+      if (skip && __any(nz) && lane == 0 && st.fnz[(pg * VEC) >> 6] > j + 1)
+        st.fnz[(pg * VEC) >> 6] = (unsigned char)(j + 1);
 #pragma unroll
       for (int m = 0; m < KS; ++m) {
 #pragma unroll
@@ -945,10 +968,16 @@ __device__ int run_lanczos(const LaunchParams& P, SGQ_L NodeState<T, BLOCK>& st,
   const int wbytes = (int)((npad / 64) * (size_t)bs * sizeof(T));
   const int nzero = ((n + VEC - 1) / VEC) * VEC;
   for (int p = tid; p < nzero; p += BLOCK) W[bidx(p, bs)] = (T)0;
+  const int nblk = (int)(npad / 64);
+  const bool fnz_on = nblk <= kFnzBlocks;
+  if (fnz_on)
+    for (int b = tid; b < nblk; b += BLOCK) st.fnz[b] = (unsigned char)kNoRow;
   __syncthreads();
   if (tid == 0) {
     W[bidx(st.start, bs)] = (T)1;
     st.scale[0] = 1.0;
+    st.fnz_on = fnz_on;
+    if (fnz_on) st.fnz[st.start >> 6] = 0;   // row 0: the unit vector at the node
   }
   __syncthreads();
 
