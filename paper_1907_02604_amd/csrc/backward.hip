@@ -4,7 +4,9 @@
 //
 // Per node (one workgroup, persistent queue as in the forward kernel):
 //   1. the forward Lanczos run is recomputed from the start vector, keeping every
-//      u_j = H q_j (the start vector is the only checkpoint stored across calls);
+//      u_j = H q_j; or, when the forward call retained the node's basis and u_j rows
+//      (sgq_plan_set_retain), those are taken with alpha, beta and K_eff from the
+//      forward's tridiagonal buffer (the same values bit for bit);
 //   2. the eigenvectors S of T (wave-parallel QR sweeps, FP64, in LDS) give the
 //      Daleckii-Krein adjoint Tbar = 2 n_q Omegabar S (D o s1 s1^T) S^T, D the divided
 //      differences of F; alphabar_j = Tbar_jj, betabar_j = 2 Tbar_j,j+1;

@@ -18,6 +18,8 @@
 // with G_i = q_i . q_j the Gram column measured (exactly, in FP64) in the previous
 // sweep and G_j = 1.  Every Lanczos step therefore reads the stored basis once.
 // The Gauss rule comes from the FP64 tridiagonal eigensolver; quadrature in FP64.
+// A node's basis and u_j rows live in its workgroup's slot, or, with retained bases
+// (sgq_plan_set_retain), in per-node storage that the next backward call reads.
 #include "lanczos_device.h"
 
 namespace sgq {

@@ -332,8 +332,10 @@ __device__ __forceinline__ V buffer_load(__amdgpu_buffer_rsrc_t r, int voff, int
 // of a block.  A lane handles PU point groups per iteration, so one iteration issues
 // KS*PU vector loads before any of them is consumed.  Rows are addressed through a
 // buffer resource: one 32-bit lane offset plus a uniform per-slot offset.  Rows i > j of
-// the last slot are read from row j (finite data) and weighted zero.  src and dst are
-// row views with block strides sbs and bs.
+// the last slot are read from row j (finite data) and weighted zero.  Slots whose rows all
+// precede the block's first nonzero row (st.fnz) are not read: they hold exact zeros in
+// that block, which contribute nothing to w or D.  src and dst are row views with block
+// strides sbs and bs.
 template <typename T, int BLOCK, int KS, int PU, int VEC, int G = 4>
 __device__ __noinline__ void fused_sweep_v(SGQ_L NodeState<T, BLOCK>& st,
                                            const SGQ_G T* __restrict__ W, int bs, int wbytes,
