@@ -171,3 +171,10 @@ def test_potential_and_fe_reject_bad_arguments_on_the_host(sgq):
     big = np.array([70000, 2, 2], np.int32)
     assert lib.sgq_fe_mesh_create(big.ctypes.data, esp.ctypes.data, 4, ok.ctypes.data, 1, 2,
                                   ctypes.byref(h)) == sgq.SGQ_EINVAL
+
+
+def test_plan_switches_reject_a_null_plan(sgq):
+    lib = sgq.lib()
+    assert lib.sgq_plan_set_retain(None, 1) == sgq.SGQ_EINVAL
+    assert lib.sgq_plan_set_graph(None, 1) == sgq.SGQ_EINVAL
+    assert lib.sgq_plan_set_schedule(None, 0) == sgq.SGQ_EINVAL
