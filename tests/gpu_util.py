@@ -40,6 +40,31 @@ def gpu_rho(prob, want_rule=False, precision=None):
     return out
 
 
+def gpu_rho_bench_launch(prob, tune_nodes=2048):
+    """rho of `prob` in the launch configuration the benchmark times: the autotuned shape,
+    on a side stream, captured into a HIP graph on the first call and replayed on the
+    second (the replay's result is returned).  Returns (rho, k_eff, status, shape)."""
+    from paper_1907_02604_amd import sgq
+    plan = sgq.Plan.from_problem(prob)
+    v, R, E, _ = sgq.device_inputs(prob)
+    side = torch.cuda.Stream()
+    shape = plan.autotune(v, R, E, prob.mu, prob.kT, sample_nodes=tune_nodes,
+                          stream=side.cuda_stream)
+    rho = torch.empty(prob.n_nodes, dtype=torch.float64, device="cuda")
+    ke = torch.zeros(prob.n_nodes, dtype=torch.int32, device="cuda")
+    for _ in range(2):
+        rho.fill_(-1.0)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(side):
+            sgq.rho_quadrature(plan, v, R, E, prob.mu, prob.kT, rho, None, ke,
+                               stream=side.cuda_stream)
+        side.synchronize()
+    status = plan.status()
+    out = (rho.cpu().numpy(), ke.cpu().numpy(), status, shape)
+    plan.close()
+    return out
+
+
 def gpu_energy(prob, kind, precision=None):
     from paper_1907_02604_amd import sgq
     prec = {"f64": sgq.SGQ_FP64, "f32": sgq.SGQ_FP32}[precision or prob.precision]

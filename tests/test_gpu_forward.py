@@ -5,7 +5,8 @@ import pytest
 import oracle as O
 from oracle_util import custom_problem, lin, smooth_random_potential
 from paper_1907_02604_amd import synth
-from gpu_util import announce, gpu_energy, gpu_rho, needs_gpu, oracle_rho, stratified_sample
+from gpu_util import (announce, gpu_energy, gpu_rho, gpu_rho_bench_launch, needs_gpu, oracle_rho,
+                      stratified_sample)
 
 pytestmark = [pytest.mark.gpu, needs_gpu]
 
@@ -46,10 +47,12 @@ def test_c2_fp32_and_fp64_paths():
 
 
 def test_c2_full_launch_sampled():
-    """The full 8192-node workload in one persistent launch; sampled against the oracle."""
+    """The full 8192-node workload in the benchmark's launch configuration (autotuned,
+    graph-replayed on a side stream); sampled against the oracle."""
     P = synth.make_problem(2)
-    announce("C2 fp32 8192 nodes")
-    rho, keff, st = gpu_rho(P)
+    announce("C2 fp32 8192 nodes, benchmark launch")
+    rho, keff, st, shape = gpu_rho_bench_launch(P)
+    print("C2 launch shape", shape)
     assert st == 0 and np.all(keff == 60)
     sample = np.random.default_rng(12).choice(P.n_nodes, 16, replace=False)
     ref, _ = oracle_rho(P, sample)
@@ -59,10 +62,12 @@ def test_c2_full_launch_sampled():
 
 
 def test_c3_uneven_full_launch_sampled():
-    """96^3, 20000 nodes with cube sides 25..49 and depths 40..100 in one launch."""
+    """96^3, 20000 nodes with cube sides 25..49 and depths 40..100 in one launch, in the
+    benchmark's launch configuration (autotuned, graph-replayed on a side stream)."""
     P = synth.make_problem(3)
-    announce("C3 fp32 20000 nodes")
-    rho, keff, st = gpu_rho(P)
+    announce("C3 fp32 20000 nodes, benchmark launch")
+    rho, keff, st, shape = gpu_rho_bench_launch(P)
+    print("C3 launch shape", shape)
     assert st == 0
     assert np.array_equal(keff, P.depth)
     sample = stratified_sample(P, 6, seed=13)

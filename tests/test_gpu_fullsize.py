@@ -10,7 +10,7 @@ import pytest
 import oracle as O
 from oracle_util import smooth_random_potential
 from paper_1907_02604_amd import synth
-from gpu_util import announce, needs_gpu, stratified_sample
+from gpu_util import announce, gpu_rho_bench_launch, needs_gpu, stratified_sample
 
 pytestmark = [pytest.mark.gpu, needs_gpu]
 
@@ -29,24 +29,19 @@ def test_dislocation_workload_all_65536_nodes():
     the autotuned launch: four stratified nodes against the oracle; the adjoint of all nodes
     equals the sum of the adjoints of the two halves of the node list (the gather over
     65536 node cubes against two gathers over 32768)."""
-    import torch
     from paper_1907_02604_amd import sgq
     P = synth.make_problem(5)
     assert P.n_nodes == 65536
-    plan = sgq.Plan.from_problem(P)
-    v, R, E, _ = sgq.device_inputs(P)
-    announce("C5 full: autotune")
-    plan.autotune(v, R, E, P.mu, P.kT, sample_nodes=2048)
-    rho = torch.empty(P.n_nodes, dtype=torch.float64, device="cuda")
-    announce("C5 full: forward, 65536 nodes")
-    sgq.rho_quadrature(plan, v, R, E, P.mu, P.kT, rho)
-    torch.cuda.synchronize()
-    assert plan.status() == sgq.SGQ_OK
+    announce("C5 full: forward, 65536 nodes, benchmark launch")
+    rho, _, st, shape = gpu_rho_bench_launch(P)
+    print("C5 launch shape", shape)
+    assert st == sgq.SGQ_OK
     sample = stratified_sample(P, 4, seed=31)
     ref, _ = O.rho_quadrature(P, nodes=sample)
-    err = O.normwise_rel_err(rho.cpu().numpy()[sample], ref)
+    err = O.normwise_rel_err(rho[sample], ref)
     print("C5 full forward sampled err", err)
     assert err < 1e-4
+    plan = sgq.Plan.from_problem(P)
     announce("C5 full: adjoint, 65536 nodes")
     full = _grad(P, plan, sgq.SGQ_FREE)
     plan.close()
