@@ -131,8 +131,8 @@ def main():
     ap.add_argument("--config", type=int, default=2, help=argparse.SUPPRESS)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the node set would shard by cost across GPUs; see the design notes).",
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(the node set would be dealt out by cost, one share per GPU).",
               file=sys.stderr)
         sys.exit(2)
 
