@@ -39,7 +39,7 @@ What it computes (paper: Sec. "Density Functional Theory"):
 Everything is float64 and written for readability, not speed: one node at a
 time, numpy array ops for the stencil, a library tridiagonal eigensolver.
 
-Readings where the paper is silent (each is listed in the design notes):
+Readings where the paper is silent:
 * H = -1/2 Lap_6 + V_loc + V_nl on the grid, where Lap_6 is the sixth-order
   central finite-difference Laplacian applied axis by axis (no cross terms);
 * node truncation: H_q = P_q H P_q on a cube of side 2R+1 centred at the node,
