@@ -50,7 +50,17 @@ Readings where the paper is silent:
   the norm drops by more than 1/sqrt(2); breakdown when beta <= tau * scale with
   scale = 9.0667/h^2 + max|V|, after which the rule has K_eff < K nodes and is exact;
 * integrands F: BAND F = lam*g; FREE (Mermin) F = lam*g + kT[g ln g + (1-g) ln(1-g)]
-  = mu*g - kT*softplus(-(lam-mu)/kT); GRAND F = -kT*softplus(-(lam-mu)/kT).
+  = mu*g - kT*softplus(-(lam-mu)/kT); GRAND F = -kT*softplus(-(lam-mu)/kT);
+* cluster sampling: N in the cluster average is the number of grid points of the ball,
+  the ball is closed with minimum-image distances, and membership is decided on the
+  integer squared distance against (r/h)^2 (1 + 1e-9);
+* corrector interpolation: linear shape functions on a tetrahedral mesh over the ESPs
+  (grid points, unwrapped coordinates); a point takes the lowest-numbered tetrahedron
+  holding it, zero-volume tetrahedra are skipped, points in none keep the predictor;
+* exchange-correlation: the Perdew-Wang (1992) unpolarised parametrisation of the
+  correlation energy, zero energy and potential where rho <= 0;
+* Poisson: the periodic problem with the Hamiltonian's FD Laplacian, the mean of the
+  source removed (and reported), phi of zero mean.
 """
 from __future__ import annotations
 
