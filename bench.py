@@ -115,6 +115,9 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--plain-nodes", type=int, default=32)
     ap.add_argument("--adjoint-nodes", type=int, default=8192)
+    ap.add_argument("--retain-gb", type=float, default=160.0,
+                    help="retention budget of the dislocation sample's checkpointed adjoint "
+                         "(GB of HBM for the Lanczos bases of its costliest nodes; 0: skip)")
     ap.add_argument("--dislocation-nodes", type=int, default=8192,
                     help="nodes of the dislocation-shaped sample (128^3 screw lattice, K=80): "
                          "forward and adjoint; 0 skips it")
@@ -533,6 +536,47 @@ def main():
                         "achieved_GBs": b5 / t5 / 1e9, "frac_hbm_peak": b5 / t5 / 1e9 / HBM_PEAK_GBS,
                         "launch": {"lanes_per_node": shape5[0], "workgroups_per_cu": shape5[1]}},
             "adjoint": {"value": Q5.n_nodes / tb5, "unit": "nodes/s", "s": tb5}}
+        if args.retain_gb > 0:
+            # the adjoint with checkpointed Lanczos vectors: the forward keeps the bases and
+            # u_j rows of the costliest nodes that fit in the budget, and the backward
+            # recomputes only the others
+            free_b, _ = torch.cuda.mem_get_info()
+            budget = int(min(args.retain_gb * 1e9, free_b - 24e9))
+            try:
+                n_ret = dplan.set_retain(True, max_bytes=budget) if budget > 0 else 0
+            except sgq.SgqError as err:
+                n_ret = 0
+                print(f"[bench] no checkpointed adjoint: {err}", file=sys.stderr, flush=True)
+            if n_ret > 0:
+                dV5_re = dV5.clone()
+                e5 = torch.empty(Q5.n_nodes, dtype=torch.float64, device="cuda")
+                om5 = torch.empty(1, dtype=torch.float64, device="cuda")
+                sgq.band_energy(dplan, v5, R5, E5, w5, Q5.mu, Q5.kT, sgq.SGQ_FREE, e5, om5)
+                sgq.band_energy_backward(dplan, v5, R5, E5, w5, Q5.mu, Q5.kT, sgq.SGQ_FREE, g5,
+                                         dV5, dR5, dE5)   # warm-up pair
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                sgq.band_energy(dplan, v5, R5, E5, w5, Q5.mu, Q5.kT, sgq.SGQ_FREE, e5, om5)
+                torch.cuda.synchronize()
+                tf5 = time.perf_counter() - t0
+                t0 = time.perf_counter()
+                sgq.band_energy_backward(dplan, v5, R5, E5, w5, Q5.mu, Q5.kT, sgq.SGQ_FREE, g5,
+                                         dV5, dR5, dE5)
+                torch.cuda.synchronize()
+                tc5 = time.perf_counter() - t0
+                assert dplan.status() == sgq.SGQ_OK
+                rec["dislocation"]["adjoint"]["checkpointed"] = {
+                    "value": Q5.n_nodes / tc5, "unit": "nodes/s", "s": tc5,
+                    "retained_nodes": n_ret, "budget_GB": budget / 1e9,
+                    "forward_s": tf5, "forward_plus_backward_nodes_per_s": Q5.n_nodes / (tf5 + tc5),
+                    "forward_plus_recompute_backward_nodes_per_s": Q5.n_nodes / (t5 + tb5),
+                    # the forward ran with the autotuned lanes per node, the recompute with
+                    # the backward's 256: the two gradients differ by FP32 rounding only
+                    "dV_normwise_rel_diff_vs_recompute":
+                        float((dV5 - dV5_re).abs().max() / dV5_re.abs().max())}
+                print(f"[bench] dislocation checkpointed adjoint {Q5.n_nodes / tc5:.1f} nodes/s "
+                      f"({n_ret} of {Q5.n_nodes} nodes retained)", file=sys.stderr, flush=True)
+            dplan.set_retain(False)
         dplan.close()
         print(f"[bench] dislocation fwd {Q5.n_nodes / t5:.1f} adj {Q5.n_nodes / tb5:.1f} nodes/s",
               file=sys.stderr, flush=True)

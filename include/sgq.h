@@ -285,19 +285,26 @@ int sgq_poisson(sgq_potential* pot, const double* source, double* phi, double* m
 int sgq_effective_potential(sgq_potential* pot, const double* rho, const double* b, double* v,
                             double* phi, double* exc, double* mean, void* stream);
 
-/* Retained forward bases.  With enable != 0, the plan allocates per-node storage for every
- * node's Lanczos basis and its u_j = H q_j rows (2 Nq K_max n_pad values of the storage
- * precision: 141 GB for 8192 nodes of 33^3 points at K = 60 in FP32; SGQ_ENOMEM if they do
- * not fit), and rho_quadrature / band_energy write them there.  The next
- * band_energy_backward call with the same v_loc, atom_R and proj_E pointers then takes the
- * retained bases instead of recomputing the forward Lanczos (bitwise the same result).
- * The backward consumes them (it overwrites the u_j rows), and any other call that runs a
- * forward launch (sgq_plan_autotune, the plain schedule) invalidates them; an invalid or
- * mismatched retention falls back to the recompute.  The caller must not change the
- * contents of those inputs between the forward and the backward call.  enable = 0 stops
- * using the storage (it stays allocated until the plan is destroyed).  Returns SGQ_EINVAL
- * for a null plan. */
-int sgq_plan_set_retain(sgq_plan* plan, int enable);
+/* Retained forward bases (checkpointed Lanczos vectors for the adjoint, Eq. eq:free_cg).
+ * With enable != 0 the plan allocates storage for the Lanczos basis and the u_j = H q_j
+ * rows of R nodes, 2 K_max n_pad values of the storage precision per node (17.2 MB for
+ * 33^3 points at K = 60 in FP32; 141 GB for 8192 such nodes).  max_bytes = 0 retains every
+ * node (R = Nq); max_bytes > 0 retains the R = min(Nq, max_bytes / per-node bytes) nodes
+ * that are costliest to recompute, n (3K + K(K+1)/2) from the front of the plan's queue.
+ * rho_quadrature / band_energy then write those nodes' rows there.  The next
+ * band_energy_backward call with the same v_loc, atom_R and proj_E pointers takes the
+ * retained rows of those nodes instead of recomputing their forward Lanczos and recomputes
+ * the others.  The result is bitwise the full recompute's when the forward ran with 256
+ * lanes per node, the backward's own launch shape; after another autotuned shape the
+ * retained rows differ from a recompute by rounding only.  The backward consumes them (it overwrites the
+ * u_j rows), and any other call that runs a forward launch (sgq_plan_autotune, the plain
+ * schedule) invalidates them; an invalid or mismatched retention falls back to the
+ * recompute.  The caller must not change the contents of those inputs between the forward
+ * and the backward call.  Every call first waits for the device and frees the storage a
+ * previous call allocated; enable = 0 stops there.  n_retained [1] (optional, host) receives
+ * R.  Returns SGQ_EINVAL for a null plan, max_bytes < 0, or a max_bytes below one node's
+ * rows; SGQ_ENOMEM when the storage does not fit (retention is then off). */
+int sgq_plan_set_retain(sgq_plan* plan, int enable, int64_t max_bytes, int64_t* n_retained);
 
 /* Launch capture.  With enable != 0 (the default), rho_quadrature and band_energy on a
  * stream other than the legacy default stream capture their launch sequence (setup

@@ -5,8 +5,9 @@
 // Per node (one workgroup, persistent queue as in the forward kernel):
 //   1. the forward Lanczos run is recomputed from the start vector, keeping every
 //      u_j = H q_j; or, when the forward call retained the node's basis and u_j rows
-//      (sgq_plan_set_retain), those are taken with alpha, beta and K_eff from the
-//      forward's tridiagonal buffer (the same values bit for bit);
+//      (sgq_plan_set_retain, for all nodes or the costliest ones within a byte limit),
+//      those are taken with alpha, beta and K_eff from the forward's tridiagonal buffer
+//      (the same values bit for bit);
 //   2. the eigenvectors S of T (wave-parallel QR sweeps, FP64, in LDS) give the
 //      Daleckii-Krein adjoint Tbar = 2 n_q Omegabar S (D o s1 s1^T) S^T, D the divided
 //      differences of F; alphabar_j = Tbar_jj, betabar_j = 2 Tbar_j,j+1;
@@ -267,8 +268,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2, 2))) v
     SGQ_G T* __restrict__ Wq = W;
     SGQ_G T* __restrict__ Uq = Ubase;
     int keff;
-    if (P.use_retained) {
-      const size_t roff = (size_t)q * kmax * npad;
+    const int rs = P.use_retained ? P.ret_slot[q] : -1;
+    if (rs >= 0) {
+      const size_t roff = (size_t)rs * kmax * npad;
       Wq = (SGQ_G T*)P.Wr + roff;
       Uq = (SGQ_G T*)P.Ur + roff;
       keff = P.tri_k[q];

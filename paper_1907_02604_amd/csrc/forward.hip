@@ -18,8 +18,8 @@
 // with G_i = q_i . q_j the Gram column measured (exactly, in FP64) in the previous
 // sweep and G_j = 1.  Every Lanczos step therefore reads the stored basis once.
 // The Gauss rule comes from the FP64 tridiagonal eigensolver; quadrature in FP64.
-// A node's basis and u_j rows live in its workgroup's slot, or, with retained bases
-// (sgq_plan_set_retain), in per-node storage that the next backward call reads.
+// A node's basis and u_j rows live in its workgroup's slot, or, for a node given retained
+// storage (sgq_plan_set_retain), in that storage, which the next backward call reads.
 #include "lanczos_device.h"
 
 namespace sgq {
@@ -46,11 +46,12 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2, 2))) v
       __syncthreads();
       continue;
     }
-    // with retention the node's basis and its u_j rows go to its own storage
-    const size_t roff = (size_t)q * P.kmax_out * P.npad;
-    const int keff = P.Wr ? run_lanczos<T, BLOCK, KG>(P, st, (SGQ_G T*)P.Wr + roff,
-                                                      (SGQ_G T*)P.Ur + roff, P.npad, K)
-                          : run_lanczos<T, BLOCK, KG>(P, st, W, U, 0, K);
+    // a retained node's basis and its u_j rows go to its own storage
+    const int rs = P.Wr ? P.ret_slot[q] : -1;
+    const size_t roff = (size_t)(rs < 0 ? 0 : rs) * P.kmax_out * P.npad;
+    const int keff = rs >= 0 ? run_lanczos<T, BLOCK, KG>(P, st, (SGQ_G T*)P.Wr + roff,
+                                                         (SGQ_G T*)P.Ur + roff, P.npad, K)
+                             : run_lanczos<T, BLOCK, KG>(P, st, W, U, 0, K);
     // ---- the tridiagonal of the node, for the Gauss-rule kernel
     double* tri = P.tri + (size_t)q * 2 * P.kmax_out;
     for (int k = tid; k < keff; k += BLOCK) {

@@ -97,6 +97,8 @@ struct sgq_plan {
   const void* ret_key[3] = {nullptr, nullptr, nullptr};
   void* d_Wr = nullptr;
   void* d_Ur = nullptr;
+  int32_t* d_ret_slot = nullptr;   // [Nq] place of each node in the retained storage, or -1
+  int64_t ret_nodes = 0;
   // backward state (allocated on the first backward call)
   bool bwd_ready = false;
   int grid_bwd = 0;
@@ -364,6 +366,7 @@ static LaunchParams base_params(sgq_plan* p, const double* v_loc, const double* 
   P.tri_k = p->d_trik;
   P.Wr = p->retain ? p->d_Wr : nullptr;
   P.Ur = p->retain ? p->d_Ur : nullptr;
+  P.ret_slot = p->retain ? p->d_ret_slot : nullptr;
   return P;
 }
 
@@ -410,7 +413,8 @@ static int run_forward(sgq_plan* p, int kind, LaunchParams& P, const double* v_l
       (uint64_t)(uintptr_t)P.proj_E, (uint64_t)(uintptr_t)P.rho, (uint64_t)(uintptr_t)P.theta_w,
       (uint64_t)(uintptr_t)P.k_eff, (uint64_t)(uintptr_t)P.e_node,
       (uint64_t)(uintptr_t)node_weight, (uint64_t)(uintptr_t)omega, bits(P.mu), bits(P.kT),
-      (uint64_t)P.integrand, (uint64_t)p->block, (uint64_t)p->grid, (uint64_t)(uintptr_t)P.Wr};
+      (uint64_t)P.integrand, (uint64_t)p->block, (uint64_t)p->grid, (uint64_t)(uintptr_t)P.Wr,
+      (uint64_t)(uintptr_t)P.Ur, (uint64_t)(uintptr_t)P.ret_slot};
   GraphCache& g = p->graphs[kind];
   if (!g.exec || g.key != key) {
     if (g.exec) {
@@ -517,27 +521,60 @@ extern "C" int sgq_cluster_energy(sgq_plan* plan, const double* e_node,
   return SGQ_OK;
 }
 
-extern "C" int sgq_plan_set_retain(sgq_plan* plan, int enable) {
+// Frees the retained storage.
+static void release_retained(sgq_plan* p) {
+  for (void** a : {&p->d_Wr, &p->d_Ur}) {
+    if (!*a) continue;
+    (void)hipFree(*a);
+    p->allocs.erase(std::remove(p->allocs.begin(), p->allocs.end(), *a), p->allocs.end());
+    *a = nullptr;
+  }
+  p->retain = false;
+  p->ret_nodes = 0;
+}
+
+extern "C" int sgq_plan_set_retain(sgq_plan* plan, int enable, int64_t max_bytes,
+                                   int64_t* n_retained) {
   if (!plan) return fail(SGQ_EINVAL, "plan is null");
+  if (n_retained) *n_retained = 0;
+  if (max_bytes < 0) return fail(SGQ_EINVAL, "max_bytes < 0");
   plan->ret_valid = false;
-  if (enable && !plan->d_Wr) {
-    const size_t es = plan->fp64 ? 8 : 4;
-    const size_t bytes = (size_t)std::max(1, plan->prob.n_nodes) * plan->kmax * plan->npad * es;
-    HIP_OR_FAIL(hipSetDevice(plan->device));
-    hipError_t e = dalloc(plan, &plan->d_Wr, bytes);
-    e = e ? e : dalloc(plan, &plan->d_Ur, bytes);
+  HIP_OR_FAIL(hipSetDevice(plan->device));
+  HIP_OR_FAIL(hipDeviceSynchronize());   // no launch may still read the storage or its table
+  release_retained(plan);
+  if (!enable) return SGQ_OK;
+  const int64_t nq = plan->prob.n_nodes;
+  const size_t es = plan->fp64 ? 8 : 4;
+  const size_t row_set = (size_t)plan->kmax * plan->npad * es;   // one node's basis (or U rows)
+  int64_t m = nq;
+  if (max_bytes > 0) m = std::min<int64_t>(nq, (int64_t)((size_t)max_bytes / (2 * row_set)));
+  if (nq > 0 && m < 1)
+    return fail(SGQ_EINVAL, "max_bytes holds no node's retained rows (" +
+                                std::to_string(2 * row_set) + " bytes per node)");
+  if (nq > 0) {
+    if (!plan->d_ret_slot) {
+      hipError_t e = dalloc(plan, &plan->d_ret_slot, sizeof(int32_t) * (size_t)nq);
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(SGQ_ENOMEM, std::string("retained-node table: ") + hipGetErrorString(e));
+      }
+    }
+    // the first m nodes of the cost-sorted queue, the costliest to recompute
+    std::vector<int32_t> slot((size_t)nq, -1);
+    for (int64_t i = 0; i < m; ++i) slot[(size_t)plan->h_order[(size_t)i]] = (int32_t)i;
+    HIP_OR_FAIL(hipMemcpy(plan->d_ret_slot, slot.data(), sizeof(int32_t) * (size_t)nq,
+                          hipMemcpyHostToDevice));
+    hipError_t e = dalloc(plan, &plan->d_Wr, (size_t)m * row_set);
+    e = e ? e : dalloc(plan, &plan->d_Ur, (size_t)m * row_set);
     if (e != hipSuccess) {
       (void)hipGetLastError();
-      if (plan->d_Wr) {
-        (void)hipFree(plan->d_Wr);
-        plan->allocs.erase(std::remove(plan->allocs.begin(), plan->allocs.end(), plan->d_Wr),
-                           plan->allocs.end());
-      }
-      plan->d_Wr = plan->d_Ur = nullptr;
+      release_retained(plan);
       return fail(SGQ_ENOMEM, std::string("retained bases: ") + hipGetErrorString(e));
     }
   }
-  plan->retain = enable != 0;
+  plan->retain = true;
+  plan->ret_nodes = m;
+  if (n_retained) *n_retained = m;
   return SGQ_OK;
 }
 

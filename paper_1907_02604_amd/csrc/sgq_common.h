@@ -80,8 +80,9 @@ struct LaunchParams {
   double* dE_part;            // [Nq][kMaxNodeAtoms][4] node partials of dE
   int32_t* node_atoms;        // [Nq][1 + kMaxNodeAtoms]: count, then the node's atom ids
   double* zbuf;               // [slots][80*80] eigenvector matrix of T per backward slot
-  void* Wr;                   // retained bases [Nq][npad/64][kmax][64] (NULL: slots only)
-  void* Ur;                   // retained u_j = H q_j rows [Nq][kmax][npad]
+  void* Wr;                   // retained bases [R][npad/64][kmax][64] (NULL: slots only)
+  void* Ur;                   // retained u_j = H q_j rows [R][kmax][npad]
+  const int32_t* ret_slot;    // [Nq] each node's place among the R retained ones, or -1
   int use_retained;           // backward: take the retained basis instead of recomputing
 };
 

@@ -61,7 +61,7 @@ def _load():
         "sgq_gauss_rule_host": (I, [P, P, I, P, P]),
         "sgq_plan_set_schedule": (I, [P, I]),
         "sgq_plan_set_graph": (I, [P, I]),
-        "sgq_plan_set_retain": (I, [P, I]),
+        "sgq_plan_set_retain": (I, [P, I, ctypes.c_int64, P]),
         "sgq_fermi_level": (I, [P, P, P, D, D, D, P, P]),
         "sgq_plan_autotune": (I, [P, P, P, P, D, D, I, P, ctypes.POINTER(ctypes.c_int32)]),
         "sgq_cluster_build": (I, [P, D, P, ctypes.c_int32, D, P, ctypes.c_int64, ctypes.c_int64,
@@ -186,9 +186,14 @@ class Plan:
         """SGQ_SCHEDULE_BATCHED (default) or SGQ_SCHEDULE_PLAIN (per-node baseline)."""
         _check(_lib.sgq_plan_set_schedule(self._h, int(schedule)))
 
-    def set_retain(self, enable):
-        """sgq_plan_set_retain: keep the forward bases for the next backward call."""
-        _check(_lib.sgq_plan_set_retain(self._h, 1 if enable else 0))
+    def set_retain(self, enable, max_bytes=0):
+        """sgq_plan_set_retain: keep the forward bases for the next backward call, of every
+        node (max_bytes 0) or of the costliest nodes that fit in max_bytes.  Returns the
+        number of nodes retained."""
+        n = ctypes.c_int64(0)
+        _check(_lib.sgq_plan_set_retain(self._h, 1 if enable else 0, int(max_bytes),
+                                        ctypes.byref(n)))
+        return n.value
 
     def set_graph(self, enable):
         """Capture and replay the forward launches as a HIP graph (default on)."""

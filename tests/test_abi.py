@@ -175,6 +175,6 @@ def test_potential_and_fe_reject_bad_arguments_on_the_host(sgq):
 
 def test_plan_switches_reject_a_null_plan(sgq):
     lib = sgq.lib()
-    assert lib.sgq_plan_set_retain(None, 1) == sgq.SGQ_EINVAL
+    assert lib.sgq_plan_set_retain(None, 1, 0, None) == sgq.SGQ_EINVAL
     assert lib.sgq_plan_set_graph(None, 1) == sgq.SGQ_EINVAL
     assert lib.sgq_plan_set_schedule(None, 0) == sgq.SGQ_EINVAL

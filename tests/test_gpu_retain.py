@@ -1,6 +1,7 @@
 """Retained forward bases (sgq_plan_set_retain): the backward that takes them gives bitwise
-the gradient of the backward that recomputes them, and the retention is consumed, keyed to
-the input pointers and invalidated by other forward launches."""
+the gradient of the backward that recomputes them, for every node or for the costliest
+nodes within a byte limit, and the retention is consumed, keyed to the input pointers and
+invalidated by other forward launches."""
 import numpy as np
 import pytest
 
@@ -86,3 +87,61 @@ def test_retention_is_keyed_to_the_inputs_and_invalidated():
     for a, b in zip(ref, got):
         assert np.array_equal(a, b)
     plan.close()
+
+
+def test_retention_within_a_byte_limit_keeps_the_costliest_nodes():
+    """Dislocation-shaped nodes (cubes 25^3..49^3, K = 80): a limit that holds a third of
+    the nodes' rows retains that many, the backward takes them and recomputes the rest, and
+    the gradient is bitwise the full recompute's.  A limit below one node is rejected."""
+    from paper_1907_02604_amd import sgq
+    P5 = synth.make_problem(5)
+    P = P5.subset(np.random.default_rng(5).choice(P5.n_nodes, 36, replace=False))
+    v, R, E, w = sgq.device_inputs(P)
+    announce("retain limit: recompute reference")
+    ref_plan = sgq.Plan.from_problem(P)
+    ref = _forward_backward(ref_plan, P, v, R, E, w)
+    ref_plan.close()
+    plan = sgq.Plan.from_problem(P)
+    npad = (max((2 * int(r) + 1) ** 3 for r in P.half_width) + 63) // 64 * 64
+    per_node = 2 * plan.kmax * npad * 4               # basis and u_j rows, FP32
+    with pytest.raises(sgq.SgqError):
+        plan.set_retain(True, max_bytes=per_node - 1)
+    budget = 12 * per_node + per_node // 2
+    assert plan.set_retain(True, max_bytes=budget) == 12
+    announce("retain limit: 12 of 36 nodes retained")
+    got = _forward_backward(plan, P, v, R, E, w)
+    for a, b, name in zip(ref, got, ("e_node", "dV", "dR", "dE")):
+        assert np.array_equal(a, b), name
+    assert plan.set_retain(True, max_bytes=10 ** 15) == P.n_nodes   # capped at the node count
+    assert plan.set_retain(False) == 0
+    announce("retain limit: retention off")
+    got = _forward_backward(plan, P, v, R, E, w)
+    for a, b in zip(ref, got):
+        assert np.array_equal(a, b)
+    plan.close()
+
+
+def test_retained_rows_of_another_launch_shape_agree_within_rounding(monkeypatch):
+    """A forward with 512 lanes per node (an autotuned shape) sums its sweeps in another
+    order than the backward's 256-lane recompute, so its retained rows differ by rounding:
+    the gradient agrees with the recompute's to the FP32 bar, 1e-4 normwise."""
+    from paper_1907_02604_amd import sgq
+    P = synth.make_problem(4)
+    P = P.subset(np.random.default_rng(6).choice(P.n_nodes, 48, replace=False))
+    v, R, E, w = sgq.device_inputs(P)
+    announce("retain shape: recompute reference (256 lanes)")
+    ref_plan = sgq.Plan.from_problem(P)
+    ref = _forward_backward(ref_plan, P, v, R, E, w)
+    ref_plan.close()
+    monkeypatch.setenv("SGQ_BLOCK", "512")         # the autotuner's 512 lanes x 1 per CU
+    monkeypatch.setenv("SGQ_WG_PER_CU", "1")
+    plan = sgq.Plan.from_problem(P)
+    monkeypatch.delenv("SGQ_BLOCK")
+    monkeypatch.delenv("SGQ_WG_PER_CU")
+    plan.set_retain(True)
+    announce("retain shape: 512-lane forward, retained backward")
+    got = _forward_backward(plan, P, v, R, E, w)
+    plan.close()
+    for a, b, name in zip(ref, got, ("e_node", "dV", "dR", "dE")):
+        err = np.max(np.abs(a - b)) / np.max(np.abs(a))
+        assert err <= 1e-4, (name, err)
