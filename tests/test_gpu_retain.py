@@ -145,3 +145,32 @@ def test_retained_rows_of_another_launch_shape_agree_within_rounding(monkeypatch
     for a, b, name in zip(ref, got, ("e_node", "dV", "dR", "dE")):
         err = np.max(np.abs(a - b)) / np.max(np.abs(a))
         assert err <= 1e-4, (name, err)
+
+
+def test_retention_limits_at_the_edges():
+    """FP64 nodes with a limit of exactly one node's rows retain one node and keep the
+    recompute's gradient bit for bit; a plan without nodes accepts any limit and retains
+    none."""
+    import dataclasses
+    from paper_1907_02604_amd import sgq
+    P = synth.make_problem(4)
+    P = dataclasses.replace(P.subset(np.random.default_rng(7).choice(P.n_nodes, 24, replace=False)),
+                            precision="f64")
+    v, R, E, w = sgq.device_inputs(P)
+    announce("retain edges: FP64 recompute reference")
+    ref_plan = sgq.Plan.from_problem(P)
+    ref = _forward_backward(ref_plan, P, v, R, E, w)
+    ref_plan.close()
+    plan = sgq.Plan.from_problem(P)
+    npad = (max((2 * int(r) + 1) ** 3 for r in P.half_width) + 63) // 64 * 64
+    per_node = 2 * plan.kmax * npad * 8               # basis and u_j rows, FP64
+    assert plan.set_retain(True, max_bytes=per_node) == 1
+    announce("retain edges: one FP64 node retained")
+    got = _forward_backward(plan, P, v, R, E, w)
+    plan.close()
+    for a, b, name in zip(ref, got, ("e_node", "dV", "dR", "dE")):
+        assert np.array_equal(a, b), name
+    empty = sgq.Plan.from_problem(synth.make_problem(2, grid=32, n_nodes=1).subset([]))
+    assert empty.set_retain(True, max_bytes=1) == 0
+    assert empty.set_retain(True) == 0
+    empty.close()
