@@ -726,6 +726,33 @@ def test_lda_potential_is_the_density_derivative():
     assert np.all(e0 == 0.0) and np.all(u0 == 0.0)
 
 
+def test_effective_potential_of_a_neutral_uniform_gas_and_of_a_random_density():
+    """V = phi[rho + b] + u(rho).  A neutral uniform system (b = -rho) has no field, so V is
+    the uniform gas's potential: the Dirac exchange -(3 rho / pi)^(1/3) plus the correlation
+    potential eps_c - (rs / 3) d eps_c / d rs.  For a random density and charge, V - u(rho)
+    satisfies the real-space periodic stencil equation with source rho + b - mean."""
+    h = 0.45
+    for rho0 in (0.002, 0.02, 0.3):
+        rho = np.full((6, 8, 10), rho0)
+        V, e, phi, mean = O.effective_potential(rho, -rho, h)
+        assert np.all(phi == 0.0) and mean == 0.0
+        rs = (3.0 / (4.0 * math.pi * rho0)) ** (1.0 / 3.0)
+        ec, dec = O.pw92_correlation(np.array([rs]))
+        u_uniform = -(3.0 * rho0 / math.pi) ** (1.0 / 3.0) + ec[0] - rs / 3.0 * dec[0]
+        np.testing.assert_allclose(V, u_uniform, rtol=1e-13)
+        np.testing.assert_allclose(e, -0.75 * (3.0 / math.pi) ** (1.0 / 3.0) * rho0 ** (4.0 / 3.0)
+                                   + rho0 * ec[0], rtol=1e-13)
+    rng = np.random.default_rng(9)
+    rho = rng.uniform(0.001, 0.2, size=(10, 12, 9))
+    b = -rng.uniform(0.0, 0.3, size=rho.shape)
+    V, _, phi, mean = O.effective_potential(rho, b, h)
+    _, u = O.lda_xc(rho)
+    lap = -2.0 * O.kinetic_apply(V - u, h, periodic=True)
+    src = rho + b
+    assert np.max(np.abs(-lap / (4.0 * math.pi) - (src - src.mean()))) < 1e-11 * np.max(np.abs(src))
+    assert abs(mean - src.mean()) < 1e-15
+
+
 def test_poisson_solution_satisfies_the_stencil():
     """-(1/4 pi) Lap_6 phi = s - mean(s), with Lap_6 applied as the real-space periodic
     stencil of the Hamiltonian's kinetic term (independent of the Fourier symbol); phi has
