@@ -317,6 +317,8 @@ class NodeHamiltonian:
                 vals.append(chi[keep, l])
                 dvals.append(dchi[keep, l, :])
             col += 4
+        if not self.proj_atoms:
+            return          # no projector reaches the cube: the nonlocal sum is empty
         r = np.concatenate(rows)
         cidx = np.concatenate(cols)
         # duplicates (several images of one atom on a tiny periodic grid) are summed

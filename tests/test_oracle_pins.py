@@ -773,3 +773,30 @@ def test_poisson_solution_satisfies_the_stencil():
               for m in range(4)) / h ** 2
     phi, _ = O.poisson_periodic(s, h)
     np.testing.assert_allclose(phi, -4.0 * math.pi * s / lam, atol=1e-12)
+
+
+def test_node_beyond_every_projector_has_no_nonlocal_term():
+    """The Kleinman-Bylander sum runs over the atoms whose projectors reach the node's cube:
+    for a 13^3 cube that none reaches, the node's density, energy and gradient are those
+    of the same system with the projectors removed, and its projector adjoints vanish."""
+    import dataclasses
+    P = synth.make_problem(4)
+    Q = P.subset(np.arange(0, P.n_nodes, 211))
+    Q.half_width[:] = 6
+    far = []
+    for q in range(Q.n_nodes):
+        if O.NodeHamiltonian(Q, q).chi is None:
+            far.append(q)
+            if len(far) == 2:
+                break
+    assert len(far) == 2, "the 48^3 cell has 13^3 cubes out of every projector's reach"
+    Q = Q.subset(far)
+    Q.depth[:] = 12
+    L = dataclasses.replace(Q, n_proj=0, proj_E=np.zeros_like(Q.proj_E))
+    assert O.NodeHamiltonian(Q, 0).chi is None
+    np.testing.assert_array_equal(O.rho_quadrature(Q)[0], O.rho_quadrature(L)[0])
+    np.testing.assert_array_equal(O.band_energy(Q, kind=O.FREE)[0], O.band_energy(L, kind=O.FREE)[0])
+    dV, dE, dR = O.band_energy_backward(Q, kind=O.FREE)
+    dVl, _, _ = O.band_energy_backward(L, kind=O.FREE)
+    np.testing.assert_array_equal(dV, dVl)
+    assert not np.any(dE) and not np.any(dR)
