@@ -207,3 +207,35 @@ def test_backward_bitwise_deterministic():
     b = _gpu_grad(P, O.FREE, "f32")
     for x, y in zip(a, b):
         assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_nodes_beyond_every_projector(precision):
+    """13^3 cubes of the differentiation workload that no projector reaches, in a plan with
+    projectors (mu and kT raised so that the cubes hold charge): density and dV match the
+    oracle, whose nonlocal sum is empty there, and the projector adjoints are exactly 0."""
+    import dataclasses
+    import torch
+    from paper_1907_02604_amd import sgq
+    P = synth.make_problem(4)
+    Q = P.subset(np.arange(0, P.n_nodes, 211))
+    Q.half_width[:] = 6
+    far = []
+    for q in range(Q.n_nodes):
+        if O.NodeHamiltonian(Q, q).chi is None:
+            far.append(q)
+            if len(far) == 3:
+                break
+    Q = dataclasses.replace(Q.subset(far), precision=precision, mu=0.5, kT=0.2)
+    Q.depth[:] = 12
+    announce(f"nodes beyond every projector, {precision}")
+    rho, _ = sgq.rho(Q)
+    dV, dR, dE = sgq.energy_backward(Q, sgq.SGQ_FREE, 1.0)
+    torch.cuda.synchronize()
+    tol = 1e-6 if precision == "f64" else 1e-4
+    ref_rho, _ = O.rho_quadrature(Q)
+    rdV, rdE, rdR = O.band_energy_backward(Q, kind=O.FREE)
+    assert not np.any(rdE) and not np.any(rdR)
+    assert _rel(rho.cpu().numpy(), ref_rho) < tol
+    assert _rel(dV.cpu().numpy(), rdV) < tol
+    assert not torch.any(dR) and not torch.any(dE)
