@@ -224,3 +224,36 @@ def test_plain_schedule_matches_oracle(precision, tol):
     print("plain err", err)
     assert err < tol
     plan.close()
+
+
+def test_node_over_the_atom_limit_is_reported_and_skipped():
+    """A node whose cube meets more atoms than the node state holds (300 atoms packed into a
+    4-bohr box) latches SGQ_ELIMIT and gets NaN density and energy, and its adjoint adds
+    nothing; a node beyond the cluster is computed as usual and matches the oracle."""
+    import torch
+    from paper_1907_02604_amd import sgq
+    N, h = 48, 0.5
+    rng = np.random.default_rng(11)
+    atoms = rng.uniform(2.0, 6.0, size=(300, 3))
+    E = rng.uniform(-1.0, 1.0, size=(300, 4))
+    centers = [lin(8, 8, 8, N), lin(32, 32, 32, N)]   # inside the cluster; 14 bohr away
+    P = custom_problem(N, h=h, atoms=atoms, proj_E=E, v_loc=smooth_random_potential(N, 3, 0.3),
+                       centers=centers, half_width=4, depth=12, mu=0.2, kT=0.1)
+    plan = sgq.Plan.from_problem(P)
+    announce("node over the atom limit: forward")
+    rho, _ = sgq.rho(P, plan=plan)
+    torch.cuda.synchronize()
+    assert plan.status() == sgq.SGQ_ELIMIT
+    rho = rho.cpu().numpy()
+    assert np.isnan(rho[0])
+    far = P.subset([1])
+    ref_rho, _ = O.rho_quadrature(far)
+    assert abs(rho[1] - ref_rho[0]) < 1e-6 * abs(ref_rho[0])
+    announce("node over the atom limit: adjoint")
+    dV, dR, dE = sgq.energy_backward(P, sgq.SGQ_FREE, 1.0, plan=plan)
+    torch.cuda.synchronize()
+    assert plan.status() == sgq.SGQ_ELIMIT
+    rdV, rdE, rdR = O.band_energy_backward(far, kind=O.FREE)
+    assert O.normwise_rel_err(dV.cpu().numpy(), rdV) < 1e-6
+    assert not torch.any(dR) and not torch.any(dE) and not np.any(rdR) and not np.any(rdE)
+    plan.close()
