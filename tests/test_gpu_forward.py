@@ -257,3 +257,47 @@ def test_node_over_the_atom_limit_is_reported_and_skipped():
     assert O.normwise_rel_err(dV.cpu().numpy(), rdV) < 1e-6
     assert not torch.any(dR) and not torch.any(dE) and not np.any(rdR) and not np.any(rdE)
     plan.close()
+
+
+def test_host_checks_of_compute_calls():
+    """Calls the host rejects before launching anything: SGQ_EPLAN for a Gauss rule from the
+    plain schedule and for a backward deeper than its eigenvector matrix (K > 80), SGQ_EINVAL
+    for kT <= 0 or a non-finite mu.  The plan stays usable and matches the oracle after."""
+    import torch
+    from paper_1907_02604_amd import sgq
+    P = synth.make_problem(2, grid=32, n_nodes=2)
+    P.half_width[:] = 4
+    P.depth[:] = 10
+    plan = sgq.Plan.from_problem(P)
+    v, R, E, w = sgq.device_inputs(P)
+    rho = torch.empty(P.n_nodes, dtype=torch.float64, device="cuda")
+    tw = torch.zeros(P.n_nodes * plan.kmax * 2, dtype=torch.float64, device="cuda")
+    announce("host checks: rejected calls")
+    for mu, kT in ((P.mu, 0.0), (P.mu, -1.0), (float("nan"), P.kT), (P.mu, float("inf"))):
+        with pytest.raises(sgq.SgqError) as err:
+            sgq.rho_quadrature(plan, v, R, E, mu, kT, rho)
+        assert err.value.code == sgq.SGQ_EINVAL
+    plan.set_schedule(sgq.SGQ_SCHEDULE_PLAIN)
+    with pytest.raises(sgq.SgqError) as err:
+        sgq.rho_quadrature(plan, v, R, E, P.mu, P.kT, rho, tw)
+    assert err.value.code == sgq.SGQ_EPLAN
+    plan.set_schedule(sgq.SGQ_SCHEDULE_BATCHED)
+    sgq.rho_quadrature(plan, v, R, E, P.mu, P.kT, rho)
+    torch.cuda.synchronize()
+    assert plan.status() == sgq.SGQ_OK
+    ref, _ = O.rho_quadrature(P)
+    assert O.normwise_rel_err(rho.cpu().numpy(), ref) < 1e-4
+    plan.close()
+    deep = synth.make_problem(2, grid=32, n_nodes=1)
+    deep.half_width[:] = 4
+    deep.depth[:] = 81
+    dplan = sgq.Plan.from_problem(deep)
+    v, R, E, w = sgq.device_inputs(deep)
+    g = torch.ones(1, dtype=torch.float64, device="cuda")
+    dV = torch.empty_like(v)
+    dR = torch.zeros_like(R)
+    announce("host checks: backward deeper than 80")
+    with pytest.raises(sgq.SgqError) as err:
+        sgq.band_energy_backward(dplan, v, R, E, w, deep.mu, deep.kT, sgq.SGQ_FREE, g, dV, dR)
+    assert err.value.code == sgq.SGQ_EPLAN
+    dplan.close()
