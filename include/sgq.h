@@ -265,7 +265,8 @@ int sgq_fe_mesh_info(const sgq_fe_mesh* mesh, int64_t* info);
  *
  * sgq_potential_create: a periodic Poisson solver for the grid n (each extent in [1, 1024]
  *   and a product of 2, 3 and 5; fewer than 2^31 points) and spacing h; holds a complex
- *   workspace of (nx/2 + 1) ny nz values of 16 bytes.  Uses the current device.
+ *   workspace of m ny nz values of 16 bytes, m = nx/2 + 1 rounded up to a multiple of 8
+ *   (whole 128-byte rows).  Uses the current device.
  * sgq_poisson: phi with -(1/4 pi) L phi = s - mean(s) and mean(phi) = 0 (Eq. eq:poisson),
  *   L the sixth-order FD Laplacian of the Hamiltonian on the periodic grid, solved exactly
  *   for that operator by FFT.  Device arrays [nz][ny][nx] double: source in, phi out;

@@ -38,6 +38,12 @@ namespace {
 constexpr int kMaxStages = 12;
 constexpr int kPassBlock = 256;
 constexpr int kLdsComplex = 1024;   // complex doubles per LDS tile (16 KB, plus the twiddles)
+constexpr int kRowAlign = 8;        // complex values per 128-byte cache line
+
+// Row stride of the work grid: the nx/2 + 1 half-spectrum columns rounded up to whole cache
+// lines, so that every column tile of the Y and Z passes starts on a line boundary and no
+// line is fetched by two tiles.
+int row_stride(int nx) { return (nx / 2 + 1 + kRowAlign - 1) / kRowAlign * kRowAlign; }
 }  // namespace
 
 struct AxisPlan {
@@ -52,7 +58,7 @@ struct sgq_potential {
   int64_t npts = 0;
   double h = 1.0;
   AxisPlan axis[3];
-  double2* d_work = nullptr;    // half-spectrum complex grid, [z][y][nx/2 + 1]
+  double2* d_work = nullptr;    // half-spectrum complex grid, [z][y][row_stride(nx)]
   double2* d_tw[3] = {};        // exp(-2 pi i m / n_a), m < n_a
   double* d_lam[3] = {};        // per-axis FD eigenvalues
 };
@@ -231,9 +237,10 @@ enum PassMode { kFwdReal = 0, kFwd = 1, kSolve = 2, kInv = 3, kInvReal = 4 };
 struct PassArgs {
   AxisPlan ap;
   int axis, tl, nx, ny, nz;
-  int nxc;               // complex row length of the work grid, nx/2 + 1
+  int nxc;               // complex columns of the work grid, nx/2 + 1
+  int nxs;               // its row stride, row_stride(nx)
   int64_t npts;
-  double2* work;         // [nz][ny][nxc] complex
+  double2* work;         // [nz][ny][nxs] complex; columns nxc and up are not used
   const double2* tw;
   const double* src_a;   // kFwdReal: rho (or the source)
   const double* src_b;   // kFwdReal: b (optional)
@@ -259,8 +266,8 @@ __global__ __launch_bounds__(kPassBlock) void fft_pass_kernel(PassArgs a) {
   extern __shared__ double2 lds[];
   constexpr bool XPASS = MODE == kFwdReal || MODE == kInvReal;
   const int N = a.ap.n, TL = a.tl;
-  const int nx = a.nx, ny = a.ny, nxc = a.nxc;
-  const int64_t nxy = (int64_t)nx * ny, nxyc = (int64_t)nxc * ny;
+  const int nx = a.nx, ny = a.ny, nxc = a.nxc, nxs = a.nxs;
+  const int64_t nxy = (int64_t)nx * ny, nxys = (int64_t)nxs * ny;
   const double sign = (MODE == kFwdReal || MODE == kFwd || MODE == kSolve) ? -1.0 : 1.0;
   if constexpr (XPASS) {
     const int pairs = TL / 2;
@@ -273,7 +280,7 @@ __global__ __launch_bounds__(kPassBlock) void fft_pass_kernel(PassArgs a) {
     const int nl = min(TL, ny - y0);
     const int np = (nl + 1) / 2;
     const int64_t rbase = (int64_t)y0 * nx + z * nxy;     // real grid, line y0
-    const int64_t cbase = (int64_t)y0 * nxc + z * nxyc;   // complex grid, line y0
+    const int64_t cbase = (int64_t)y0 * nxs + z * nxys;   // complex grid, line y0
     const int total = np * N;
     if constexpr (MODE == kFwdReal) {
       for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
@@ -290,9 +297,9 @@ __global__ __launch_bounds__(kPassBlock) void fft_pass_kernel(PassArgs a) {
         const int p = idx / N, k = idx - p * N;
         const bool lo = k <= half;
         const int src = lo ? k : N - k;
-        const int64_t g0 = cbase + (int64_t)(2 * p) * nxc + src;
+        const int64_t g0 = cbase + (int64_t)(2 * p) * nxs + src;
         double2 A = a.work[g0];
-        double2 B = 2 * p + 1 < nl ? a.work[g0 + nxc] : make_double2(0.0, 0.0);
+        double2 B = 2 * p + 1 < nl ? a.work[g0 + nxs] : make_double2(0.0, 0.0);
         if (!lo) {
           A.y = -A.y;
           B.y = -B.y;
@@ -311,9 +318,9 @@ __global__ __launch_bounds__(kPassBlock) void fft_pass_kernel(PassArgs a) {
         // A = (Zk + conj Zm) / 2, B = (Zk - conj Zm) / 2i
         const double2 A = make_double2(0.5 * (Zk.x + Zm.x), 0.5 * (Zk.y - Zm.y));
         const double2 B = make_double2(0.5 * (Zk.y + Zm.y), -0.5 * (Zk.x - Zm.x));
-        const int64_t g0 = cbase + (int64_t)(2 * p) * nxc + k;
+        const int64_t g0 = cbase + (int64_t)(2 * p) * nxs + k;
         a.work[g0] = A;
-        if (2 * p + 1 < nl) a.work[g0 + nxc] = B;
+        if (2 * p + 1 < nl) a.work[g0 + nxs] = B;
       }
     } else {
       for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
@@ -346,11 +353,11 @@ __global__ __launch_bounds__(kPassBlock) void fft_pass_kernel(PassArgs a) {
     const int nl = min(TL, nxc - line0);
     int64_t base, sj;
     if (a.axis == 1) {
-      base = line0 + other * nxyc;
-      sj = nxc;
+      base = line0 + other * nxys;
+      sj = nxs;
     } else {
-      base = line0 + (int64_t)other * nxc;
-      sj = nxyc;
+      base = line0 + (int64_t)other * nxs;
+      sj = nxys;
     }
     const int total = nl * N;
     for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
@@ -421,6 +428,7 @@ hipError_t solve(const sgq_potential* P, const double* src_a, const double* src_
   a.ny = P->n[1];
   a.nz = P->n[2];
   a.nxc = P->n[0] / 2 + 1;
+  a.nxs = row_stride(P->n[0]);
   a.npts = P->npts;
   a.work = P->d_work;
   a.src_a = src_a;
@@ -498,7 +506,7 @@ extern "C" int sgq_potential_create(const int32_t n[3], double h, sgq_potential*
   P->npts = npts;
   P->h = h;
   POT_HIP(hipGetDevice(&P->device));
-  POT_HIP(hipMalloc(&P->d_work, sizeof(double2) * (size_t)(n[0] / 2 + 1) * n[1] * n[2]));
+  POT_HIP(hipMalloc(&P->d_work, sizeof(double2) * (size_t)row_stride(n[0]) * n[1] * n[2]));
   // sixth-order FD weights of the Laplacian (per axis, over h^2)
   const double w[4] = {-49.0 / 18.0, 3.0 / 2.0, -3.0 / 20.0, 1.0 / 90.0};
   for (int a = 0; a < 3; ++a) {
