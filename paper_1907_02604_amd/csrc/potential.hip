@@ -79,37 +79,71 @@ __device__ __forceinline__ double recip(double x) {
   return r;
 }
 
-// e_xc per volume and u = d e_xc / d rho; zero for rho <= 0.  y = rho^(-1/3) comes from an
-// FP32 seed (hardware log2 / exp2) and two division-free Newton steps for y^-3 = rho,
-// y <- y (4 - rho y^3) / 3, whose relative error squares (1e-7 -> 1e-14 -> rounding); then
-// rho^(1/3) = rho y^2 and rs = (3/(4 pi))^(1/3) y.  Outside [1e-30, 1e30] the seed is
-// taken from the library cube root instead.
+// log(1 + x) for finite x >= 0.  With y = 1 + x rounded and c = x - (y - 1) its rounding
+// error, log(1 + x) = log y + c / y to first order.  y = m 2^e with m in [sqrt(1/2),
+// sqrt(2)), log y = e ln 2 + 2 atanh(s) with s = (m - 1) / (m + 1), |s| <= 0.1716, and atanh
+// from its odd series to s^21, whose remainder is below 2^-53 of the sum.
+__device__ __forceinline__ double log1p_nonneg(double x) {
+  const double y = 1.0 + x;
+  const double c = x - (y - 1.0);
+  int e;
+  double m = frexp(y, &e);                     // y = m 2^e, m in [1/2, 1)
+  if (m < 0.70710678118654752) {
+    m *= 2.0;
+    e -= 1;
+  }
+  const double s = (m - 1.0) * recip(m + 1.0);
+  const double z = s * s;
+  double p = 1.0 / 21.0;
+  p = fma(p, z, 1.0 / 19.0);
+  p = fma(p, z, 1.0 / 17.0);
+  p = fma(p, z, 1.0 / 15.0);
+  p = fma(p, z, 1.0 / 13.0);
+  p = fma(p, z, 1.0 / 11.0);
+  p = fma(p, z, 1.0 / 9.0);
+  p = fma(p, z, 1.0 / 7.0);
+  p = fma(p, z, 1.0 / 5.0);
+  p = fma(p, z, 1.0 / 3.0);
+  const double s2 = 2.0 * s;
+  const double log_m = fma(s2 * z, p, s2);
+  return fma((double)e, 0.6931471805599453, log_m) + c * __builtin_amdgcn_rcp(y);
+}
+
+// e_xc per volume and u = d e_xc / d rho; zero for rho <= 0.  z = rho^(-1/6) comes from an
+// FP32 seed (hardware log2 / exp2) and two division-free Newton steps for z^-6 = rho,
+// z <- z (7 - rho z^6) / 6, whose relative error squares (1e-7 -> 1e-14 -> rounding).  Then
+// rho^(-1/3) = z^2, rs = (3/(4 pi))^(1/3) z^2 and sqrt(rs) = (3/(4 pi))^(1/6) z, with no FP64
+// square root.  Outside [1e-30, 1e30] z is taken from the library cube root instead.
 __device__ __forceinline__ void lda_xc(double rho, double& e, double& u) {
   if (!(rho > 0.0)) {
     e = 0.0;
     u = 0.0;
     return;
   }
-  double y;
+  double z;
   if (rho > 1e-30 && rho < 1e30) {
     const float lf = __builtin_amdgcn_logf((float)rho);          // log2, FP32
-    y = (double)__builtin_amdgcn_exp2f(lf * (-1.0f / 3.0f));
-    y = y * (4.0 - rho * y * y * y) * (1.0 / 3.0);
-    y = y * (4.0 - rho * y * y * y) * (1.0 / 3.0);
+    z = (double)__builtin_amdgcn_exp2f(lf * (-1.0f / 6.0f));
+    double z2 = z * z;
+    z = z * (7.0 - rho * (z2 * z2 * z2)) * (1.0 / 6.0);
+    z2 = z * z;
+    z = z * (7.0 - rho * (z2 * z2 * z2)) * (1.0 / 6.0);
   } else {
-    y = 1.0 / cbrt(rho);
+    z = sqrt(1.0 / cbrt(rho));
   }
   const double cx = 0.98474502184269641;            // (3/pi)^(1/3)
   const double crs = 0.62035049089940001;           // (3/(4 pi))^(1/3)
+  const double crs2 = 0.7876233178997433;           // (3/(4 pi))^(1/6)
+  const double y = z * z;                           // rho^(-1/3)
   const double r13 = rho * y * y;
   const double ex = -0.75 * cx * rho * r13, ux = -cx * r13;
   const double rs = crs * y;
-  const double sq = sqrt(rs);
+  const double sq = crs2 * z;                       // sqrt(rs)
   const double isq = sq * r13 * (1.0 / crs);        // 1/sqrt(rs) = sqrt(rs) / rs
   const double Q = 2.0 * kPwA * (kPwB1 * sq + kPwB2 * rs + kPwB3 * rs * sq + kPwB4 * rs * rs);
   const double dQ = 2.0 * kPwA * (0.5 * kPwB1 * isq + kPwB2 + 1.5 * kPwB3 * sq + 2.0 * kPwB4 * rs);
   const double iQ = recip(Q), iQ1 = recip(Q + 1.0);
-  const double L = log1p(iQ);
+  const double L = log1p_nonneg(iQ);
   const double ec = -2.0 * kPwA * (1.0 + kPwA1 * rs) * L;
   const double dec = -2.0 * kPwA * kPwA1 * L + 2.0 * kPwA * (1.0 + kPwA1 * rs) * dQ * iQ * iQ1;
   e = ex + rho * ec;
