@@ -662,6 +662,14 @@ __device__ __noinline__ void scatter_group(SGQ_L NodeState<T, BLOCK>& st, ProjEv
   }
 }
 
+// The three stencil forms below take the Laplacian as sum_d w_d ((v_-d - v) + (v_+d - v)),
+// which equals the usual weighted sum because the sixth-order weights add up to zero.
+// Forming each neighbour difference first keeps the FP32 rounding of the matvec
+// proportional to those differences, not to the point values: on the smooth parts of a
+// vector the usual form loses the Laplacian to cancellation of terms up to 8 |v|, and
+// that rounding, seen by the Lanczos rule as a perturbation of H, was the largest error of
+// the FP32 adjoint.
+//
 // u = s_j (-1/2 Lap_6 + V) W_j on a Dirichlet cube, four points per thread with every
 // load issued unconditionally (out-of-cube neighbours read the centre and are masked).
 // Returns this thread's part of q_j . u.
@@ -673,7 +681,7 @@ __device__ __noinline__ double stencil_cube(int gnx, int gny, int gnz,
                                             SGQ_G T* __restrict__ U, T sj, T kin) {
   const int n = st.n, sx = st.sx, sy = st.sy, sz = st.sz, sxy = sx * sy;
   const float inv_sx = 1.0f / (float)sx, inv_sxy = 1.0f / (float)sxy;
-  const T w0 = (T)(3.0 * kFd0), w1 = (T)kFd1, w2 = (T)kFd2, w3 = (T)kFd3;
+  const T w1 = (T)kFd1, w2 = (T)kFd2, w3 = (T)kFd3;
   const int ox = st.ox, oy = st.oy, oz = st.oz;
   double apart = 0.0;
   constexpr int UNR = 4;
@@ -689,22 +697,23 @@ __device__ __noinline__ double stencil_cube(int gnx, int gny, int gnz,
       unflatten(pc, sx, sxy, inv_sx, inv_sxy, x, y, z);
       const T c = Wj[bidx(pc, vbs)];
       wc[k] = c;
+      // neighbour minus centre (zero outside the cube, so the difference is -c there)
       auto nb = [&](bool ok, int idx) -> T {
         T v = Wj[bidx(ok ? idx : pc, vbs)];
-        return ok ? v : (T)0;
+        return (ok ? v : (T)0) - c;
       };
-      T l1 = nb(x >= 1, pc - 1) + nb(x + 1 < sx, pc + 1) + nb(y >= 1, pc - sx) +
-             nb(y + 1 < sy, pc + sx) + nb(z >= 1, pc - sxy) + nb(z + 1 < sz, pc + sxy);
-      T l2 = nb(x >= 2, pc - 2) + nb(x + 2 < sx, pc + 2) + nb(y >= 2, pc - 2 * sx) +
-             nb(y + 2 < sy, pc + 2 * sx) + nb(z >= 2, pc - 2 * sxy) + nb(z + 2 < sz, pc + 2 * sxy);
-      T l3 = nb(x >= 3, pc - 3) + nb(x + 3 < sx, pc + 3) + nb(y >= 3, pc - 3 * sx) +
-             nb(y + 3 < sy, pc + 3 * sx) + nb(z >= 3, pc - 3 * sxy) + nb(z + 3 < sz, pc + 3 * sxy);
+      T l1 = (nb(x >= 1, pc - 1) + nb(x + 1 < sx, pc + 1)) + (nb(y >= 1, pc - sx) +
+             nb(y + 1 < sy, pc + sx)) + (nb(z >= 1, pc - sxy) + nb(z + 1 < sz, pc + sxy));
+      T l2 = (nb(x >= 2, pc - 2) + nb(x + 2 < sx, pc + 2)) + (nb(y >= 2, pc - 2 * sx) +
+             nb(y + 2 < sy, pc + 2 * sx)) + (nb(z >= 2, pc - 2 * sxy) + nb(z + 2 < sz, pc + 2 * sxy));
+      T l3 = (nb(x >= 3, pc - 3) + nb(x + 3 < sx, pc + 3)) + (nb(y >= 3, pc - 3 * sx) +
+             nb(y + 3 < sy, pc + 3 * sx)) + (nb(z >= 3, pc - 3 * sxy) + nb(z + 3 < sz, pc + 3 * sxy));
       int gx = ox + x, gy = oy + y, gz = oz + z;
       gx = gx < 0 ? gx + gnx : (gx >= gnx ? gx - gnx : gx);
       gy = gy < 0 ? gy + gny : (gy >= gny ? gy - gny : gy);
       gz = gz < 0 ? gz + gnz : (gz >= gnz ? gz - gnz : gz);
       const T vloc = V[gx + gnx * (gy + gny * gz)];
-      const T lap = w0 * c + w1 * l1 + w2 * l2 + w3 * l3;
+      const T lap = w1 * l1 + w2 * l2 + w3 * l3;
       u[k] = sj * (kin * lap + vloc * c);
     }
 #pragma unroll
@@ -760,7 +769,7 @@ __device__ __noinline__ double stencil_march(int gnx, int gny, int gnz,
   const int rx = sx + 6;   // padded row
   const int tid = threadIdx.x;
   const int vplane = gnx * gny;
-  const T w0 = (T)(3.0 * kFd0), w1 = (T)kFd1, w2 = (T)kFd2, w3 = (T)kFd3;
+  const T w1 = (T)kFd1, w2 = (T)kFd2, w3 = (T)kFd3;
   for (int i = tid; i < 2 * kMarchPad; i += BLOCK) (&st.plane[0][0])[i] = (T)0;
   if (PROJ)
     for (int i = tid; i < 2 * NodeState<T, BLOCK>::kCorr; i += BLOCK) (&st.corr[0][0])[i] = (T)0;
@@ -818,13 +827,14 @@ __device__ __noinline__ double stencil_march(int gnx, int gny, int gnz,
         for (int k = 0; k < PPT; ++k) {
           const SGQ_L T* c0 = plane + li[k];
           const T c = ring[k][r];
-          const T l1 = mz1 * ring[k][(r + NQ - 1) % NQ] + pz1 * ring[k][(r + 1) % NQ] +
-                       (c0[-1] + c0[1]) + (c0[-rx] + c0[rx]);
-          const T l2 = mz2 * ring[k][(r + NQ - 2) % NQ] + pz2 * ring[k][(r + 2) % NQ] +
-                       (c0[-2] + c0[2]) + (c0[-2 * rx] + c0[2 * rx]);
-          const T l3 = mz3 * ring[k][(r + NQ - 3) % NQ] + pz3 * ring[k][(r + 3) % NQ] +
-                       (c0[-3] + c0[3]) + (c0[-3 * rx] + c0[3 * rx]);
-          const T lap = w0 * c + w1 * l1 + w2 * l2 + w3 * l3;
+          // neighbour minus centre; the halo and the masked z planes are zero
+          const T l1 = ((mz1 * ring[k][(r + NQ - 1) % NQ] - c) + (pz1 * ring[k][(r + 1) % NQ] - c)) +
+                       ((c0[-1] - c) + (c0[1] - c)) + ((c0[-rx] - c) + (c0[rx] - c));
+          const T l2 = ((mz2 * ring[k][(r + NQ - 2) % NQ] - c) + (pz2 * ring[k][(r + 2) % NQ] - c)) +
+                       ((c0[-2] - c) + (c0[2] - c)) + ((c0[-2 * rx] - c) + (c0[2 * rx] - c));
+          const T l3 = ((mz3 * ring[k][(r + NQ - 3) % NQ] - c) + (pz3 * ring[k][(r + 3) % NQ] - c)) +
+                       ((c0[-3] - c) + (c0[3] - c)) + ((c0[-3 * rx] - c) + (c0[3 * rx] - c));
+          const T lap = w1 * l1 + w2 * l2 + w3 * l3;
           const T u = sj * (kin * lap + vring[k][r % NV] * c);
           if (own[k]) {
             const int p2 = tid + k * BLOCK;
@@ -872,21 +882,21 @@ __device__ __noinline__ double stencil_periodic(const SGQ_L NodeState<T, BLOCK>&
                                                 SGQ_G T* __restrict__ U, T sj, T kin) {
   const int n = st.n, sx = st.sx, sy = st.sy, sz = st.sz, sxy = sx * sy;
   const float inv_sx = 1.0f / (float)sx, inv_sxy = 1.0f / (float)sxy;
-  const T w0 = (T)(3.0 * kFd0);
   const T wd[4] = {(T)0, (T)kFd1, (T)kFd2, (T)kFd3};
   double apart = 0.0;
   for (int p = threadIdx.x; p < n; p += BLOCK) {
     int x, y, z;
     unflatten(p, sx, sxy, inv_sx, inv_sxy, x, y, z);
     T wc = Wj[bidx(p, vbs)];
-    T lap = w0 * wc;
+    T lap = (T)0;
     for (int d = 1; d <= 3; ++d) {
-      lap += wd[d] * (Wj[bidx(wrap_index(x - d, sx) + sx * (y + sy * z), vbs)] +
-                      Wj[bidx(wrap_index(x + d, sx) + sx * (y + sy * z), vbs)]);
-      lap += wd[d] * (Wj[bidx(x + sx * (wrap_index(y - d, sy) + sy * z), vbs)] +
-                      Wj[bidx(x + sx * (wrap_index(y + d, sy) + sy * z), vbs)]);
-      lap += wd[d] * (Wj[bidx(x + sx * (y + sy * wrap_index(z - d, sz)), vbs)] +
-                      Wj[bidx(x + sx * (y + sy * wrap_index(z + d, sz)), vbs)]);
+      // neighbour minus centre, as in the cube forms
+      lap += wd[d] * ((Wj[bidx(wrap_index(x - d, sx) + sx * (y + sy * z), vbs)] - wc) +
+                      (Wj[bidx(wrap_index(x + d, sx) + sx * (y + sy * z), vbs)] - wc));
+      lap += wd[d] * ((Wj[bidx(x + sx * (wrap_index(y - d, sy) + sy * z), vbs)] - wc) +
+                      (Wj[bidx(x + sx * (wrap_index(y + d, sy) + sy * z), vbs)] - wc));
+      lap += wd[d] * ((Wj[bidx(x + sx * (y + sy * wrap_index(z - d, sz)), vbs)] - wc) +
+                      (Wj[bidx(x + sx * (y + sy * wrap_index(z + d, sz)), vbs)] - wc));
     }
     T u = sj * (kin * lap + V[p] * wc);
     if (ACC) U[p] += u; else U[p] = u;

@@ -101,20 +101,24 @@ __global__ void plain_matvec_kernel(LaunchParams P, int q, const PlainScalars* S
   if (p >= g.n) return;
   const T* V = (const T*)P.v;
   const int x = p % g.sx, y = (p / g.sx) % g.sy, z = p / (g.sx * g.sy);
-  const double w[4] = {3.0 * kFd0, kFd1, kFd2, kFd3};
-  T lap = (T)w[0] * Wj[p];
+  // sum_d w_d (neighbour - centre) over the six neighbours at distance d: the weights add
+  // up to zero, and differences keep the FP32 rounding small where the vector is smooth
+  const double w[4] = {0.0, kFd1, kFd2, kFd3};
+  const T c0 = Wj[p];
+  T lap = (T)0;
   for (int d = 1; d <= 3; ++d) {
     const int xs[2] = {x - d, x + d}, ys[2] = {y - d, y + d}, zs[2] = {z - d, z + d};
     for (int e = 0; e < 2; ++e) {
       int a = xs[e], b = ys[e], c = zs[e];
       if (g.periodic) {
         a = wrap_index(a, g.sx); b = wrap_index(b, g.sy); c = wrap_index(c, g.sz);
-        lap += (T)w[d] * (Wj[a + g.sx * (y + g.sy * z)] + Wj[x + g.sx * (b + g.sy * z)] +
-                          Wj[x + g.sx * (y + g.sy * c)]);
+        lap += (T)w[d] * ((Wj[a + g.sx * (y + g.sy * z)] - c0) + (Wj[x + g.sx * (b + g.sy * z)] - c0) +
+                          (Wj[x + g.sx * (y + g.sy * c)] - c0));
       } else {
-        if (a >= 0 && a < g.sx) lap += (T)w[d] * Wj[a + g.sx * (y + g.sy * z)];
-        if (b >= 0 && b < g.sy) lap += (T)w[d] * Wj[x + g.sx * (b + g.sy * z)];
-        if (c >= 0 && c < g.sz) lap += (T)w[d] * Wj[x + g.sx * (y + g.sy * c)];
+        const T va = (a >= 0 && a < g.sx) ? Wj[a + g.sx * (y + g.sy * z)] : (T)0;
+        const T vb = (b >= 0 && b < g.sy) ? Wj[x + g.sx * (b + g.sy * z)] : (T)0;
+        const T vc = (c >= 0 && c < g.sz) ? Wj[x + g.sx * (y + g.sy * c)] : (T)0;
+        lap += (T)w[d] * ((va - c0) + (vb - c0) + (vc - c0));
       }
     }
   }

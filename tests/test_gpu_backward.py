@@ -159,22 +159,13 @@ def test_hellmann_feynman_on_gpu():
     plan.close()
 
 
-# Bar of the FP32 projector-energy gradient.  FP32 Lanczos vectors make the computed
-# Gauss rule the exact rule of H + dH with |dH| ~ eps32 |H| ~ 6e-8 * 36.3 Ha ~ 2.2e-6 Ha.  A
-# Gauss node within a few kT of mu then moves by that much, and the energy adjoint carries
-# F'' = g' (up to 1/(4 kT) = 25 / Ha at kT = 0.01) through the divided differences and the
-# reverse recurrence: a relative error up to ~2.2e-6 * 25 * 10 ~ 5e-4 on the nodes whose
-# rule has a point at the Fermi level.  dE (a sum of products of projector overlaps) is the
-# output most exposed to it; dV and dR keep the 1e-4 bar.
-FP32_DE_TOL = 5e-4
-
-
-@pytest.mark.parametrize("precision,tol,tol_e", [("f32", 1e-4, FP32_DE_TOL), ("f64", 1e-6, 1e-6)])
-@pytest.mark.parametrize("seed", [21, 22])
-def test_differentiation_workload_subset(precision, tol, tol_e, seed):
+@pytest.mark.parametrize("precision,tol", [("f32", 1e-4), ("f64", 1e-6)])
+@pytest.mark.parametrize("seed", [21, 22, 23, 24])
+def test_differentiation_workload_subset(precision, tol, seed):
     """48^3 grid, 16 atoms, 33^3 cubes, K = 60 (the differentiation workload) on a node
-    subset: dV, dR (nonlocal) and dE against the oracle gradient.  Seed 21's subset holds a
-    node with a Gauss point 2.7 kT above mu (its FP32 dE error is ~1e-4, the others' ~2e-6)."""
+    subset: dV, dR (nonlocal) and dE against the oracle gradient, every output within the
+    precision's bar.  Seed 21's subset holds a node with a Gauss point 2.7 kT above mu, the
+    case most sensitive to the rounding of the FP32 matvec."""
     P = synth.make_problem(4)
     idx = np.random.default_rng(seed).choice(P.n_nodes, 6, replace=False)
     Q = P.subset(idx)
@@ -184,11 +175,12 @@ def test_differentiation_workload_subset(precision, tol, tol_e, seed):
     print("C4 grad errs", _rel(dV, rdV), _rel(dR, rdR), _rel(dE, rdE))
     assert _rel(dV, rdV) < tol
     assert _rel(dR, rdR) < tol
-    assert _rel(dE, rdE) < tol_e
+    assert _rel(dE, rdE) < tol
 
 
 def test_dislocation_workload_subset():
-    """128^3 screw-displaced lattice, cubes 25^3..49^3, K = 80, node weights 32: FP32."""
+    """128^3 screw-displaced lattice, cubes 25^3..49^3, K = 80, node weights 32: FP32, every
+    adjoint output within 1e-4 of the oracle gradient."""
     P = synth.make_problem(5)
     from gpu_util import stratified_sample
     Q = P.subset(stratified_sample(P, 2, seed=22))
@@ -198,6 +190,7 @@ def test_dislocation_workload_subset():
     print("C5 grad errs", _rel(dV, rdV), _rel(dR, rdR), _rel(dE, rdE))
     assert _rel(dV, rdV) < 1e-4
     assert _rel(dR, rdR) < 1e-4
+    assert _rel(dE, rdE) < 1e-4
 
 
 def test_backward_bitwise_deterministic():

@@ -228,8 +228,10 @@ def test_plain_schedule_matches_oracle(precision, tol):
 
 def test_node_over_the_atom_limit_is_reported_and_skipped():
     """A node whose cube meets more atoms than the node state holds (300 atoms packed into a
-    4-bohr box) latches SGQ_ELIMIT and gets NaN density and energy, and its adjoint adds
-    nothing; a node beyond the cluster is computed as usual and matches the oracle."""
+    4-bohr box) latches SGQ_ELIMIT and gets NaN density, energy and Gauss rule, and its
+    adjoint adds nothing; a node beyond the cluster is computed as usual and matches the
+    oracle.  A Fermi-level solve on those rules reports the NaN rule, although it starts
+    from a clear status word."""
     import torch
     from paper_1907_02604_amd import sgq
     N, h = 48, 0.5
@@ -241,14 +243,23 @@ def test_node_over_the_atom_limit_is_reported_and_skipped():
                        centers=centers, half_width=4, depth=12, mu=0.2, kT=0.1)
     plan = sgq.Plan.from_problem(P)
     announce("node over the atom limit: forward")
-    rho, _ = sgq.rho(P, plan=plan)
+    rho, tw, _ = sgq.rho(P, plan=plan, want_rule=True)
     torch.cuda.synchronize()
     assert plan.status() == sgq.SGQ_ELIMIT
     rho = rho.cpu().numpy()
     assert np.isnan(rho[0])
+    rule = tw.cpu().numpy()
+    assert np.all(np.isnan(rule[0])) and np.all(np.isfinite(rule[1]))
     far = P.subset([1])
     ref_rho, _ = O.rho_quadrature(far)
     assert abs(rho[1] - ref_rho[0]) < 1e-6 * abs(ref_rho[0])
+    announce("node over the atom limit: Fermi level of its rules")
+    res = torch.zeros(3, dtype=torch.float64, device="cuda")
+    w = torch.ones(P.n_nodes, dtype=torch.float64, device="cuda")
+    sgq.fermi_level(plan, tw, w, 1.0, P.kT, res)
+    torch.cuda.synchronize()
+    assert plan.status() == sgq.SGQ_ENONFINITE
+    assert np.isnan(res[0].item())
     announce("node over the atom limit: adjoint")
     dV, dR, dE = sgq.energy_backward(P, sgq.SGQ_FREE, 1.0, plan=plan)
     torch.cuda.synchronize()

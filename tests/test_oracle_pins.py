@@ -574,8 +574,8 @@ def test_fermi_level_recovers_the_density_level():
 
 # ---------------------------------------------------------------- cluster sampling
 def test_cluster_members_count_lattice_points_in_balls():
-    """Lattice points with i^2 + j^2 + k^2 <= R^2: 1, 7, 19, 27, 33, 57, 81, 93 for
-    R^2 = 0..7 (sums of three squares), on a grid wide enough for no periodic wrap."""
+    """Lattice points with i^2 + j^2 + k^2 <= R^2: 1, 7, 19, 27, 33, 57, 81, 81 for
+    R^2 = 0..7 (7 is not a sum of three squares) (sums of three squares), on a grid wide enough for no periodic wrap."""
     counts = {0: 1, 1: 7, 2: 19, 3: 27, 4: 33, 5: 57, 6: 81, 7: 81}
     for r2, cnt in counts.items():
         m = O.cluster_members((12, 12, 12), 0.5, lin(5, 6, 7, 12), 0.5 * math.sqrt(r2))
@@ -711,6 +711,65 @@ def test_pw92_high_density_logarithm():
     assert abs(slope - (1.0 - math.log(2.0)) / math.pi ** 2) < 1e-4 * 0.0311
     ec_far, _ = O.pw92_correlation(np.array([1e6]))
     assert abs(ec_far[0] * 1e6 / -0.44 - 1.0) < 0.02
+
+
+def _pw92_expansions():
+    """Coefficients of the small- and large-rs expansions of the oracle's eps_c, by least
+    squares on FP64 samples:  eps_c - c0 ln rs = -c1 + k sqrt(rs) - c3 rs + c2 rs ln rs + ...
+    (s = sqrt(rs) in [1e-5, 3e-3]) and eps_c = -d0/rs + d1/rs^(3/2) + ... (rs in [1e4, 1e7])."""
+    c0 = O.PW92_A
+    s = np.geomspace(1e-5, 3e-3, 60)
+    ec, _ = O.pw92_correlation(s * s)
+    X = np.stack([np.ones_like(s), s, s ** 2, s ** 2 * np.log(s), s ** 3, s ** 3 * np.log(s),
+                  s ** 4, s ** 4 * np.log(s)], axis=1)
+    a = np.linalg.lstsq(X, ec - c0 * np.log(s * s), rcond=None)[0]
+    r = np.geomspace(1e4, 1e7, 40)
+    ec, _ = O.pw92_correlation(r)
+    Y = np.stack([1.0 / r, r ** -1.5, r ** -2.0, r ** -2.5], axis=1)
+    d = np.linalg.lstsq(Y, ec, rcond=None)[0]
+    # rs ln rs = 2 s^2 ln s, so c2 is half the s^2 ln s coefficient
+    return {"c1": -a[0], "k": a[1], "c3": -a[2], "c2": a[3] / 2.0, "d0": -d[0], "d1": d[1]}
+
+
+def test_pw92_expansion_coefficients():
+    """The Perdew-Wang (1992) form is built to reproduce the exact high-density expansion
+    eps_c = c0 ln rs - c1 + c2 rs ln rs - c3 rs + ... with no sqrt(rs) term (that is what
+    fixes beta1 = exp(-c1 / 2c0) / 2c0 and beta2 = 2 c0 beta1^2) and the low-density form
+    eps_c = -d0 / rs + d1 / rs^(3/2) + ...; its Table I lists c1 = 0.046644, c2 = 0.00664,
+    c3 = 0.01043, d0 = 0.4335 and d1 = 1.4408 Ha for the unpolarised gas.  The oracle's
+    constants must give these back: a slip in the last printed digit of beta1 or beta2 moves
+    c1 or the sqrt(rs) coefficient past its bound, and a slip in beta3, beta4 or alpha1
+    moves c3, d0 or c2 by far more than the printed digits."""
+    c = _pw92_expansions()
+    assert abs(c["c1"] - 0.046644) < 1.2e-6
+    assert abs(c["k"]) < 5e-7
+    assert abs(c["c2"] - 0.00664) < 1e-5
+    assert abs(c["c3"] - 0.01043) < 1e-5
+    assert abs(c["d0"] - 0.4335) < 1e-4
+    assert abs(c["d1"] - 1.4408) < 2e-4
+
+
+def test_pw92_expansion_pins_catch_digit_slips():
+    """Each of these slips of one constant makes the expansion test above fail: the last
+    printed digit of beta1 or beta2, two swapped digits, and a changed third digit of beta3,
+    beta4 or alpha1.  A change in the last printed digit of beta3, beta4 or alpha1 stays
+    below the printed precision of c2, c3 and d0; those last digits rest on the citation."""
+    import importlib
+    mod = importlib.import_module("oracle.sgq_oracle")
+    good_b, good_a1 = mod.PW92_B, mod.PW92_A1
+    slips = [((7.5958, 3.5876, 1.6382, 0.49294), good_a1), ((7.5975, 3.5876, 1.6382, 0.49294), good_a1),
+             ((7.5957, 3.5877, 1.6382, 0.49294), good_a1), ((7.5957, 3.5867, 1.6382, 0.49294), good_a1),
+             ((7.5957, 3.5876, 1.6832, 0.49294), good_a1), ((7.5957, 3.5876, 1.6482, 0.49294), good_a1),
+             ((7.5957, 3.5876, 1.6382, 0.49924), good_a1), ((7.5957, 3.5876, 1.6382, 0.49394), good_a1),
+             (good_b, 0.21730), (good_b, 0.21470)]
+    try:
+        for b, a1 in slips:
+            mod.PW92_B, mod.PW92_A1 = b, a1
+            with pytest.raises(AssertionError):
+                test_pw92_expansion_coefficients()
+    finally:
+        mod.PW92_B, mod.PW92_A1 = good_b, good_a1
+    test_pw92_expansion_coefficients()
 
 
 def test_lda_potential_is_the_density_derivative():
