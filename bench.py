@@ -1,14 +1,20 @@
 """Benchmark: density nodes/s of the batched Lanczos-Gauss path on one MI355X.
 
-Workload: 64^3 periodic grid (h = 0.5 bohr) with a jittered hcp Gaussian local
-potential and four Kleinman-Bylander projectors per atom (255 atoms), 8192 seeded
-nodes, 33^3 truncation cubes, Lanczos depth 60, FP32 matvecs with FP64 dots,
-tridiagonal and quadrature.  One step = one rho_quadrature call over all nodes
-(potential/projector setup kernels + the persistent Lanczos launch), inputs resident
-in HBM.  Prints one JSON line.
+Headline workload: 64^3 periodic grid (h = 0.5 bohr) with a jittered hcp Gaussian local
+potential and four Kleinman-Bylander projectors per atom (255 atoms), 8192 seeded nodes,
+33^3 truncation cubes, Lanczos depth 60, FP32 matvecs with FP64 dots, tridiagonal and
+quadrature.  One step = one rho_quadrature call over all nodes (potential/projector setup
+kernels + the persistent Lanczos launch), inputs resident in HBM.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-plain]
-                    [--plain-nodes N] [--adjoint-nodes N]
+The other workloads are measured once each at their full sizes: the 16^3 untruncated FP64
+grid (all 4096 points), the 96^3 uneven batch (20000 nodes), the 48^3 differentiation
+workload (all 110592 nodes, forward and adjoint) and the 128^3 dislocation-shaped workload
+(all 65536 nodes, forward, adjoint and the adjoint with checkpointed Lanczos vectors).
+Before the GPU is touched, the FP64 oracle is timed on seeded samples of every workload
+(stratified by node cost), on all the host cores the box grants and on one thread; the
+same samples give each GPU result's error against the oracle.  Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--legs a,b,...]
 """
 import argparse
 import json
@@ -26,6 +32,9 @@ METRIC = "density nodes/sec and % HBM roofline at ≤1e-4 rel err, batched vs pl
 HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ("sgq_common.h", "tridiag.h", "lanczos_device.h", "forward.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_lanczos_forward_64grid_8192nodes.txt")
+LEGS = ("copy", "fermi", "cluster", "fe", "plain", "c1", "c3", "c4", "c5")
+# host cores a one-GPU machine grants a job, whatever the machine has
+HOST_CORE_SHARE = 16
 
 
 def kernel_source_digest():
@@ -60,93 +69,240 @@ def alg_bytes(n, K, elem=4):
     return elem * n * (3 * K + K * (K + 1) / 2)
 
 
+def cube_points(half_width, n_grid):
+    """Points of each node's cube (the whole grid for an untruncated node)."""
+    hw = np.asarray(half_width, dtype=np.int64)
+    return np.where(hw < 0, int(np.prod(n_grid)), (2 * hw + 1) ** 3)
+
+
+def launch_bytes(prob, elem=4):
+    n = cube_points(prob.half_width, prob.n)
+    return float(sum(alg_bytes(int(a), int(k), elem) for a, k in zip(n, prob.depth)))
+
+
+def stratified_order(cost, n_bins, seed):
+    """Node ids in an order whose every run of n_bins consecutive entries holds one node of
+    each cost stratum (nodes sorted by cost and split into n_bins equal bins), each bin
+    visited in a seeded random order: any prefix is a stratified sample."""
+    order = np.argsort(np.asarray(cost), kind="stable")
+    bins = [np.random.default_rng(seed + i).permutation(b)
+            for i, b in enumerate(np.array_split(order, n_bins)) if b.size]
+    out = []
+    for r in range(max(b.size for b in bins)):
+        out += [int(b[r]) for b in bins if r < b.size]
+    return np.array(out, dtype=np.int64)
+
+
+def node_cost(prob):
+    n = cube_points(prob.half_width, prob.n).astype(np.float64)
+    K = prob.depth.astype(np.float64)
+    return n * (3 * K + K * (K + 1) / 2)
+
+
+def errors(got, ref, floor=1e-3):
+    """Normwise ||got - ref||_inf / ||ref||_inf and the largest per-node relative error over
+    the nodes with |ref| > floor * ||ref||_inf."""
+    got, ref = np.asarray(got, np.float64), np.asarray(ref, np.float64)
+    den = float(np.max(np.abs(ref)))
+    sig = np.abs(ref) > floor * den
+    return {"normwise_rel_err": float(np.max(np.abs(got - ref)) / den),
+            "per_node_rel_err_max": float(np.max(np.abs(got[sig] - ref[sig]) / np.abs(ref[sig]))),
+            "per_node_floor": floor, "nodes_checked": int(ref.size),
+            "nodes_above_floor": int(sig.sum())}
+
+
 # ------------------------------------------------------------------ CPU baseline (oracle)
+_PROBLEMS = {}
+
+
 def _oracle_node(args):
     cfg, q = args
     import oracle as O
-    from paper_1907_02604_amd import synth
-    if "blas" not in _CACHE:
-        # one BLAS thread per worker process: the pool already uses every core
+    if "blas" not in _PROBLEMS:
+        # one BLAS thread per worker process: the pool already uses every core it has
         from threadpoolctl import threadpool_limits
-        _CACHE["blas"] = threadpool_limits(1)
-    P = _CACHE.get(cfg)
-    if P is None:
+        _PROBLEMS["blas"] = threadpool_limits(1)
+    return float(O.rho_quadrature(_PROBLEMS[cfg], nodes=[q])[0][0])
+
+
+def cpu_baselines(cfgs, target_s, target_1t):
+    """Time the FP64 oracle on a stratified seeded node sample of every workload, before the
+    GPU is touched: a pool of one process per granted core (one untimed warm-up round, then
+    rounds of one node per process until target_s[cfg] has passed), then one thread in this
+    process on further nodes of the same order for target_1t seconds.  Returns
+    {cfg: (record, node ids, oracle rho of those nodes)}."""
+    from paper_1907_02604_amd import synth
+    from threadpoolctl import threadpool_limits
+    import oracle as O
+    nproc = os.cpu_count() or 1
+    try:
+        granted = len(os.sched_getaffinity(0))
+    except AttributeError:
+        granted = nproc
+    cores = max(1, min(HOST_CORE_SHARE, granted))
+    orders = {}
+    for cfg in cfgs:
         P = synth.make_problem(cfg)
-        _CACHE[cfg] = P
-    return O.rho_quadrature(P, nodes=[q])[0][0]
-
-
-_CACHE = {}
-
-
-def cpu_baseline(cfg, n_nodes_total, target_s=15.0):
-    """Time the FP64 oracle on a seeded node sample, one process per core, before the
-    GPU is touched: one untimed round lets every worker build the inputs, then rounds of
-    one node per worker run until target_s has passed.  Returns (record, sample node ids,
-    oracle rho of the sample)."""
-    cores = min(16, os.cpu_count() or 1)
-    rng = np.random.default_rng(1234)
-    order = rng.permutation(n_nodes_total)
+        _PROBLEMS[cfg] = P          # built before the fork: the workers share it
+        orders[cfg] = stratified_order(node_cost(P), min(64, P.n_nodes), 100 + cfg)
+    out = {}
     ctx = mp.get_context("fork")
     with ctx.Pool(cores) as pool:
-        first = pool.map(_oracle_node, [(cfg, int(q)) for q in order[:cores]])
-        done = cores
-        timed = []
-        t0 = time.perf_counter()
-        while time.perf_counter() - t0 < target_s and done + cores <= n_nodes_total:
-            timed += pool.map(_oracle_node, [(cfg, int(q)) for q in order[done:done + cores]])
-            done += cores
-        wall = time.perf_counter() - t0
-    n_timed = len(timed)
-    rec = {"value": n_timed / wall, "unit": "nodes/s", "cores": cores, "kind": "oracle",
-           "sample": f"{n_timed} seeded nodes of the 8192-node workload timed after a warm-up "
-                     f"round of {cores}, FP64 numpy oracle, {cores} processes x 1 thread, "
-                     f"{wall:.1f} s wall"}
-    return rec, order[:done], np.array(first + timed)
+        for cfg in cfgs:
+            order = orders[cfg]
+            nq = order.size
+            first = pool.map(_oracle_node, [(cfg, int(q)) for q in order[:cores]])
+            done, timed = min(cores, nq), []
+            t0 = time.perf_counter()
+            while time.perf_counter() - t0 < target_s[cfg] and done < nq:
+                chunk = order[done:done + cores]
+                timed += pool.map(_oracle_node, [(cfg, int(q)) for q in chunk])
+                done += chunk.size
+            wall = time.perf_counter() - t0
+            out[cfg] = {"ids": order[:done], "rho": np.array(first + timed),
+                        "all": {"value": len(timed) / wall if timed else None, "nodes": len(timed),
+                                "wall_s": wall, "processes": cores}}
+    with threadpool_limits(1):
+        for cfg in cfgs:
+            order, ids = orders[cfg], out[cfg]["ids"]
+            start, n1 = ids.size, 0
+            vals = []
+            t0 = time.perf_counter()
+            while time.perf_counter() - t0 < target_1t[cfg] and start + n1 < order.size:
+                vals.append(float(O.rho_quadrature(_PROBLEMS[cfg], nodes=[int(order[start + n1])])[0][0]))
+                n1 += 1
+            wall = time.perf_counter() - t0
+            out[cfg]["one"] = {"value": n1 / wall if n1 else None, "nodes": n1, "wall_s": wall}
+            out[cfg]["ids"] = order[:start + n1]
+            out[cfg]["rho"] = np.concatenate([out[cfg]["rho"], vals])
+    for cfg in cfgs:
+        out[cfg]["nproc"], out[cfg]["granted"] = nproc, granted
+    return out
 
 
-# ------------------------------------------------------------------ GPU
+def cpu_record(base, cfg, desc):
+    a, o = base[cfg]["all"], base[cfg]["one"]
+    return {"value": a["value"], "unit": "nodes/s", "cores": a["processes"], "kind": "oracle",
+            "nproc": base[cfg]["nproc"], "cores_granted": base[cfg]["granted"],
+            "one_thread": {"value": o["value"], "nodes": o["nodes"], "wall_s": o["wall_s"]},
+            "sample": f"{a['nodes']} nodes of {desc} (stratified by cost, seeded) after a warm-up "
+                      f"round, FP64 numpy oracle, {a['processes']} processes x 1 BLAS thread, "
+                      f"{a['wall_s']:.1f} s wall; one thread: {o['nodes']} more nodes, "
+                      f"{o['wall_s']:.1f} s"}
+
+
+# ------------------------------------------------------------------ GPU helpers
+def event_time(stream, fn):
+    """Seconds between HIP events recorded on `stream` around fn()."""
+    import torch
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    fn()
+    e1.record(stream)
+    stream.synchronize()
+    return e0.elapsed_time(e1) * 1e-3
+
+
+def copy_peak():
+    """Device-to-device copy of 1 GiB (read 1 GiB, write 1 GiB) and a 4 GiB streaming read
+    (a reduction), best of five, as GB/s of bytes moved."""
+    import torch
+    src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    big = torch.ones(1 << 30, dtype=torch.float32, device="cuda")
+    s = torch.cuda.current_stream()
+    dst.copy_(src)
+    big.sum()
+    torch.cuda.synchronize()
+    tc = min(event_time(s, lambda: dst.copy_(src)) for _ in range(5))
+    tr = min(event_time(s, lambda: big.sum()) for _ in range(5))
+    rec = {"copy_GBs": 2.0 * src.numel() * 4 / tc / 1e9, "copy_bytes": 2 * src.numel() * 4,
+           "read_GBs": big.numel() * 4 / tr / 1e9, "read_bytes": big.numel() * 4,
+           "method": "torch copy_ of 1 GiB device to device (hipMemcpy kernel) and torch sum of "
+                     "4 GiB of FP32, HIP events, best of 5"}
+    del src, dst, big
+    torch.cuda.empty_cache()
+    return rec
+
+
+def forward_leg(sgq, torch, P, stream, tune_nodes, kind=None, warm=False):
+    """Plan, autotune and one timed forward launch of problem P (density, or the energy
+    with kind).  With warm, an untimed call first captures the launch graph and the timed
+    call replays it; without, the timed call launches directly (a multi-second launch needs
+    no warm-up).  Returns (plan, rho or e_node tensor, seconds, launch shape, inputs,
+    omega)."""
+    plan = sgq.Plan.from_problem(P)
+    if not warm:
+        plan.set_graph(False)
+    v, R, E, w = sgq.device_inputs(P)
+    out = torch.empty(P.n_nodes, dtype=torch.float64, device="cuda")
+    om = torch.empty(1, dtype=torch.float64, device="cuda")
+    shape = plan.autotune(v, R, E, P.mu, P.kT, sample_nodes=tune_nodes, stream=stream.cuda_stream)
+
+    def run():
+        if kind is None:
+            sgq.rho_quadrature(plan, v, R, E, P.mu, P.kT, out, stream=stream.cuda_stream)
+        else:
+            sgq.band_energy(plan, v, R, E, w, P.mu, P.kT, kind, out, om, stream=stream.cuda_stream)
+
+    if warm:
+        run()
+        stream.synchronize()
+    t = event_time(stream, run)
+    assert plan.status() == sgq.SGQ_OK
+    return plan, out, t, shape, (v, R, E, w), om
+
+
+def accuracy(base, cfg, values):
+    if base is None or cfg not in base:
+        return None
+    ids, ref = base[cfg]["ids"], base[cfg]["rho"]
+    return errors(values[ids], ref)
+
+
+# ------------------------------------------------------------------ main
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--legs", default=",".join(LEGS),
+                    help="comma-separated legs besides the headline: " + ",".join(LEGS))
     ap.add_argument("--plain-nodes", type=int, default=32)
-    ap.add_argument("--adjoint-nodes", type=int, default=8192)
     ap.add_argument("--retain-gb", type=float, default=160.0,
-                    help="retention budget of the dislocation sample's checkpointed adjoint "
-                         "(GB of HBM for the Lanczos bases of its costliest nodes; 0: skip)")
-    ap.add_argument("--dislocation-nodes", type=int, default=8192,
-                    help="nodes of the dislocation-shaped sample (128^3 screw lattice, K=80): "
-                         "forward and adjoint; 0 skips it")
-    ap.add_argument("--cluster-esps", type=int, default=256,
-                    help="energy sampling points of the cluster-energy leg (0 skips it)")
-    ap.add_argument("--no-fe", action="store_true",
-                    help="skip the fine-grid predictor + corrector reconstruction leg")
-    ap.add_argument("--no-uneven", action="store_true",
-                    help="skip the uneven-batching measurement (96^3, 20000 nodes, R and K drawn)")
+                    help="retention budget of the checkpointed adjoints (GB of HBM for the "
+                         "Lanczos bases of the costliest nodes; 0: skip)")
+    ap.add_argument("--cluster-esps", type=int, default=256)
     ap.add_argument("--tune-nodes", type=int, default=2048,
                     help="nodes of the sample the launch-shape autotuner times")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a 1 GiB device-to-device copy first (reference for byte counters)")
-    ap.add_argument("--config", type=int, default=2, help=argparse.SUPPRESS)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(the node set would be dealt out by cost, one share per GPU).",
               file=sys.stderr)
         sys.exit(2)
+    legs = set(x for x in args.legs.split(",") if x)
+    unknown = legs - set(LEGS)
+    if unknown:
+        print(f"unknown legs: {sorted(unknown)}", file=sys.stderr)
+        sys.exit(2)
 
     from paper_1907_02604_amd import synth
-    cfg = args.config
-    P = synth.make_problem(cfg)
-    cpu_rec, sample, ref = (None, None, None)
+    P = synth.make_problem(2)
+    base = None
     if not args.no_cpu:
-        cpu_rec, sample, ref = cpu_baseline(cfg, P.n_nodes)
-        print(f"[bench] cpu baseline {cpu_rec['value']:.2f} nodes/s on {cpu_rec['cores']} cores",
-              file=sys.stderr, flush=True)
+        cfgs = [2] + [c for c, leg in ((1, "c1"), (3, "c3"), (4, "c4"), (5, "c5")) if leg in legs]
+        target = {1: 3.0, 2: 10.0, 3: 8.0, 4: 5.0, 5: 8.0}
+        target1 = {1: 2.0, 2: 4.0, 3: 4.0, 4: 3.0, 5: 4.0}
+        base = cpu_baselines(cfgs, target, target1)
+        for c in cfgs:
+            print(f"[bench] oracle C{c}: {base[c]['all']['value']:.2f} nodes/s on "
+                  f"{base[c]['all']['processes']} processes, {base[c]['one']['value']:.2f} on "
+                  f"one thread", file=sys.stderr, flush=True)
         import oracle as O          # the oracle timed beside the next-work legs
 
     import torch
@@ -157,6 +313,12 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    peak = copy_peak() if "copy" in legs else None
+    if peak:
+        print(f"[bench] copy {peak['copy_GBs']:.0f} GB/s, read {peak['read_GBs']:.0f} GB/s",
+              file=sys.stderr, flush=True)
+
+    # ---------------- headline: the 64^3 workload, K steps of one launch each
     plan = sgq.Plan.from_problem(P)
     v, R, E, _ = sgq.device_inputs(P)
     rho = torch.empty(P.n_nodes, dtype=torch.float64, device="cuda")
@@ -176,7 +338,7 @@ def main():
         step()
     torch.cuda.synchronize()
     assert plan.status() == sgq.SGQ_OK
-    print(f"[bench] warmup done", file=sys.stderr, flush=True)
+    print("[bench] warmup done", file=sys.stderr, flush=True)
     starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
     ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
     torch.cuda.synchronize()
@@ -195,10 +357,25 @@ def main():
 
     n_cube = int((2 * P.half_width[0] + 1) ** 3)
     K = int(P.depth[0])
-    bytes_launch = float(sum(alg_bytes((2 * r + 1) ** 3, k) for r, k in zip(P.half_width, P.depth)))
+    bytes_launch = launch_bytes(P)
     t_launch = float(np.mean(launch_ms)) * 1e-3
     achieved = bytes_launch / t_launch / 1e9
     traffic = measured_traffic()
+    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "kernel": f"lanczos_forward_kernel<float,{lanes},16>",
+            "alg_bytes_per_launch": bytes_launch, "avg_launch_ms": t_launch * 1e3,
+            # the sweep skips the leading basis rows of a block while they are still exactly
+            # zero there, so the HBM bytes it moves fall below the dense count above; this is
+            # the fraction of the peak those bytes make
+            "frac_of_measured_traffic": (traffic / t_launch / 1e9 / HBM_PEAK_GBS
+                                         if traffic else None)}
+    if peak:
+        roof["measured_copy_GBs"] = peak["copy_GBs"]
+        roof["measured_read_GBs"] = peak["read_GBs"]
+        roof["frac_of_measured_copy"] = achieved / peak["copy_GBs"]
+        if traffic:
+            roof["measured_traffic_frac_of_measured_copy"] = traffic / t_launch / 1e9 / peak["copy_GBs"]
     rec = {
         "metric": METRIC, "value": value, "unit": "nodes/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
@@ -209,54 +386,45 @@ def main():
                    "grid": list(P.n), "nodes": P.n_nodes, "cube_points": n_cube, "depth": K,
                    "launch": {"lanes_per_node": lanes, "workgroups_per_cu": wg_per_cu,
                               "autotuned": True, "hip_graph": True}},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": f"lanczos_forward_kernel<float,{lanes},16>",
-                     "alg_bytes_per_launch": bytes_launch, "avg_launch_ms": t_launch * 1e3,
-                     # the sweep skips the leading basis rows of a block while they are still
-                     # exactly zero there, so the HBM bytes it moves fall below the dense
-                     # count above; this is the fraction of the peak those bytes make
-                     "frac_of_measured_traffic": (traffic / t_launch / 1e9 / HBM_PEAK_GBS
-                                                  if traffic else None)},
+        "roofline": roof,
     }
-    # Fermi level from the stored Gauss rules (no new Lanczos run): the count of the
-    # density at mu = -0.1 is solved for its level again
-    tw = torch.zeros(P.n_nodes * plan.kmax * 2, dtype=torch.float64, device="cuda")
-    rho_f = torch.empty_like(rho)
-    sgq.rho_quadrature(plan, v, R, E, P.mu, P.kT, rho_f, tw, stream=stream.cuda_stream)
-    stream.synchronize()
-    wq = torch.as_tensor(P.weight, dtype=torch.float64, device="cuda")
-    n_el = float((rho_f * wq).sum().item()) * P.h ** 3
-    fres = torch.empty(3, dtype=torch.float64, device="cuda")
-    sgq.fermi_level(plan, tw, wq, n_el, P.kT, fres, stream=stream.cuda_stream)   # warm-up
-    f0 = torch.cuda.Event(enable_timing=True)
-    f1 = torch.cuda.Event(enable_timing=True)
-    f0.record(stream)
-    sgq.fermi_level(plan, tw, wq, n_el, P.kT, fres, stream=stream.cuda_stream)
-    f1.record(stream)
-    stream.synchronize()
-    assert plan.status() == sgq.SGQ_OK
-    fr = fres.cpu().numpy()
-    rec["fermi_level"] = {"n_electrons": n_el, "mu": float(fr[0]), "mu_of_the_count": P.mu,
-                          "steps": int(fr[2]), "ms": f0.elapsed_time(f1),
-                          "rule_points": int(P.n_nodes * plan.kmax)}
+    if peak:
+        rec["hbm_measured"] = peak
+    rho_c2 = rho.cpu().numpy()
     oracle_rows = {}
-    if cpu_rec is not None:
-        cpu_rec["next_rows"] = oracle_rows
-        # the oracle's Brent solve on the same rules, on the host
-        twh = tw.cpu().numpy().reshape(P.n_nodes, plan.kmax, 2)
-        t0 = time.perf_counter()
-        mu_o = O.fermi_level(twh[:, :, 0], twh[:, :, 1], P.weight, n_el, P.kT)
-        oracle_rows["fermi_level"] = {"ms": (time.perf_counter() - t0) * 1e3,
-                                      "mu_diff": abs(mu_o - float(fr[0])),
-                                      "sample": "the same 491520 rule points, 1 thread"}
-    if args.cluster_esps > 0:
+
+    if "fermi" in legs:
+        # Fermi level from the stored Gauss rules (no new Lanczos run): the count of the
+        # density at mu = -0.1 is solved for its level again
+        tw = torch.zeros(P.n_nodes * plan.kmax * 2, dtype=torch.float64, device="cuda")
+        rho_f = torch.empty_like(rho)
+        sgq.rho_quadrature(plan, v, R, E, P.mu, P.kT, rho_f, tw, stream=stream.cuda_stream)
+        stream.synchronize()
+        wq = torch.as_tensor(P.weight, dtype=torch.float64, device="cuda")
+        n_el = float((rho_f * wq).sum().item()) * P.h ** 3
+        fres = torch.empty(3, dtype=torch.float64, device="cuda")
+        sgq.fermi_level(plan, tw, wq, n_el, P.kT, fres, stream=stream.cuda_stream)   # warm-up
+        tf = event_time(stream, lambda: sgq.fermi_level(plan, tw, wq, n_el, P.kT, fres,
+                                                        stream=stream.cuda_stream))
+        assert plan.status() == sgq.SGQ_OK
+        fr = fres.cpu().numpy()
+        rec["fermi_level"] = {"n_electrons": n_el, "mu": float(fr[0]), "mu_of_the_count": P.mu,
+                              "steps": int(fr[2]), "ms": tf * 1e3,
+                              "rule_points": int(P.n_nodes * plan.kmax)}
+        if base is not None:
+            twh = tw.cpu().numpy().reshape(P.n_nodes, plan.kmax, 2)
+            t0 = time.perf_counter()
+            mu_o = O.fermi_level(twh[:, :, 0], twh[:, :, 1], P.weight, n_el, P.kT)
+            oracle_rows["fermi_level"] = {"ms": (time.perf_counter() - t0) * 1e3,
+                                          "mu_diff": abs(mu_o - float(fr[0])),
+                                          "sample": "the same 491520 rule points, 1 thread"}
+        del tw, rho_f
+    if "cluster" in legs and args.cluster_esps > 0:
         # cluster-sampled energy: balls of radius 1 bohr (33 grid points) around C2 nodes
         # taken as energy sampling points; the band energy of the merged ball nodes, then
         # the per-cluster means and the weighted total
         Pc, cl = sgq.cluster_problem(P, np.arange(args.cluster_esps), 1.0)
         cplan = sgq.Plan.from_problem(Pc)
-        cplan.set_graph(True)
         cplan.autotune(v, R, E, Pc.mu, Pc.kT, sample_nodes=args.tune_nodes, stream=stream.cuda_stream)
         wn = torch.as_tensor(Pc.weight, device="cuda")
         ec = torch.empty(Pc.n_nodes, dtype=torch.float64, device="cuda")
@@ -274,27 +442,20 @@ def main():
 
         cluster_pass()                                   # warm-up (and graph capture)
         stream.synchronize()
-        c0 = torch.cuda.Event(enable_timing=True)
-        c1 = torch.cuda.Event(enable_timing=True)
-        c2 = torch.cuda.Event(enable_timing=True)
-        c0.record(stream)
-        cluster_pass()
-        c1.record(stream)
-        sgq.cluster_energy(cplan, ec, off, mem, we, fbar, en, stream=stream.cuda_stream)
-        c2.record(stream)
-        stream.synchronize()
+        tc = event_time(stream, cluster_pass)
+        tm = event_time(stream, lambda: sgq.cluster_energy(cplan, ec, off, mem, we, fbar, en,
+                                                           stream=stream.cuda_stream))
         assert cplan.status() == sgq.SGQ_OK
-        tc = c0.elapsed_time(c1) * 1e-3
         rec["cluster_energy"] = {
             "workload": f"{args.cluster_esps} ESPs of the 64^3 system, balls of radius 1 bohr "
                         f"(33 points), {Pc.n_nodes} merged nodes, 33^3 cubes, K=60, FP32",
             "value": args.cluster_esps / tc, "unit": "ESPs/s", "nodes_per_s": Pc.n_nodes / tc,
-            "pass_ms": tc * 1e3, "segmented_mean_ms": c1.elapsed_time(c2),
+            "pass_ms": tc * 1e3, "segmented_mean_ms": tm * 1e3,
             "energy": en.item(), "omega_with_cluster_weights": omc.item()}
         print(f"[bench] cluster energy {args.cluster_esps / tc:.1f} ESPs/s "
               f"({Pc.n_nodes / tc:.1f} nodes/s)", file=sys.stderr, flush=True)
         cplan.close()
-    if not args.no_fe:
+    if "fe" in legs:
         # predictor + corrector reconstruction of two fields (density, potential) on the
         # 128^3 fine grid from the ESPs of a coarse-grained dislocation run: the cylinder of
         # radius 4 points around the core line plus 65536 seeded points, Delaunay mesh
@@ -315,14 +476,12 @@ def main():
         mesh.reconstruct(vd, pd, od, stream=stream.cuda_stream)       # warm-up
         stream.synchronize()
         reps = 50
-        f0 = torch.cuda.Event(enable_timing=True)
-        f1 = torch.cuda.Event(enable_timing=True)
-        f0.record(stream)
-        for _ in range(reps):
-            mesh.reconstruct(vd, pd, od, stream=stream.cuda_stream)
-        f1.record(stream)
-        stream.synchronize()
-        t_fe = f0.elapsed_time(f1) * 1e-3 / reps
+
+        def fe_reps():
+            for _ in range(reps):
+                mesh.reconstruct(vd, pd, od, stream=stream.cuda_stream)
+
+        t_fe = event_time(stream, fe_reps) / reps
         npts5 = 128 ** 3
         fe_bytes = npts5 * (4 + 2 * 16) + esp5.size * 2 * 24
         info = mesh.info()
@@ -337,7 +496,7 @@ def main():
               f"{fe_bytes / t_fe / 1e9:.0f} GB/s; mesh + location {t_mesh:.2f} s",
               file=sys.stderr, flush=True)
         mesh.close()
-        if cpu_rec is not None:
+        if base is not None:
             # the oracle's brute-force location and 4x4 solves on 100 sampled fine points
             pts = np.random.default_rng(21).choice(npts5, 100, replace=False)
             t0 = time.perf_counter()
@@ -357,12 +516,12 @@ def main():
         vpot = torch.empty_like(rho5)
         pot.effective(rho5, vpot, b=bq, stream=stream.cuda_stream)    # warm-up
         stream.synchronize()
-        f0.record(stream)
-        for _ in range(reps):
-            pot.effective(rho5, vpot, b=bq, stream=stream.cuda_stream)
-        f1.record(stream)
-        stream.synchronize()
-        t_pot = f0.elapsed_time(f1) * 1e-3 / reps
+
+        def pot_reps():
+            for _ in range(reps):
+                pot.effective(rho5, vpot, b=bq, stream=stream.cuda_stream)
+
+        t_pot = event_time(stream, pot_reps) / reps
         # five line passes over the half-spectrum complex grid (65 x 128 x 128, 16 B each): X
         # forward reads rho and b and writes the grid, the Y, Z (solve) and Y inverse passes
         # read and write it, the X inverse pass reads it and rho and writes V
@@ -376,7 +535,7 @@ def main():
             "frac_hbm_peak": pot_bytes / t_pot / 1e9 / HBM_PEAK_GBS}
         print(f"[bench] effective potential {t_pot * 1e6:.1f} us/call, "
               f"{pot_bytes / t_pot / 1e9:.0f} GB/s", file=sys.stderr, flush=True)
-        if cpu_rec is not None:
+        if base is not None:
             t0 = time.perf_counter()
             ref_v, _, _, _ = O.effective_potential(rho5.cpu().numpy().reshape(128, 128, 128),
                                                    bq.cpu().numpy().reshape(128, 128, 128), 0.5)
@@ -387,10 +546,11 @@ def main():
                 "max_rel_err_of_gpu": float(np.max(np.abs(got_v - ref_v)) / np.max(np.abs(ref_v))),
                 "sample": "the whole 128^3 grid, numpy FFT"}
         pot.close()
-    if not args.no_plain:
+        del pd, vd, od, bq, rho5, vpot
+    if "plain" in legs:
         # per-node GPU baseline: the plain schedule on a seeded node sample
-        idx = np.random.default_rng(7).choice(P.n_nodes, args.plain_nodes, replace=False)
-        Q = P.subset(np.sort(idx))
+        idx = np.sort(np.random.default_rng(7).choice(P.n_nodes, args.plain_nodes, replace=False))
+        Q = P.subset(idx)
         pplan = sgq.Plan.from_problem(Q)
         pplan.set_schedule(sgq.SGQ_SCHEDULE_PLAIN)
         prho = torch.empty(Q.n_nodes, dtype=torch.float64, device="cuda")
@@ -401,192 +561,147 @@ def main():
         torch.cuda.synchronize()
         tp = time.perf_counter() - t0
         assert pplan.status() == sgq.SGQ_OK
-        perr = float(np.max(np.abs(prho.cpu().numpy() - rho.cpu().numpy()[np.sort(idx)]))
-                     / np.max(np.abs(rho.cpu().numpy()[np.sort(idx)])))
+        perr = float(np.max(np.abs(prho.cpu().numpy() - rho_c2[idx])) / np.max(np.abs(rho_c2[idx])))
         rec["plain"] = {"value": Q.n_nodes / tp, "unit": "nodes/s", "nodes": Q.n_nodes,
                         "schedule": "one node at a time, grid-wide kernels per Lanczos step",
                         "rel_diff_vs_batched": perr,
                         "batched_speedup": value / (Q.n_nodes / tp)}
         pplan.close()
         print(f"[bench] plain {Q.n_nodes / tp:.1f} nodes/s", file=sys.stderr, flush=True)
-    if args.adjoint_nodes > 0:
-        # adjoint throughput on the differentiation workload (48^3, 16 atoms, 33^3 cubes,
-        # K = 60): forward recompute + reverse recurrence + gathers, on a node sample
-        P4 = synth.make_problem(4)
-        idx = np.random.default_rng(8).choice(P4.n_nodes, args.adjoint_nodes, replace=False)
-        Q4 = P4.subset(np.sort(idx))
-        aplan = sgq.Plan.from_problem(Q4)
-        v4, R4, E4, w4 = sgq.device_inputs(Q4)
-        g = torch.ones(1, dtype=torch.float64, device="cuda")
-        dV = torch.empty_like(v4)
-        dR = torch.zeros_like(R4)
-        dE = torch.zeros_like(E4)
-        sgq.band_energy_backward(aplan, v4, R4, E4, w4, Q4.mu, Q4.kT, sgq.SGQ_FREE, g, dV, dR, dE)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        sgq.band_energy_backward(aplan, v4, R4, E4, w4, Q4.mu, Q4.kT, sgq.SGQ_FREE, g, dV, dR, dE)
-        torch.cuda.synchronize()
-        ta = time.perf_counter() - t0
-        assert aplan.status() == sgq.SGQ_OK
-        # algorithmic bytes of one node's adjoint: the forward recompute B(n, K), the adjoint
-        # vectors and their matvec 4n*8K, the node's dV cube 4n
-        abytes = float(sum(alg_bytes((2 * r + 1) ** 3, k) + 4.0 * (2 * r + 1) ** 3 * (8 * k + 1)
-                           for r, k in zip(Q4.half_width, Q4.depth)))
-        rec["adjoint"] = {"value": Q4.n_nodes / ta, "unit": "nodes/s", "nodes": Q4.n_nodes,
-                          "workload": "48^3 grid, 16 atoms with KB projectors, 33^3 cubes, K=60, "
-                                      "FP32, dOmega/dV + dOmega/dR + dOmega/dE",
-                          "alg_bytes": abytes, "achieved_GBs": abytes / ta / 1e9,
-                          "frac_hbm_peak": abytes / ta / 1e9 / HBM_PEAK_GBS}
-        print(f"[bench] adjoint {Q4.n_nodes / ta:.1f} nodes/s", file=sys.stderr, flush=True)
-        # the same adjoint after a forward call that retained its bases (per-node storage of
-        # the Lanczos vectors and u_j rows, 141 GB here), so the backward skips the recompute
-        dV_re = dV.clone()
-        aplan.set_retain(True)
-        e4 = torch.empty(Q4.n_nodes, dtype=torch.float64, device="cuda")
-        om4 = torch.empty(1, dtype=torch.float64, device="cuda")
-        sgq.band_energy(aplan, v4, R4, E4, w4, Q4.mu, Q4.kT, sgq.SGQ_FREE, e4, om4)   # warm-up
-        sgq.band_energy_backward(aplan, v4, R4, E4, w4, Q4.mu, Q4.kT, sgq.SGQ_FREE, g, dV, dR, dE)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        sgq.band_energy(aplan, v4, R4, E4, w4, Q4.mu, Q4.kT, sgq.SGQ_FREE, e4, om4)
-        torch.cuda.synchronize()
-        tf = time.perf_counter() - t0
-        t0 = time.perf_counter()
-        sgq.band_energy_backward(aplan, v4, R4, E4, w4, Q4.mu, Q4.kT, sgq.SGQ_FREE, g, dV, dR, dE)
-        torch.cuda.synchronize()
-        tb = time.perf_counter() - t0
-        assert aplan.status() == sgq.SGQ_OK
-        rec["adjoint"]["retained_bases"] = {
-            "value": Q4.n_nodes / tb, "unit": "nodes/s", "forward_s": tf, "backward_s": tb,
-            "forward_plus_backward_nodes_per_s": Q4.n_nodes / (tf + tb),
-            "forward_plus_recompute_backward_nodes_per_s": Q4.n_nodes / (tf + ta),
-            "dV_bitwise_equal_to_recompute": bool(torch.equal(dV, dV_re))}
-        aplan.close()
-        print(f"[bench] adjoint with retained bases {Q4.n_nodes / tb:.1f} nodes/s "
-              f"(forward + backward {Q4.n_nodes / (tf + tb):.1f} nodes/s)", file=sys.stderr, flush=True)
-    if not args.no_uneven:
+    plan.close()
+    del v, R, E, rho
+    torch.cuda.empty_cache()
+
+    configs = {}
+    if "c1" in legs:
+        # untruncated FP64 path: every point of the 16^3 periodic grid, K = 30
+        P1 = synth.make_problem(1)
+        p1, rho1, t1, shape1, _, _ = forward_leg(sgq, torch, P1, stream, args.tune_nodes, warm=True)
+        b1 = launch_bytes(P1, elem=8)
+        configs["c1"] = {
+            "workload": "16^3 periodic grid h=0.5, 6 atoms, no projectors, all 4096 points "
+                        "untruncated (the whole periodic H), K=30, kT=0.01, FP64",
+            "value": P1.n_nodes / t1, "unit": "nodes/s", "nodes": P1.n_nodes, "launch_ms": t1 * 1e3,
+            "alg_bytes": b1, "achieved_GBs": b1 / t1 / 1e9, "frac_hbm_peak": b1 / t1 / 1e9 / HBM_PEAK_GBS,
+            "launch": {"lanes_per_node": shape1[0], "workgroups_per_cu": shape1[1]},
+            "accuracy": accuracy(base, 1, rho1.cpu().numpy())}
+        p1.close()
+        print(f"[bench] C1 {P1.n_nodes / t1:.1f} nodes/s", file=sys.stderr, flush=True)
+    if "c3" in legs:
         # uneven batching: 20000 nodes with radii U{6..12} bohr and depths U{40..100} in one
         # persistent, autotuned, graph-replayed launch
         P3 = synth.make_problem(3)
-        uplan = sgq.Plan.from_problem(P3)
-        v3, R3, E3, _ = sgq.device_inputs(P3)
-        rho3 = torch.empty(P3.n_nodes, dtype=torch.float64, device="cuda")
-        shape3 = uplan.autotune(v3, R3, E3, P3.mu, P3.kT, sample_nodes=args.tune_nodes,
-                                stream=stream.cuda_stream)
-        sgq.rho_quadrature(uplan, v3, R3, E3, P3.mu, P3.kT, rho3, stream=stream.cuda_stream)
-        stream.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        sgq.rho_quadrature(uplan, v3, R3, E3, P3.mu, P3.kT, rho3, stream=stream.cuda_stream)
-        e1.record(stream)
-        stream.synchronize()
-        t3 = e0.elapsed_time(e1) * 1e-3
-        assert uplan.status() == sgq.SGQ_OK
-        b3 = float(sum(alg_bytes((2 * r + 1) ** 3, k) for r, k in zip(P3.half_width, P3.depth)))
-        costs = [alg_bytes((2 * r + 1) ** 3, k) for r, k in zip(P3.half_width, P3.depth)]
-        rec["uneven"] = {"value": P3.n_nodes / t3, "unit": "nodes/s", "nodes": P3.n_nodes,
-                         "workload": "96^3 grid h=0.5, 760 atoms with KB projectors, radii "
-                                     "U{6..12} bohr (cubes 25^3..49^3), depths U{40..100}, "
-                                     "kT=0.005, FP32",
-                         "launch_ms": t3 * 1e3, "alg_bytes": b3, "achieved_GBs": b3 / t3 / 1e9,
-                         "frac_hbm_peak": b3 / t3 / 1e9 / HBM_PEAK_GBS,
-                         "node_cost_spread": max(costs) / min(costs),
-                         "launch": {"lanes_per_node": shape3[0], "workgroups_per_cu": shape3[1],
-                                    "autotuned": True, "hip_graph": True}}
-        uplan.close()
-        print(f"[bench] uneven {P3.n_nodes / t3:.1f} nodes/s", file=sys.stderr, flush=True)
-    if args.dislocation_nodes > 0:
-        # dislocation-shaped input: 128^3 screw-displaced lattice, radii 6..12 bohr, K = 80,
-        # node weights 32; forward (autotuned, graph-replayed) and adjoint on a node sample
-        P5 = synth.make_problem(5)
-        Q5 = P5.subset(np.arange(min(args.dislocation_nodes, P5.n_nodes)))
-        dplan = sgq.Plan.from_problem(Q5)
-        v5, R5, E5, w5 = sgq.device_inputs(Q5)
-        rho5 = torch.empty(Q5.n_nodes, dtype=torch.float64, device="cuda")
-        shape5 = dplan.autotune(v5, R5, E5, Q5.mu, Q5.kT, sample_nodes=args.tune_nodes,
-                                stream=stream.cuda_stream)
-        sgq.rho_quadrature(dplan, v5, R5, E5, Q5.mu, Q5.kT, rho5, stream=stream.cuda_stream)
-        stream.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        sgq.rho_quadrature(dplan, v5, R5, E5, Q5.mu, Q5.kT, rho5, stream=stream.cuda_stream)
-        e1.record(stream)
-        stream.synchronize()
-        t5 = e0.elapsed_time(e1) * 1e-3
-        assert dplan.status() == sgq.SGQ_OK
-        b5 = float(sum(alg_bytes((2 * r + 1) ** 3, k) for r, k in zip(Q5.half_width, Q5.depth)))
-        g5 = torch.ones(1, dtype=torch.float64, device="cuda")
-        dV5 = torch.empty_like(v5)
-        dR5 = torch.zeros_like(R5)
-        dE5 = torch.zeros_like(E5)
-        sgq.band_energy_backward(dplan, v5, R5, E5, w5, Q5.mu, Q5.kT, sgq.SGQ_FREE, g5, dV5, dR5, dE5)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        sgq.band_energy_backward(dplan, v5, R5, E5, w5, Q5.mu, Q5.kT, sgq.SGQ_FREE, g5, dV5, dR5, dE5)
-        torch.cuda.synchronize()
-        tb5 = time.perf_counter() - t0
-        assert dplan.status() == sgq.SGQ_OK
-        rec["dislocation"] = {
-            "workload": f"128^3 grid h=0.5, 1925 screw-displaced atoms with KB projectors, "
-                        f"{Q5.n_nodes} of 65536 nodes (weights 32), cubes 25^3..49^3, K=80, "
-                        f"kT=0.005, FP32",
-            "forward": {"value": Q5.n_nodes / t5, "unit": "nodes/s", "launch_ms": t5 * 1e3,
-                        "achieved_GBs": b5 / t5 / 1e9, "frac_hbm_peak": b5 / t5 / 1e9 / HBM_PEAK_GBS,
-                        "launch": {"lanes_per_node": shape5[0], "workgroups_per_cu": shape5[1]}},
-            "adjoint": {"value": Q5.n_nodes / tb5, "unit": "nodes/s", "s": tb5}}
+        p3, rho3, t3, shape3, in3, _ = forward_leg(sgq, torch, P3, stream, args.tune_nodes, warm=True)
+        b3 = launch_bytes(P3)
+        costs = [alg_bytes(int(n), int(k)) for n, k in zip(cube_points(P3.half_width, P3.n), P3.depth)]
+        configs["c3"] = {
+            "workload": "96^3 grid h=0.5, 760 atoms with KB projectors, 20000 nodes, radii "
+                        "U{6..12} bohr (cubes 25^3..49^3), depths U{40..100}, kT=0.005, FP32",
+            "value": P3.n_nodes / t3, "unit": "nodes/s", "nodes": P3.n_nodes, "launch_ms": t3 * 1e3,
+            "alg_bytes": b3, "achieved_GBs": b3 / t3 / 1e9, "frac_hbm_peak": b3 / t3 / 1e9 / HBM_PEAK_GBS,
+            "node_cost_spread": max(costs) / min(costs),
+            "launch": {"lanes_per_node": shape3[0], "workgroups_per_cu": shape3[1],
+                       "autotuned": True, "hip_graph": True},
+            "accuracy": accuracy(base, 3, rho3.cpu().numpy())}
+        p3.close()
+        del in3, rho3
+        print(f"[bench] C3 {P3.n_nodes / t3:.1f} nodes/s", file=sys.stderr, flush=True)
+    for cfg, leg, kind_name in ((4, "c4", "differentiation"), (5, "c5", "dislocation")):
+        if leg not in legs:
+            continue
+        # every node of the workload: forward (density, for the accuracy check), the band
+        # free energy, its adjoint with the Lanczos vectors recomputed, and the adjoint after
+        # a forward call that checkpointed the bases of the costliest nodes within a budget
+        Pk = synth.make_problem(cfg)
+        pk, rhok, tk, shapek, (vk, Rk, Ek, wk), _ = forward_leg(sgq, torch, Pk, stream, args.tune_nodes)
+        acc = accuracy(base, cfg, rhok.cpu().numpy())
+        del rhok
+        bk = launch_bytes(Pk)
+        pk.prepare_backward()
+        ek = torch.empty(Pk.n_nodes, dtype=torch.float64, device="cuda")
+        omk = torch.empty(1, dtype=torch.float64, device="cuda")
+        g = torch.ones(1, dtype=torch.float64, device="cuda")
+        dV = torch.empty_like(vk)
+        dR = torch.zeros_like(Rk)
+        dE = torch.zeros_like(Ek)
+
+        def energy():
+            sgq.band_energy(pk, vk, Rk, Ek, wk, Pk.mu, Pk.kT, sgq.SGQ_FREE, ek, omk,
+                            stream=stream.cuda_stream)
+
+        def backward():
+            sgq.band_energy_backward(pk, vk, Rk, Ek, wk, Pk.mu, Pk.kT, sgq.SGQ_FREE, g, dV, dR, dE,
+                                     stream=stream.cuda_stream)
+
+        ta = event_time(stream, backward)
+        assert pk.status() == sgq.SGQ_OK
+        npts = cube_points(Pk.half_width, Pk.n)
+        # algorithmic bytes of one node's adjoint: the forward recompute B(n, K), the adjoint
+        # vectors and their matvec 4n*8K, the node's dV cube 4n
+        abytes = float(sum(alg_bytes(int(n), int(k)) + 4.0 * int(n) * (8 * int(k) + 1)
+                           for n, k in zip(npts, Pk.depth)))
+        entry = {
+            "forward": {"value": Pk.n_nodes / tk, "unit": "nodes/s", "launch_ms": tk * 1e3,
+                        "alg_bytes": bk, "achieved_GBs": bk / tk / 1e9,
+                        "frac_hbm_peak": bk / tk / 1e9 / HBM_PEAK_GBS,
+                        "launch": {"lanes_per_node": shapek[0], "workgroups_per_cu": shapek[1]},
+                        "accuracy": acc},
+            "adjoint": {"value": Pk.n_nodes / ta, "unit": "nodes/s", "s": ta, "alg_bytes": abytes,
+                        "achieved_GBs": abytes / ta / 1e9,
+                        "frac_hbm_peak": abytes / ta / 1e9 / HBM_PEAK_GBS,
+                        "recompute": True}}
         if args.retain_gb > 0:
-            # the adjoint with checkpointed Lanczos vectors: the forward keeps the bases and
-            # u_j rows of the costliest nodes that fit in the budget, and the backward
-            # recomputes only the others
+            dV_re = dV.clone()
             free_b, _ = torch.cuda.mem_get_info()
             budget = int(min(args.retain_gb * 1e9, free_b - 24e9))
             try:
-                n_ret = dplan.set_retain(True, max_bytes=budget) if budget > 0 else 0
+                n_ret = pk.set_retain(True, max_bytes=budget) if budget > 0 else 0
             except sgq.SgqError as err:
                 n_ret = 0
                 print(f"[bench] no checkpointed adjoint: {err}", file=sys.stderr, flush=True)
             if n_ret > 0:
-                dV5_re = dV5.clone()
-                e5 = torch.empty(Q5.n_nodes, dtype=torch.float64, device="cuda")
-                om5 = torch.empty(1, dtype=torch.float64, device="cuda")
-                sgq.band_energy(dplan, v5, R5, E5, w5, Q5.mu, Q5.kT, sgq.SGQ_FREE, e5, om5)
-                sgq.band_energy_backward(dplan, v5, R5, E5, w5, Q5.mu, Q5.kT, sgq.SGQ_FREE, g5,
-                                         dV5, dR5, dE5)   # warm-up pair
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                sgq.band_energy(dplan, v5, R5, E5, w5, Q5.mu, Q5.kT, sgq.SGQ_FREE, e5, om5)
-                torch.cuda.synchronize()
-                tf5 = time.perf_counter() - t0
-                t0 = time.perf_counter()
-                sgq.band_energy_backward(dplan, v5, R5, E5, w5, Q5.mu, Q5.kT, sgq.SGQ_FREE, g5,
-                                         dV5, dR5, dE5)
-                torch.cuda.synchronize()
-                tc5 = time.perf_counter() - t0
-                assert dplan.status() == sgq.SGQ_OK
-                rec["dislocation"]["adjoint"]["checkpointed"] = {
-                    "value": Q5.n_nodes / tc5, "unit": "nodes/s", "s": tc5,
-                    "retained_nodes": n_ret, "budget_GB": budget / 1e9,
-                    "forward_s": tf5, "forward_plus_backward_nodes_per_s": Q5.n_nodes / (tf5 + tc5),
-                    "forward_plus_recompute_backward_nodes_per_s": Q5.n_nodes / (t5 + tb5),
+                tf = event_time(stream, energy)
+                tb = event_time(stream, backward)
+                assert pk.status() == sgq.SGQ_OK
+                entry["adjoint"]["checkpointed"] = {
+                    "value": Pk.n_nodes / tb, "unit": "nodes/s", "s": tb,
+                    "retained_nodes": n_ret, "budget_GB": budget / 1e9, "forward_s": tf,
+                    "forward_plus_backward_nodes_per_s": Pk.n_nodes / (tf + tb),
+                    "forward_plus_recompute_backward_nodes_per_s": Pk.n_nodes / (tk + ta),
                     # the forward ran with the autotuned lanes per node, the recompute with
                     # the backward's 256: the two gradients differ by FP32 rounding only
                     "dV_normwise_rel_diff_vs_recompute":
-                        float((dV5 - dV5_re).abs().max() / dV5_re.abs().max())}
-                print(f"[bench] dislocation checkpointed adjoint {Q5.n_nodes / tc5:.1f} nodes/s "
-                      f"({n_ret} of {Q5.n_nodes} nodes retained)", file=sys.stderr, flush=True)
-            dplan.set_retain(False)
-        dplan.close()
-        print(f"[bench] dislocation fwd {Q5.n_nodes / t5:.1f} adj {Q5.n_nodes / tb5:.1f} nodes/s",
+                        float((dV - dV_re).abs().max() / dV_re.abs().max())}
+                print(f"[bench] C{cfg} checkpointed adjoint {Pk.n_nodes / tb:.1f} nodes/s "
+                      f"({n_ret} of {Pk.n_nodes} nodes retained)", file=sys.stderr, flush=True)
+            pk.set_retain(False)
+            del dV_re
+        if cfg == 4:
+            entry["workload"] = ("48^3 grid h=0.5, 16 atoms with KB projectors, all 110592 grid "
+                                 "points as nodes, 33^3 cubes, K=60, kT=0.01, FP32; adjoint "
+                                 "dOmega/dV + dOmega/dR + dOmega/dE of the Mermin free energy")
+        else:
+            entry["workload"] = ("128^3 grid h=0.5, 1925 screw-displaced atoms with KB projectors, "
+                                 "all 65536 nodes (weights 32), cubes 25^3..49^3, K=80, kT=0.005, "
+                                 "FP32; adjoint of the Mermin free energy")
+        configs[leg] = entry
+        pk.close()
+        del vk, Rk, Ek, wk, dV, dR, dE, ek
+        torch.cuda.empty_cache()
+        print(f"[bench] C{cfg} fwd {Pk.n_nodes / tk:.1f} adj {Pk.n_nodes / ta:.1f} nodes/s",
               file=sys.stderr, flush=True)
-    if cpu_rec is not None:
-        got = rho.cpu().numpy()[sample]
-        err = float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
-        rec["cpu_baseline"] = cpu_rec
-        rec["accuracy"] = {"normwise_rel_err_vs_fp64_oracle": err, "nodes_checked": int(len(sample))}
+    if configs:
+        rec["configs"] = configs
+    if base is not None:
+        rec["cpu_baseline"] = cpu_record(base, 2, "the 8192-node 64^3 workload")
+        rec["cpu_baseline"]["next_rows"] = oracle_rows
+        rec["cpu_baseline"]["configs"] = {
+            f"c{c}": cpu_record(base, c, d) for c, d in
+            ((1, "the 16^3 untruncated FP64 workload"), (3, "the 20000-node 96^3 workload"),
+             (4, "the 110592-node 48^3 workload"), (5, "the 65536-node 128^3 workload"))
+            if c in base}
+        rec["accuracy"] = accuracy(base, 2, rho_c2)
     print(json.dumps(rec), flush=True)
-    plan.close()
 
 
 if __name__ == "__main__":

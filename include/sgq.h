@@ -27,7 +27,12 @@
  *     sgq_plan_create, sgq_fe_mesh_create and the host-only helpers (sgq_cluster_build,
  *     sgq_validate, sgq_gauss_rule_host).
  *   - Compute calls are asynchronous on `stream` (a hipStream_t; NULL = default
- *     stream).  Inputs must stay valid until the stream reaches the call.
+ *     stream).  Inputs must stay valid until the stream reaches the call.  They allocate
+ *     no device memory and do not synchronise: everything they need is allocated by the
+ *     synchronous set-up calls (sgq_plan_create, sgq_plan_prepare_backward,
+ *     sgq_plan_set_schedule, sgq_plan_set_retain, sgq_plan_autotune, the mesh and solver
+ *     constructors), which report SGQ_ENOMEM.  (The HIP runtime itself sets up a stream's
+ *     kernel-argument buffers, and a kernel's private memory, on their first launches.)
  *   - Every function returns an sgq_status and never throws.  Argument errors found
  *     on the host are returned before anything is launched; errors found by the GPU
  *     (non-finite input, a node touching more atoms than the library supports) are
@@ -47,7 +52,7 @@ extern "C" {
 typedef enum {
   SGQ_OK = 0,
   SGQ_EINVAL = -1,      /* invalid argument (null pointer, bad size, kT <= 0, ...) */
-  SGQ_ENOMEM = -2,      /* device allocation failed at plan creation */
+  SGQ_ENOMEM = -2,      /* device allocation failed (set-up calls only) */
   SGQ_EHIP = -3,        /* a HIP runtime call failed */
   SGQ_EPLAN = -4,       /* the call does not match the plan (e.g. no projectors planned) */
   SGQ_ENONFINITE = -5,  /* device status: NaN/Inf in an input */
@@ -113,8 +118,20 @@ int band_energy(sgq_plan* plan, const double* v_loc, const double* atom_R,
                 const double* proj_E, const double* node_weight, double mu, double kT,
                 int integrand, double* e_node, double* omega, void* stream);
 
+/* Backward workspace of a plan: the per-workgroup adjoint slots, the per-node dV cubes
+ * (one cube of the node's points per node: 15.9 GB for 110592 nodes of 33^3 points in
+ * FP32), the per-node atom partials and the lists that gather the cubes into dV.  Allocates
+ * and uploads them (host geometry, hipMalloc, blocking copies), so it is synchronous; call it
+ * once before the first band_energy_backward.  Returns SGQ_ENOMEM when the workspace does
+ * not fit, SGQ_EPLAN when the plan's depth exceeds the adjoint's (80); calling it again is a
+ * no-op. */
+int sgq_plan_prepare_backward(sgq_plan* plan);
+
 /* Adjoint of Omega (reverse mode through the Lanczos recurrence; the Lanczos vectors
- * of each node are recomputed from the start vector, the only checkpoint kept).
+ * of each node are recomputed from the start vector, the only checkpoint kept, unless the
+ * forward call retained them, see sgq_plan_set_retain).  Requires
+ * sgq_plan_prepare_backward (SGQ_EPLAN otherwise); the call itself allocates nothing and
+ * does not synchronise: it only enqueues kernels on `stream`.
  *   grad_omega [1] double        upstream dL/dOmega
  *   dV    [nz*ny*nx] double      out: dL/dV_loc(x)
  *   dR_nl [M*3] double           out: dL/dR_J through the projectors (NULL allowed when
@@ -141,7 +158,10 @@ int sgq_vloc_gaussian_backward(sgq_plan* plan, const double* dV, const double* a
  *   SGQ_SCHEDULE_PLAIN:  one node after another, every Lanczos step as grid-wide kernels
  *                        (classical Gram-Schmidt against all earlier vectors); the
  *                        per-node GPU baseline.  Same precision and depth; theta_w must be
- *                        NULL.  Returns SGQ_EINVAL for an unknown schedule. */
+ *                        NULL.  Its scratch is allocated by this call (synchronous;
+ *                        SGQ_ENOMEM if it does not fit, and the schedule is unchanged), so
+ *                        the compute calls allocate nothing.
+ * Returns SGQ_EINVAL for an unknown schedule. */
 int sgq_plan_set_schedule(sgq_plan* plan, int schedule);
 
 /* Fermi level of stored Gauss rules (Eq. Eqn:LSSGQ:Fermi_level:GQ, with the node weights
@@ -295,13 +315,14 @@ int sgq_effective_potential(sgq_potential* pot, const double* rho, const double*
  * rho_quadrature / band_energy then write those nodes' rows there.  The next
  * band_energy_backward call with the same v_loc, atom_R and proj_E pointers takes the
  * retained rows of those nodes instead of recomputing their forward Lanczos and recomputes
- * the others.  The result is bitwise the full recompute's when the forward ran with 256
+ * the others; both calls hash the contents of those inputs on the device (64-bit, order
+ * independent), and when the hashes differ (inputs overwritten in place in between) the
+ * backward recomputes every node.  The result is bitwise the full recompute's when the forward ran with 256
  * lanes per node, the backward's own launch shape; after another autotuned shape the
  * retained rows differ from a recompute by rounding only.  The backward consumes them (it overwrites the
  * u_j rows), and any other call that runs a forward launch (sgq_plan_autotune, the plain
  * schedule) invalidates them; an invalid or mismatched retention falls back to the
- * recompute.  The caller must not change the contents of those inputs between the forward
- * and the backward call.  Every call first waits for the device and frees the storage a
+ * recompute.  Every call first waits for the device and frees the storage a
  * previous call allocated; enable = 0 stops there.  n_retained [1] (optional, host) receives
  * R.  Returns SGQ_EINVAL for a null plan, max_bytes < 0, or a max_bytes below one node's
  * rows; SGQ_ENOMEM when the storage does not fit (retention is then off). */

@@ -6,7 +6,8 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = ["plan.hip", "forward.hip", "backward.hip", "plain.hip", "cluster.hip", "fe.hip", "potential.hip"]
+SOURCES = ["plan.hip", "forward.hip", "fermi.hip", "backward.hip", "plain.hip", "cluster.hip", "fe.hip",
+           "potential.hip", "host.cpp"]
 LIB = os.path.join(HERE, "libsgq.so")
 
 

@@ -21,15 +21,15 @@
 //   4. the projector adjoints Ebar_Jl = h^3 sum_j (chi.ubar_j)(chi.q_j) and
 //      Rbar_J = h^3 E sum_j [(ubar_j.dchi)(chi.q_j) + (ubar_j.chi)(dchi.q_j)]
 //      (dchi = d chi / d R) come from one dense product per atom,
-//      M = [chi; d chi] (16 x box points) . [ubar_0 .. ubar_K-1 | q_0 .. q_K-1], on the
-//      matrix cores (16x16x4 MFMA, accumulation in the storage precision);
+//      M = [chi; d chi] (16 x box points) . [ubar_j | q_j], on the matrix cores (16x16x4
+//      MFMA, accumulation in the storage precision), one wave per atom;
 //   5. a gather kernel sums the node cubes into dV in a fixed order (deterministic,
 //      no floating-point atomics) and a reduction kernel sums the atom adjoints.
 #include "lanczos_device.h"
 
 namespace sgq {
 
-constexpr int kBwdMaxDepth = 80;   // largest depth of the adjoint (eigenvector matrix K x K)
+constexpr int kBwdMaxDepth = kMaxDepth;   // largest depth of the adjoint (eigenvector matrix K x K)
 constexpr int kGatherCell = 8;     // dV gather cell edge (points)
 
 struct BwdState {
@@ -61,33 +61,41 @@ struct Mfma16<double> {
 };
 
 // Projector adjoints of one node from its stored vectors: for every node atom (one wave
-// per atom) M = [chi_0..3 ; d chi_l / d d_a] (16 x box points) times the matrix of the
-// box values of [ubar_0 .. ubar_K-1 | q_0 .. q_K-1] on the matrix cores, then
-//   Ebar_l = h^3 sum_j M[l][j] M[l][K+j],
-//   Rbar_a = -h^3 sum_l E_l sum_j (M[4+3l+a][j] M[l][K+j] + M[l][j] M[4+3l+a][K+j]).
-// The waves stage M through `scratch` (LDS), `slots` waves at a time.
-template <typename T, int BLOCK, int MAXB>
+// per atom, the node's waves working side by side) the dense product
+// M = [chi_0..3 ; d chi_l / d d_a] (16 x box points) times the box values of the columns
+// [ubar_j | q_j] on the matrix cores, then
+//   Ebar_l = h^3 sum_j M[l][ubar_j] M[l][q_j],
+//   Rbar_a = -h^3 sum_l E_l sum_j (M[4+3l+a][ubar_j] M[l][q_j] + M[l][ubar_j] M[4+3l+a][q_j]).
+// Column block b of the product holds ubar_j in its columns 0..7 and q_j in its columns
+// 8..15, j = 8b .. 8b+7, so every pair the sums need lies in one 16 x 16 output tile: the
+// wave stages a finished tile in its own 16 x 16 piece of `scratch` (LDS) and folds it into
+// FP64 sums at once.  CB blocks are accumulated per pass over the box (CB MFMA accumulators
+// in registers), so a depth of 8 CB or less takes one pass and the projector values are
+// evaluated once.
+template <typename T, int BLOCK, int CB>
 __device__ __noinline__ void projector_gradients(const SGQ_G double* proj_E,
                                                  SGQ_L NodeState<T, BLOCK>& st, ProjEval<T> pe,
                                                  const SGQ_G T* W, int wbs, const SGQ_G T* Ub,
                                                  int npad, int keff, double h3, int B, int B3,
-                                                 SGQ_L T* scratch, int slots, double* dEp,
-                                                 double* dRp) {
+                                                 SGQ_L T* scratch, double* dEp, double* dRp) {
   using M16 = Mfma16<T>;
   using V = typename M16::V;
   constexpr int NW = BLOCK / kWave;
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-  const int ncol = 2 * keff, nblk = (ncol + 15) / 16, ld = 16 * MAXB;
   const int fr = lane & 15, kk = lane >> 4;   // A row / B column, and the k index of the lane
-  SGQ_L T* Ms = scratch + (size_t)(wave < slots ? wave : 0) * 16 * ld;
+  const int nblk = (keff + 7) / 8;
+  SGQ_L T* Ms = scratch + wave * 256;          // this wave's 16 x 16 tile
   const int natoms = st.natoms;
-  for (int a0 = 0; a0 < natoms; a0 += slots) {
-    const int a = a0 + wave;
-    const bool mine = wave < slots && a < natoms;
-    if (mine) {
-      V acc[MAXB];
+  for (int a = wave; a < natoms; a += NW) {
+    const int J = st.atom[a];
+    double El[4];
 #pragma unroll
-      for (int jb = 0; jb < MAXB; ++jb) acc[jb] = (V)(T)0;
+    for (int l = 0; l < 4; ++l) El[l] = proj_E[4 * J + l];
+    double eb[4] = {0, 0, 0, 0}, rb[3] = {0, 0, 0};
+    for (int b0 = 0; b0 < nblk; b0 += CB) {
+      V acc[CB];
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb) acc[cb] = (V)(T)0;
       for (int k0 = 0; k0 < B3; k0 += 4) {
         const int b = k0 + kk;
         const int bx = b % B, by = (b / B) % B, bz = b / (B * B);
@@ -99,53 +107,51 @@ __device__ __noinline__ void projector_gradients(const SGQ_G double* proj_E,
         for (int r = 0; r < 16; ++r) av = fr == r ? (r < 4 ? c[r] : g[r - 4]) : av;
         av = b < B3 ? av : (T)0;
 #pragma unroll
-        for (int jb = 0; jb < MAXB; ++jb) {
-          if (jb < nblk) {
-            const int col = 16 * jb + fr;
+        for (int cb = 0; cb < CB; ++cb) {
+          if (b0 + cb < nblk) {
+            const int j = 8 * (b0 + cb) + (fr & 7);
             T bv = (T)0;
-            if (lp >= 0 && col < ncol) {
-              if (col < keff) bv = Ub[(size_t)col * npad + lp];
-              else bv = W[64 * (col - keff) + bidx(lp, wbs)] * (T)st.scale[col - keff];
+            if (lp >= 0 && j < keff)
+              bv = fr < 8 ? Ub[(size_t)j * npad + lp]
+                          : W[64 * j + bidx(lp, wbs)] * (T)st.scale[j];
+            acc[cb] = M16::op(av, bv, acc[cb]);
+          }
+        }
+      }
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb) {
+        if (b0 + cb < nblk) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) Ms[M16::row(lane, r) * 16 + fr] = acc[cb][r];
+          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          const int j = 8 * (b0 + cb) + lane;
+          if (lane < 8 && j < keff) {
+#pragma unroll
+            for (int l = 0; l < 4; ++l) {
+              const double cu = (double)Ms[l * 16 + lane], cq = (double)Ms[l * 16 + 8 + lane];
+              eb[l] += cu * cq;
+#pragma unroll
+              for (int ax = 0; ax < 3; ++ax) {
+                const int rr = 4 + 3 * l + ax;
+                rb[ax] += El[l] * ((double)Ms[rr * 16 + lane] * cq + cu * (double)Ms[rr * 16 + 8 + lane]);
+              }
             }
-            acc[jb] = M16::op(av, bv, acc[jb]);
           }
+          // the tile is read before the next block overwrites it
+          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+          __builtin_amdgcn_wave_barrier();
         }
       }
-#pragma unroll
-      for (int jb = 0; jb < MAXB; ++jb)
-        if (jb < nblk)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) Ms[M16::row(lane, r) * ld + 16 * jb + fr] = acc[jb][r];
     }
-    __syncthreads();
-    if (mine) {
-      const int J = st.atom[a];
-      double El[4];
 #pragma unroll
-      for (int l = 0; l < 4; ++l) El[l] = proj_E[4 * J + l];
-      double eb[4] = {0, 0, 0, 0}, rb[3] = {0, 0, 0};
-      for (int j = lane; j < keff; j += kWave) {
+    for (int l = 0; l < 4; ++l) eb[l] = wave_sum(eb[l]);
 #pragma unroll
-        for (int l = 0; l < 4; ++l) {
-          const double cu = (double)Ms[l * ld + j], cq = (double)Ms[l * ld + keff + j];
-          eb[l] += cu * cq;
-#pragma unroll
-          for (int ax = 0; ax < 3; ++ax) {
-            const int rr = 4 + 3 * l + ax;
-            rb[ax] += El[l] * ((double)Ms[rr * ld + j] * cq + cu * (double)Ms[rr * ld + keff + j]);
-          }
-        }
-      }
-#pragma unroll
-      for (int l = 0; l < 4; ++l) eb[l] = wave_sum(eb[l]);
-#pragma unroll
-      for (int ax = 0; ax < 3; ++ax) rb[ax] = wave_sum(rb[ax]);
-      if (lane == 0) {
-        for (int l = 0; l < 4; ++l) dEp[4 * a + l] = h3 * eb[l];
-        for (int ax = 0; ax < 3; ++ax) dRp[3 * a + ax] = -h3 * rb[ax];
-      }
+    for (int ax = 0; ax < 3; ++ax) rb[ax] = wave_sum(rb[ax]);
+    if (lane == 0) {
+      for (int l = 0; l < 4; ++l) dEp[4 * a + l] = h3 * eb[l];
+      for (int ax = 0; ax < 3; ++ax) dRp[3 * a + ax] = -h3 * rb[ax];
     }
-    __syncthreads();
   }
 }
 
@@ -268,7 +274,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2, 2))) v
     SGQ_G T* __restrict__ Wq = W;
     SGQ_G T* __restrict__ Uq = Ubase;
     int keff;
-    const int rs = P.use_retained ? P.ret_slot[q] : -1;
+    // retained rows serve only inputs with the contents the forward call saw
+    const int rs = P.use_retained && P.hash[0] == P.hash[1] ? P.ret_slot[q] : -1;
     if (rs >= 0) {
       const size_t roff = (size_t)rs * kmax * npad;
       Wq = (SGQ_G T*)P.Wr + roff;
@@ -458,14 +465,11 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2, 2))) v
     double* dEp = P.dE_part + (size_t)q * kMaxNodeAtoms * 4;
     double* dRp = P.dR_part + (size_t)q * kMaxNodeAtoms * 3;
     if (natoms > 0) {
-      constexpr int MAXB = (2 * kBwdMaxDepth + 15) / 16;
-      constexpr int per_wave = 16 * 16 * MAXB * (int)sizeof(T);
-      constexpr int room = (int)sizeof(st.plane) / per_wave;
-      constexpr int slots = room < NW ? room : NW;
-      static_assert(slots >= 1, "the plane buffers must hold one wave's product");
+      static_assert(sizeof(st.plane) >= NW * 256 * sizeof(T),
+                    "the plane buffers must hold a 16 x 16 tile per wave");
       __syncthreads();
-      projector_gradients<T, BLOCK, MAXB>(proj_E, st, pe, Wq, wbs, Uq, (int)npad, keff, h3, B,
-                                          B3, (SGQ_L T*)&st.plane[0][0], slots, dEp, dRp);
+      projector_gradients<T, BLOCK, 8>(proj_E, st, pe, Wq, wbs, Uq, (int)npad, keff, h3, B, B3,
+                                       (SGQ_L T*)&st.plane[0][0], dEp, dRp);
     }
     for (int a = tid; a < natoms; a += BLOCK) natoms_out[1 + a] = st.atom[a];
     if (tid == 0) natoms_out[0] = natoms;

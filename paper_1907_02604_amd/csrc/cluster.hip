@@ -1,10 +1,9 @@
 // Cluster sampling of the energy (Eq. eq:free_cg with the cluster averages of
 // Eq. eq:free_cg_sampling).
 //
-// Host side: sgq_cluster_build enumerates, for each energy sampling point (ESP) q, the
-// cluster C_q of grid points within a ball of radius r around it, merges the clusters into
-// one ascending node list (so a point shared by several clusters is evaluated once) and
-// writes the clusters as a CSR list of positions in that node list.
+// The host side, sgq_cluster_build (the clusters C_q of grid points within a ball of radius
+// r around each energy sampling point, merged into one ascending node list, and the
+// clusters as CSR positions in it), lives in host.cpp.
 //
 // Device side: the segmented mean Fbar_q = (1/|C_q|) sum_{p in C_q} e_p over the per-node
 // energies of a band_energy call on that node list, one wavefront per cluster with a fixed
@@ -84,100 +83,3 @@ hipError_t launch_cluster_energy(const double* e_node, int nq, const int64_t* of
 }
 
 }  // namespace sgq
-
-using sgq::report_error;
-
-extern "C" int sgq_cluster_build(const int32_t n[3], double h, const int64_t* esp_center,
-                                 int32_t n_esp, double radius, const double* esp_weight,
-                                 int64_t node_capacity, int64_t member_capacity,
-                                 int64_t* node_center, int32_t* node_esp, double* node_weight,
-                                 int64_t* member_offset, int32_t* member_node, int64_t* n_nodes,
-                                 int64_t* n_members) {
-  if (!n || !n_nodes || !n_members) return report_error(SGQ_EINVAL, "null argument");
-  if (n_esp < 0) return report_error(SGQ_EINVAL, "n_esp < 0");
-  if (n_esp > 0 && !esp_center) return report_error(SGQ_EINVAL, "esp_center is null");
-  for (int a = 0; a < 3; ++a)
-    if (n[a] < 1) return report_error(SGQ_EINVAL, "grid extent must be >= 1");
-  const int64_t nx = n[0], ny = n[1], nz = n[2], ng = nx * ny * nz;
-  if (ng >= 2147483647LL) return report_error(SGQ_EINVAL, "grid has 2^31 or more points");
-  if (!(h > 0.0) || !std::isfinite(h)) return report_error(SGQ_EINVAL, "h must be finite and > 0");
-  if (!(radius >= 0.0) || !std::isfinite(radius))
-    return report_error(SGQ_EINVAL, "radius must be finite and >= 0");
-  if (node_weight && !esp_weight)
-    return report_error(SGQ_EINVAL, "node_weight needs esp_weight");
-  for (int32_t q = 0; q < n_esp; ++q)
-    if (esp_center[q] < 0 || esp_center[q] >= ng)
-      return report_error(SGQ_EINVAL, "ESP " + std::to_string(q) + ": centre outside the grid");
-
-  // Offsets of the ball: squared distance in grid units (an integer) against (r/h)^2
-  // widened by a relative 1e-9, so a radius equal to a lattice distance keeps that shell.
-  // Each axis offset is the minimum-image representative of its residue class, so every
-  // grid point of the periodic box is reached at most once per cluster.
-  const double lim = (radius / h) * (radius / h) * (1.0 + 1e-9);
-  const int64_t reach = (int64_t)std::floor(std::sqrt(lim));
-  const int64_t dims[3] = {nx, ny, nz};
-  int64_t lo[3], hi[3];
-  for (int a = 0; a < 3; ++a) {
-    lo[a] = std::max(-reach, -((dims[a] - 1) / 2));
-    hi[a] = std::min(reach, dims[a] / 2);
-  }
-  std::vector<int64_t> off;   // (dx, dy, dz) triples
-  for (int64_t dz = lo[2]; dz <= hi[2]; ++dz)
-    for (int64_t dy = lo[1]; dy <= hi[1]; ++dy)
-      for (int64_t dx = lo[0]; dx <= hi[0]; ++dx)
-        if ((double)(dx * dx + dy * dy + dz * dz) <= lim) {
-          off.push_back(dx);
-          off.push_back(dy);
-          off.push_back(dz);
-        }
-  const int64_t per = (int64_t)off.size() / 3;
-  const int64_t total = per * n_esp;
-  *n_members = total;
-
-  // Members of every cluster as ascending linear indices.
-  std::vector<int64_t> lin((size_t)total);
-  for (int32_t q = 0; q < n_esp; ++q) {
-    const int64_t c = esp_center[q];
-    const int64_t cx = c % nx, cy = (c / nx) % ny, cz = c / (nx * ny);
-    int64_t* out = lin.data() + (size_t)q * per;
-    for (int64_t i = 0; i < per; ++i) {
-      const int64_t x = ((cx + off[3 * i]) % nx + nx) % nx;
-      const int64_t y = ((cy + off[3 * i + 1]) % ny + ny) % ny;
-      const int64_t z = ((cz + off[3 * i + 2]) % nz + nz) % nz;
-      out[i] = x + nx * (y + ny * z);
-    }
-    std::sort(out, out + per);
-  }
-  std::vector<int64_t> nodes(lin);
-  std::sort(nodes.begin(), nodes.end());
-  nodes.erase(std::unique(nodes.begin(), nodes.end()), nodes.end());
-  *n_nodes = (int64_t)nodes.size();
-
-  const bool want_nodes = node_center || node_esp || node_weight;
-  const bool want_members = member_offset || member_node;
-  if (want_nodes && node_capacity < *n_nodes)
-    return report_error(SGQ_EINVAL, "node arrays hold " + std::to_string(node_capacity) +
-                                        " entries, " + std::to_string(*n_nodes) + " needed");
-  if (member_node && member_capacity < total)
-    return report_error(SGQ_EINVAL, "member_node holds " + std::to_string(member_capacity) +
-                                        " entries, " + std::to_string(total) + " needed");
-  if (!want_nodes && !want_members) return SGQ_OK;
-
-  if (node_center) std::copy(nodes.begin(), nodes.end(), node_center);
-  if (node_esp) std::fill(node_esp, node_esp + nodes.size(), -1);
-  if (node_weight) std::fill(node_weight, node_weight + nodes.size(), 0.0);
-  if (member_offset) member_offset[0] = 0;
-  for (int32_t q = 0; q < n_esp; ++q) {
-    const int64_t* mem = lin.data() + (size_t)q * per;
-    if (member_offset) member_offset[q + 1] = (int64_t)(q + 1) * per;
-    const double share = esp_weight ? esp_weight[q] / (double)per : 0.0;
-    for (int64_t i = 0; i < per; ++i) {
-      const int32_t k =
-          (int32_t)(std::lower_bound(nodes.begin(), nodes.end(), mem[i]) - nodes.begin());
-      if (member_node) member_node[(size_t)q * per + i] = k;
-      if (node_esp && node_esp[k] < 0) node_esp[k] = q;
-      if (node_weight) node_weight[k] += share;
-    }
-  }
-  return SGQ_OK;
-}

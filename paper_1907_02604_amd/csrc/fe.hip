@@ -262,82 +262,19 @@ extern "C" int sgq_fe_mesh_create(const int32_t n[3], const int64_t* esp_center,
                                   sgq_fe_mesh** out) {
   if (!out) return report_error(SGQ_EINVAL, "out is null");
   *out = nullptr;
-  if (!n) return report_error(SGQ_EINVAL, "n is null");
-  for (int a = 0; a < 3; ++a)
-    if (n[a] < 1 || n[a] > 65536) return report_error(SGQ_EINVAL, "grid extents must be in [1, 65536]");
+  // host geometry: ESP coordinates, oriented tetrahedra, bucket lists (host.cpp)
+  sgq::FeGeometry geo;
+  int st = sgq::fe_geometry(n, esp_center, n_esp, tets, n_tets, max_fields, &geo);
+  if (st != SGQ_OK) return st;
   const int64_t npts = (int64_t)n[0] * n[1] * n[2];
-  if (npts >= 2147483647LL) return report_error(SGQ_EINVAL, "grid has 2^31 or more points");
-  if (n_esp < 1 || !esp_center) return report_error(SGQ_EINVAL, "no ESPs");
-  if (n_tets < 0 || (n_tets > 0 && !tets)) return report_error(SGQ_EINVAL, "bad tetrahedra");
-  if (max_fields < 1 || max_fields > 4) return report_error(SGQ_EINVAL, "max_fields must be in [1, 4]");
-
-  std::vector<int4> esp(n_esp);
-  for (int32_t q = 0; q < n_esp; ++q) {
-    const int64_t c = esp_center[q];
-    if (c < 0 || c >= npts)
-      return report_error(SGQ_EINVAL, "ESP " + std::to_string(q) + ": centre outside the grid");
-    esp[q] = make_int4((int)(c % n[0]), (int)((c / n[0]) % n[1]), (int)(c / ((int64_t)n[0] * n[1])),
-                       (int)c);
-  }
-  // orient, drop zero volumes, bucket by bounding box
-  std::vector<int4> tet(std::max(n_tets, 1), make_int4(0, 0, 0, 0));
-  std::vector<char> keep(std::max(n_tets, 1), 0);
-  auto coord = [&](int v, int a) { return (int64_t)(a == 0 ? esp[v].x : a == 1 ? esp[v].y : esp[v].z); };
-  int32_t kept = 0;
-  for (int32_t t = 0; t < n_tets; ++t) {
-    int v[4];
-    for (int i = 0; i < 4; ++i) {
-      v[i] = tets[4 * t + i];
-      if (v[i] < 0 || v[i] >= n_esp)
-        return report_error(SGQ_EINVAL, "tetrahedron " + std::to_string(t) + ": vertex out of range");
-    }
-    int64_t u[3][3];
-    for (int k = 0; k < 3; ++k)
-      for (int a = 0; a < 3; ++a) u[k][a] = coord(v[k + 1], a) - coord(v[0], a);
-    const int64_t D = u[0][0] * (u[1][1] * u[2][2] - u[1][2] * u[2][1]) -
-                      u[0][1] * (u[1][0] * u[2][2] - u[1][2] * u[2][0]) +
-                      u[0][2] * (u[1][0] * u[2][1] - u[1][1] * u[2][0]);
-    if (D == 0) continue;
-    if (D < 0) std::swap(v[0], v[1]);
-    tet[t] = make_int4(v[0], v[1], v[2], v[3]);
-    keep[t] = 1;
-    ++kept;
-  }
-  // bucket edge: about one kept tetrahedron per 2 bucket points
-  const double per = kept > 0 ? (double)npts / kept : (double)npts;
-  int bucket = (int)std::lround(2.0 * std::cbrt(per));
-  bucket = std::max(2, std::min(bucket, 32));
-  int nb[3];
-  for (int a = 0; a < 3; ++a) nb[a] = (n[a] + bucket - 1) / bucket;
-  const int64_t nbuckets = (int64_t)nb[0] * nb[1] * nb[2];
-  std::vector<int64_t> count(nbuckets + 1, 0);
-  auto for_buckets = [&](int32_t t, auto&& fn) {
-    const int vv[4] = {tet[t].x, tet[t].y, tet[t].z, tet[t].w};
-    int lo[3], hi[3];
-    for (int a = 0; a < 3; ++a) {
-      int64_t mn = coord(vv[0], a), mx = mn;
-      for (int i = 1; i < 4; ++i) {
-        mn = std::min(mn, coord(vv[i], a));
-        mx = std::max(mx, coord(vv[i], a));
-      }
-      lo[a] = (int)(mn / bucket);
-      hi[a] = (int)(mx / bucket);
-    }
-    for (int bz = lo[2]; bz <= hi[2]; ++bz)
-      for (int by = lo[1]; by <= hi[1]; ++by)
-        for (int bx = lo[0]; bx <= hi[0]; ++bx) fn(bx + (int64_t)nb[0] * (by + (int64_t)nb[1] * bz));
-  };
-  for (int32_t t = 0; t < n_tets; ++t)
-    if (keep[t]) for_buckets(t, [&](int64_t b) { ++count[b + 1]; });
-  for (int64_t b = 0; b < nbuckets; ++b) count[b + 1] += count[b];
-  if (count[nbuckets] >= 2147483647LL)
-    return report_error(SGQ_EINVAL, "bucket lists exceed 2^31 entries");
-  std::vector<int32_t> bstart(nbuckets + 1), blist(std::max<int64_t>(count[nbuckets], 1));
-  for (int64_t b = 0; b <= nbuckets; ++b) bstart[b] = (int32_t)count[b];
-  std::vector<int64_t> fill(count.begin(), count.end() - 1);
-  for (int32_t t = 0; t < n_tets; ++t)
-    if (keep[t]) for_buckets(t, [&](int64_t b) { blist[fill[b]++] = t; });
-
+  const int32_t kept = geo.kept;
+  const int bucket = geo.bucket;
+  const int* nb = geo.nb;
+  // the [n][4] int32 arrays have the layout of int4 records
+  static_assert(sizeof(int4) == 4 * sizeof(int32_t), "int4 records");
+  const std::vector<int32_t>& bstart = geo.bstart;
+  const std::vector<int32_t>& blist = geo.blist;
+  const size_t ntet = geo.tet.size() / 4;
   sgq_fe_mesh* m = new sgq_fe_mesh;
   for (int a = 0; a < 3; ++a) {
     m->n[a] = n[a];
@@ -352,17 +289,19 @@ extern "C" int sgq_fe_mesh_create(const int32_t n[3], const int64_t* esp_center,
   FE_HIP(hipGetDevice(&m->device));
   FE_HIP(hipMalloc(&m->d_esp, sizeof(int4) * n_esp));
   FE_HIP(hipMalloc(&m->d_xyz, sizeof(uint2) * n_esp));
-  FE_HIP(hipMalloc(&m->d_tet, sizeof(int4) * tet.size()));
+  FE_HIP(hipMalloc(&m->d_tet, sizeof(int4) * ntet));
   FE_HIP(hipMalloc(&m->d_bstart, sizeof(int32_t) * bstart.size()));
   FE_HIP(hipMalloc(&m->d_blist, sizeof(int32_t) * blist.size()));
   FE_HIP(hipMalloc(&m->d_loc, sizeof(int32_t) * npts));
   FE_HIP(hipMalloc(&m->d_corr, sizeof(double) * max_fields * (size_t)n_esp));
-  FE_HIP(hipMemcpy(m->d_esp, esp.data(), sizeof(int4) * n_esp, hipMemcpyHostToDevice));
+  FE_HIP(hipMemcpy(m->d_esp, geo.esp.data(), sizeof(int4) * n_esp, hipMemcpyHostToDevice));
   std::vector<uint2> packed(n_esp);
-  for (int32_t q = 0; q < n_esp; ++q)
-    packed[q] = make_uint2((uint32_t)esp[q].x | ((uint32_t)esp[q].y << 16), (uint32_t)esp[q].z);
+  for (int32_t q = 0; q < n_esp; ++q) {
+    const int32_t* e = geo.esp.data() + 4 * (size_t)q;
+    packed[q] = make_uint2((uint32_t)e[0] | ((uint32_t)e[1] << 16), (uint32_t)e[2]);
+  }
   FE_HIP(hipMemcpy(m->d_xyz, packed.data(), sizeof(uint2) * n_esp, hipMemcpyHostToDevice));
-  FE_HIP(hipMemcpy(m->d_tet, tet.data(), sizeof(int4) * tet.size(), hipMemcpyHostToDevice));
+  FE_HIP(hipMemcpy(m->d_tet, geo.tet.data(), sizeof(int4) * ntet, hipMemcpyHostToDevice));
   FE_HIP(hipMemcpy(m->d_bstart, bstart.data(), sizeof(int32_t) * bstart.size(), hipMemcpyHostToDevice));
   FE_HIP(hipMemcpy(m->d_blist, blist.data(), sizeof(int32_t) * blist.size(), hipMemcpyHostToDevice));
   hipLaunchKernelGGL(sgq::fe_locate_kernel, dim3(sgq::fe_grid(npts)), dim3(sgq::kFeBlock), 0, 0,

@@ -89,6 +89,10 @@ __global__ void gauss_rule_kernel(LaunchParams P) {
     if (P.rho) P.rho[q] = nan;
     if (P.e_node) P.e_node[q] = nan;
     if (P.k_eff) P.k_eff[q] = 0;
+    // a NaN rule, so that a Fermi-level solve on these rules latches a non-finite input
+    // even though it starts with a clear status word
+    if (P.theta_w)
+      for (int k = 0; k < 2 * kmax; ++k) P.theta_w[(size_t)q * kmax * 2 + k] = nan;
     return;
   }
   SGQ_L double* base = (SGQ_L double*)lds_tri;
@@ -133,38 +137,55 @@ __global__ void gauss_rule_kernel(LaunchParams P) {
 }
 
 // ------------------------------------------------------------------ setup kernels
-__global__ void reset_kernel(int* queue, int* status, double* vmax) {
+__global__ void reset_kernel(int* queue, int* status, double* vmax, unsigned long long* hash) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     *queue = 0;
     *status = 0;
     *vmax = 0.0;
+    *hash = 0ull;
   }
 }
 
-// Potential in the storage precision, max |V| (order-independent) and a finiteness check.
+// Potential in the storage precision, max |V| (order-independent), a finiteness check and
+// the potential's part of the input hash (a wrapping sum of mixed (value, index) pairs, so
+// the order of the additions does not matter).
 template <typename T>
 __global__ void prepare_potential_kernel(const double* __restrict__ v64, T* __restrict__ vout,
-                                         size_t n, double* vmax, int* status) {
+                                         size_t n, double* vmax, int* status,
+                                         unsigned long long* hash) {
   __shared__ double red[1024 / kWave];
+  __shared__ unsigned long long hred[1024 / kWave];
   double mx = 0.0;
+  unsigned long long hs = 0ull;
   bool bad = false;
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
        i += (size_t)gridDim.x * blockDim.x) {
     double v = v64[i];
     if (!isfinite(v)) bad = true;
     mx = fmax(mx, fabs(v));
+    hs += mix64((unsigned long long)__double_as_longlong(v) ^ mix64(i));
     if (vout) vout[i] = (T)v;
   }
   if (bad) atomicOr(status, kStatusNonFinite);
 #pragma unroll
-  for (int off = kWave / 2; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, kWave));
-  if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = mx;
+  for (int off = kWave / 2; off > 0; off >>= 1) {
+    mx = fmax(mx, __shfl_xor(mx, off, kWave));
+    hs += __shfl_xor(hs, off, kWave);
+  }
+  if ((threadIdx.x & (kWave - 1)) == 0) {
+    red[threadIdx.x / kWave] = mx;
+    hred[threadIdx.x / kWave] = hs;
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
-    for (int w = 1; w < (int)(blockDim.x / kWave); ++w) mx = fmax(mx, red[w]);
+    for (int w = 1; w < (int)(blockDim.x / kWave); ++w) {
+      mx = fmax(mx, red[w]);
+      hs += hred[w];
+    }
     // non-negative doubles order like their bit patterns
     atomicMax(reinterpret_cast<unsigned long long*>(vmax),
               (unsigned long long)__double_as_longlong(mx));
+    atomicAdd(hash, hs);
   }
 }
 
@@ -180,6 +201,11 @@ __global__ void projector_table_kernel(LaunchParams P, T* __restrict__ chi, int3
     bool bad = !(isfinite(Rx) && isfinite(Ry) && isfinite(Rz));
     for (int l = 0; l < 4; ++l) bad = bad || !isfinite(P.proj_E[4 * J + l]);
     if (bad) atomicOr(P.status, kStatusNonFinite);
+    // the atom's part of the input hash: its position and projector energies
+    unsigned long long hs = mix64(~(unsigned long long)J);
+    for (int c = 0; c < 3; ++c) hs = mix64(hs ^ (unsigned long long)__double_as_longlong(P.atom_R[3 * J + c]));
+    for (int l = 0; l < 4; ++l) hs = mix64(hs ^ (unsigned long long)__double_as_longlong(P.proj_E[4 * J + l]));
+    atomicAdd(P.hash + P.hash_slot, hs);
     g0[3 * J] = bad ? 0 : gx;
     g0[3 * J + 1] = bad ? 0 : gy;
     g0[3 * J + 2] = bad ? 0 : gz;
@@ -217,170 +243,6 @@ __global__ void weighted_sum_kernel(const double* __restrict__ e, const double* 
   if (threadIdx.x == 0) *out = red[0];
 }
 
-// Fermi level of stored Gauss rules: the mu at which
-//   N(mu) = 2 sum_q n_q sum_k w_k g(theta_k; mu)
-// equals ne.  N increases strictly with mu.  A first pass brackets the level by every rule
-// point -+ 60 kT and totals the count; then safeguarded Newton steps (dN/dmu =
-// 2 sum n w g (1 - g) / kT; a step that leaves the bracket is replaced by bisection) run
-// until |N - ne| <= tol ne, the bracket shrinks to rounding, or kFermiSteps steps.
-//
-// Every pass spreads the rule points over the whole chip: fermi_partial_kernel writes one
-// partial sum per workgroup, and fermi_update_kernel (one wavefront) combines them in a
-// fixed order and takes the step.  The host enqueues kFermiSteps pass pairs; once the
-// state says done, the remaining launches return at once.  Points more than 36 kT from mu
-// count as fully occupied or empty (g differs from 0 or 1 by less than 2.4e-16 there).
-// State ws[0..5] = mu, lo, hi, N, step, done (0 running, 1 finished, 2 error); partials
-// from ws[16], four per workgroup.  out[0] = mu, out[1] = N(mu), out[2] = steps taken.
-__global__ __launch_bounds__(kFermiThreads) void fermi_partial_kernel(
-    const double* __restrict__ tw, const double* __restrict__ weight, int nq, int kmax,
-    double kT, int mode, double* __restrict__ ws) {
-  constexpr int NW = kFermiThreads / kWave;
-  __shared__ double red[4][NW];
-  if (mode == 1 && ws[5] != 0.0) return;   // the same value for every lane: uniform exit
-  const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
-  const unsigned ntot = (unsigned)nq * (unsigned)kmax;   // < 2^31 (checked by the host)
-  const double mu = ws[0];
-  double a0, a1, a2 = 0.0, a3 = 0.0;
-  if (mode == 0) {
-    a0 = __builtin_inf();    // lowest rule point
-    a1 = -__builtin_inf();   // highest
-  } else {
-    a0 = 0.0;                // sum n w g
-    a1 = 0.0;                // sum n w g (1 - g)
-  }
-  for (unsigned e = blockIdx.x * kFermiThreads + tid; e < ntot; e += gridDim.x * kFermiThreads) {
-    const double th = tw[2 * e], w = tw[2 * e + 1], n = weight[e / (unsigned)kmax];
-    if (mode == 0) {
-      if (!isfinite(th) || !isfinite(w) || !isfinite(n)) a3 = 1.0;
-      if (w > 0.0) {
-        a0 = fmin(a0, th);
-        a1 = fmax(a1, th);
-        a2 += n * w;
-      }
-    } else if (w > 0.0) {
-      const double x = (th - mu) / kT;
-      const double nw = n * w;
-      if (x < -36.0) {
-        a0 += nw;
-      } else if (x <= 36.0) {
-        const double g = fermi_occ(x);
-        a0 += nw * g;
-        a1 += nw * g * (1.0 - g);
-      }
-    }
-  }
-  if (mode == 0) {
-#pragma unroll
-    for (int off = kWave / 2; off > 0; off >>= 1) {
-      a0 = fmin(a0, __shfl_xor(a0, off, kWave));
-      a1 = fmax(a1, __shfl_xor(a1, off, kWave));
-      a3 = fmax(a3, __shfl_xor(a3, off, kWave));
-    }
-  } else {
-    a0 = wave_sum(a0);
-    a1 = wave_sum(a1);
-  }
-  a2 = wave_sum(a2);
-  if (lane == 0) {
-    red[0][wave] = a0;
-    red[1][wave] = a1;
-    red[2][wave] = a2;
-    red[3][wave] = a3;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    double b0 = red[0][0], b1 = red[1][0], b2 = red[2][0], b3 = red[3][0];
-    for (int w = 1; w < NW; ++w) {
-      b0 = mode == 0 ? fmin(b0, red[0][w]) : b0 + red[0][w];
-      b1 = mode == 0 ? fmax(b1, red[1][w]) : b1 + red[1][w];
-      b2 += red[2][w];
-      b3 = fmax(b3, red[3][w]);
-    }
-    double* part = ws + 16 + 4 * blockIdx.x;
-    part[0] = b0;
-    part[1] = b1;
-    part[2] = b2;
-    part[3] = b3;
-  }
-}
-
-__global__ __launch_bounds__(kWave) void fermi_update_kernel(int nparts, int mode, double ne,
-                                                             double kT, double tol,
-                                                             double* __restrict__ ws,
-                                                             double* __restrict__ out,
-                                                             int* status) {
-  const int lane = threadIdx.x;
-  if (mode == 1 && ws[5] != 0.0) return;
-  const double* part = ws + 16;
-  double a0, a1, a2 = 0.0, a3 = 0.0;
-  if (mode == 0) {
-    a0 = __builtin_inf();
-    a1 = -__builtin_inf();
-  } else {
-    a0 = 0.0;
-    a1 = 0.0;
-  }
-  for (int b = lane; b < nparts; b += kWave) {
-    a0 = mode == 0 ? fmin(a0, part[4 * b]) : a0 + part[4 * b];
-    a1 = mode == 0 ? fmax(a1, part[4 * b + 1]) : a1 + part[4 * b + 1];
-    a2 += part[4 * b + 2];
-    a3 = fmax(a3, part[4 * b + 3]);
-  }
-  if (mode == 0) {
-#pragma unroll
-    for (int off = kWave / 2; off > 0; off >>= 1) {
-      a0 = fmin(a0, __shfl_xor(a0, off, kWave));
-      a1 = fmax(a1, __shfl_xor(a1, off, kWave));
-      a3 = fmax(a3, __shfl_xor(a3, off, kWave));
-    }
-  } else {
-    a0 = wave_sum(a0);
-    a1 = wave_sum(a1);
-  }
-  a2 = wave_sum(a2);
-  if (lane != 0) return;
-  if (mode == 0) {
-    *status = 0;   // this call's latch
-    const double total = 2.0 * a2 + (a3 != 0.0 ? __builtin_nan("") : 0.0);
-    if (!(isfinite(total) && ne > 0.0 && ne < total)) {
-      atomicOr(status, isfinite(total) ? kStatusRange : kStatusNonFinite);
-      out[0] = out[1] = __builtin_nan("");
-      out[2] = 0.0;
-      ws[5] = 2.0;
-      return;
-    }
-    const double lo = a0 - 60.0 * kT, hi = a1 + 60.0 * kT;
-    ws[0] = 0.5 * (lo + hi);
-    ws[1] = lo;
-    ws[2] = hi;
-    ws[3] = 0.0;
-    ws[4] = 0.0;
-    ws[5] = 0.0;
-    return;
-  }
-  const double N = 2.0 * a0, dN = 2.0 * a1 / kT, f = N - ne;
-  double mu = ws[0], lo = ws[1], hi = ws[2];
-  const int it = (int)ws[4];
-  bool done = fabs(f) <= tol * ne || it >= kFermiSteps - 1;
-  if (!done) {
-    if (f < 0.0) lo = mu; else hi = mu;
-    done = hi - lo <= 4.0 * 2.220446049250313e-16 * fmax(1.0, fabs(mu));
-  }
-  if (done) {
-    out[0] = mu;
-    out[1] = N;
-    out[2] = (double)(it + 1);
-    ws[5] = 1.0;
-    return;
-  }
-  const double cand = mu - f / dN;
-  ws[0] = (dN > 0.0 && cand > lo && cand < hi) ? cand : 0.5 * (lo + hi);
-  ws[1] = lo;
-  ws[2] = hi;
-  ws[3] = N;
-  ws[4] = (double)(it + 1);
-}
-
 // ------------------------------------------------------------------ host launchers
 template <typename T, int BLOCK>
 static hipError_t launch_forward_t(const LaunchParams& P, int grid, int kg, hipStream_t s) {
@@ -408,16 +270,17 @@ hipError_t launch_forward(const LaunchParams& P, bool fp64, int grid, int block,
 
 hipError_t launch_setup(const LaunchParams& P, bool fp64, const double* v64, void* vstore,
                         void* chi, int32_t* g0, double* vmax, hipStream_t s) {
-  hipLaunchKernelGGL(reset_kernel, dim3(1), dim3(1), 0, s, P.queue, P.status, vmax);
+  unsigned long long* hash = P.hash + P.hash_slot;
+  hipLaunchKernelGGL(reset_kernel, dim3(1), dim3(1), 0, s, P.queue, P.status, vmax, hash);
   size_t n = (size_t)P.nx * P.ny * P.nz;
   int blocks = (int)((n + 1023) / 1024);
   if (blocks > 1024) blocks = 1024;
   if (fp64) {
     hipLaunchKernelGGL(prepare_potential_kernel<double>, dim3(blocks), dim3(1024), 0, s, v64,
-                       (double*)nullptr, n, vmax, P.status);
+                       (double*)nullptr, n, vmax, P.status, hash);
   } else {
     hipLaunchKernelGGL(prepare_potential_kernel<float>, dim3(blocks), dim3(1024), 0, s, v64,
-                       (float*)vstore, n, vmax, P.status);
+                       (float*)vstore, n, vmax, P.status, hash);
   }
   if (P.n_proj > 0 && P.n_atoms > 0) {
     if (fp64)
@@ -436,21 +299,6 @@ hipError_t launch_gauss_rule(const LaunchParams& P, hipStream_t s) {
   const int nt = P.kmax_out <= 40 ? 64 : (P.kmax_out <= 80 ? 32 : 16);
   const size_t lds = (size_t)3 * P.kmax_out * nt * sizeof(double);
   hipLaunchKernelGGL(gauss_rule_kernel, dim3((P.n_nodes + nt - 1) / nt), dim3(nt), lds, s, P);
-  return hipGetLastError();
-}
-
-hipError_t launch_fermi_level(const double* tw, const double* weight, int nq, int kmax,
-                              double ne, double kT, double tol, double* out, int* status,
-                              double* ws, hipStream_t s) {
-  const size_t ntot = (size_t)nq * kmax;
-  const int parts = (int)std::min<size_t>(kFermiBlocks, (ntot + kFermiThreads - 1) / kFermiThreads);
-  for (int step = -1; step < kFermiSteps; ++step) {
-    const int mode = step < 0 ? 0 : 1;
-    hipLaunchKernelGGL(fermi_partial_kernel, dim3(parts), dim3(kFermiThreads), 0, s, tw, weight, nq,
-                       kmax, kT, mode, ws);
-    hipLaunchKernelGGL(fermi_update_kernel, dim3(1), dim3(kWave), 0, s, parts, mode, ne, kT, tol, ws,
-                       out, status);
-  }
   return hipGetLastError();
 }
 

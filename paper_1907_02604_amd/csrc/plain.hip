@@ -257,7 +257,8 @@ __global__ void plain_norm_kernel(int nblocks, int j, const double* partial, Pla
 }
 
 __global__ void plain_quadrature_kernel(LaunchParams P, int q, PlainScalars* S) {
-  double a[kMaxDepth], b[kMaxDepth], z[kMaxDepth];
+  // one thread: its three arrays in LDS, so the kernel needs no private (scratch) memory
+  __shared__ double a[kMaxDepth], b[kMaxDepth], z[kMaxDepth];
   const int K = S->keff;
   for (int k = 0; k < K; ++k) a[k] = S->alpha[k];
   for (int k = 0; k + 1 < K; ++k) b[k] = S->beta[k];

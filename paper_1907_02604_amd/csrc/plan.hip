@@ -47,17 +47,7 @@ hipError_t launch_vloc_backward(const double* dV, const double* R, int M, int nx
 
 using namespace sgq;
 
-static thread_local std::string g_error;
-
-static int fail(int code, const std::string& msg) {
-  g_error = msg;
-  return code;
-}
-
-namespace sgq {
-// Error reporting for entry points defined in other sources of the library.
-int report_error(int code, const std::string& msg) { return fail(code, msg); }
-}  // namespace sgq
+static int fail(int code, const std::string& msg) { return report_error(code, msg); }
 
 #define HIP_OR_FAIL(expr)                                                             \
   do {                                                                                \
@@ -91,6 +81,7 @@ struct sgq_plan {
   double* d_tri = nullptr;
   int32_t* d_trik = nullptr;
   double* d_fermi = nullptr;   // Fermi-level state and per-workgroup partial sums
+  unsigned long long* d_hash = nullptr;   // input hashes: last forward call, current backward
   // retained forward bases (sgq_plan_set_retain): valid after a forward call with these
   // input pointers, consumed by the next backward call
   bool retain = false, ret_valid = false;
@@ -144,11 +135,6 @@ static hipError_t dalloc(sgq_plan* p, T** out, size_t bytes) {
   return e;
 }
 
-static int box_half_width(double rc, double h) {
-  // grid offsets d from the nearest grid point that can lie within rc: d < rc/h + 1/2
-  return (int)std::ceil(rc / h + 0.5) - 1;
-}
-
 // Continuum normalisation of the projectors: int chi^2 d^3r = 1 (composite Simpson).
 static void projector_norms(double rg, double rc, double* ns, double* np_) {
   const int n = 200000;
@@ -168,46 +154,6 @@ static void projector_norms(double rg, double rc, double* ns, double* np_) {
   ip *= dr / 3.0;
   *ns = 1.0 / std::sqrt(is);
   *np_ = 1.0 / std::sqrt(ip);
-}
-
-extern "C" const char* sgq_last_error(void) { return g_error.c_str(); }
-
-extern "C" int sgq_validate(const sgq_problem* prob, const int64_t* center,
-                            const int32_t* half_width, const int32_t* depth) {
-  if (!prob) return fail(SGQ_EINVAL, "problem is null");
-  for (int a = 0; a < 3; ++a)
-    if (prob->n[a] < 1) return fail(SGQ_EINVAL, "grid extent must be >= 1");
-  double ng = (double)prob->n[0] * prob->n[1] * prob->n[2];
-  if (ng >= 2147483647.0) return fail(SGQ_EINVAL, "grid has 2^31 or more points");
-  if (!(prob->h > 0.0) || !std::isfinite(prob->h)) return fail(SGQ_EINVAL, "h must be > 0");
-  if (prob->n_atoms < 0) return fail(SGQ_EINVAL, "n_atoms < 0");
-  if (prob->n_proj != 0 && prob->n_proj != 4) return fail(SGQ_EINVAL, "n_proj must be 0 or 4");
-  if (prob->precision != SGQ_FP64 && prob->precision != SGQ_FP32)
-    return fail(SGQ_EINVAL, "precision must be SGQ_FP64 or SGQ_FP32");
-  int m = 3;
-  if (prob->n_proj == 4) {
-    if (!(prob->proj_rc > 0.0) || !(prob->proj_rg > 0.0) || !std::isfinite(prob->proj_rc) ||
-        !std::isfinite(prob->proj_rg))
-      return fail(SGQ_EINVAL, "projector radii must be > 0");
-    m = std::max(3, box_half_width(prob->proj_rc, prob->h));
-    if (2 * m + 1 > 33) return fail(SGQ_EINVAL, "projector cutoff spans more than 33 points");
-  }
-  if (prob->n_nodes < 0) return fail(SGQ_EINVAL, "n_nodes < 0");
-  if (prob->n_nodes > 0 && (!center || !half_width || !depth))
-    return fail(SGQ_EINVAL, "node arrays are null");
-  int nmin = std::min(prob->n[0], std::min(prob->n[1], prob->n[2]));
-  for (int q = 0; q < prob->n_nodes; ++q) {
-    if (center[q] < 0 || (double)center[q] >= ng)
-      return fail(SGQ_EINVAL, "node " + std::to_string(q) + ": centre outside the grid");
-    if (depth[q] < 1 || depth[q] > kMaxDepth)
-      return fail(SGQ_EINVAL, "node " + std::to_string(q) + ": depth outside [1, 128]");
-    int R = half_width[q];
-    if (R < -1) return fail(SGQ_EINVAL, "node " + std::to_string(q) + ": half_width < -1");
-    if (R >= 0 && 2 * R + 1 > nmin - 2 * m)
-      return fail(SGQ_EINVAL, "node " + std::to_string(q) +
-                                  ": cube side exceeds the grid minus the stencil/projector reach");
-  }
-  return SGQ_OK;
 }
 
 extern "C" int sgq_plan_create(const sgq_problem* prob, const int64_t* center,
@@ -285,6 +231,7 @@ extern "C" int sgq_plan_create(const sgq_problem* prob, const int64_t* center,
   e = e ? e : dalloc(p, &p->d_tri, (size_t)nq * 2 * p->kmax * 8);
   e = e ? e : dalloc(p, &p->d_trik, (size_t)nq * 4);
   e = e ? e : dalloc(p, &p->d_fermi, (size_t)(16 + 4 * kFermiBlocks) * 8);
+  e = e ? e : dalloc(p, &p->d_hash, 2 * sizeof(unsigned long long));
   if (e != hipSuccess) {
     free_all(p);
     delete p;
@@ -296,6 +243,7 @@ extern "C" int sgq_plan_create(const sgq_problem* prob, const int64_t* center,
   e = e ? e : hipMemcpy(p->d_hw, p->h_hw.data(), nq * 4, hipMemcpyHostToDevice);
   e = e ? e : hipMemcpy(p->d_depth, p->h_depth.data(), nq * 4, hipMemcpyHostToDevice);
   e = e ? e : hipMemset(p->d_status, 0, 8);
+  e = e ? e : hipMemset(p->d_hash, 0, 2 * sizeof(unsigned long long));
   if (e != hipSuccess) {
     free_all(p);
     delete p;
@@ -367,6 +315,8 @@ static LaunchParams base_params(sgq_plan* p, const double* v_loc, const double* 
   P.Wr = p->retain ? p->d_Wr : nullptr;
   P.Ur = p->retain ? p->d_Ur : nullptr;
   P.ret_slot = p->retain ? p->d_ret_slot : nullptr;
+  P.hash = p->d_hash;
+  P.hash_slot = 0;
   return P;
 }
 
@@ -456,13 +406,6 @@ extern "C" int rho_quadrature(sgq_plan* plan, const double* v_loc, const double*
     if (theta_w) return fail(SGQ_EPLAN, "the plain schedule does not return the Gauss rule");
     hipStream_t s = (hipStream_t)stream;
     HIP_OR_FAIL(hipSetDevice(plan->device));
-    if (!plan->d_plain) {
-      hipError_t e = dalloc(plan, &plan->d_plain, plain_scratch_bytes(plan->npad, plan->kmax, plan->fp64));
-      if (e != hipSuccess) {
-        (void)hipGetLastError();
-        return fail(SGQ_ENOMEM, "plain schedule scratch");
-      }
-    }
     P.slot_stride = (size_t)plan->kmax * plan->npad;
     HIP_OR_FAIL(launch_setup(P, plan->fp64, v_loc, plan->d_v, plan->d_chi, plan->d_g0, plan->d_vmax, s));
     plan->ret_valid = false;
@@ -478,6 +421,15 @@ extern "C" int sgq_plan_set_schedule(sgq_plan* plan, int schedule) {
   if (!plan) return fail(SGQ_EINVAL, "plan is null");
   if (schedule != SGQ_SCHEDULE_BATCHED && schedule != SGQ_SCHEDULE_PLAIN)
     return fail(SGQ_EINVAL, "unknown schedule");
+  if (schedule == SGQ_SCHEDULE_PLAIN && !plan->d_plain) {
+    // the plain schedule's scratch is allocated here, so that its compute calls allocate nothing
+    HIP_OR_FAIL(hipSetDevice(plan->device));
+    hipError_t e = dalloc(plan, &plan->d_plain, plain_scratch_bytes(plan->npad, plan->kmax, plan->fp64));
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(SGQ_ENOMEM, std::string("plain schedule scratch: ") + hipGetErrorString(e));
+    }
+  }
   plan->schedule = schedule;
   return SGQ_OK;
 }
@@ -754,72 +706,32 @@ extern "C" int band_energy(sgq_plan* plan, const double* v_loc, const double* at
   return run_forward(plan, 1, P, v_loc, node_weight, omega, (hipStream_t)stream);
 }
 
-// Backward workspace, node cube offsets and the dV gather lists (first backward call).
+// Backward workspace, node cube offsets and the dV gather lists (sgq_plan_prepare_backward).
 static int ensure_backward(sgq_plan* p) {
   if (p->bwd_ready) return SGQ_OK;
+  if (p->kmax > backward_max_depth())
+    return fail(SGQ_EPLAN, "backward supports Lanczos depths up to " +
+                               std::to_string(backward_max_depth()));
   const int nq = p->prob.n_nodes;
   const size_t es = p->fp64 ? 8 : 4;
-  const int nx = p->prob.n[0], ny = p->prob.n[1], nz = p->prob.n[2];
   // node cubes of the per-node dV contributions, each rounded up to 4 values so that every
   // cube starts 16-byte aligned (the reverse recurrence updates it with vector accesses)
-  std::vector<int64_t> off(nq + 1, 0);
-  for (int q = 0; q < nq; ++q) {
-    int64_t n = p->h_hw[q] < 0 ? (int64_t)p->n_grid : (int64_t)std::pow(2 * p->h_hw[q] + 1, 3);
-    off[q + 1] = off[q] + (n + 3) / 4 * 4;
-  }
+  const std::vector<int64_t> off = cube_offsets(p->h_hw, (int64_t)p->n_grid);
   // gather lists: for every cell of the grid, the nodes (ascending) whose cube meets it
-  const int C = gather_cell();
-  const int ncx = (nx + C - 1) / C, ncy = (ny + C - 1) / C, ncz = (nz + C - 1) / C;
-  const int ncells = ncx * ncy * ncz;
-  auto axis_cells = [&](int c, int R, int n, int nc, std::vector<int>& out) {
-    out.clear();
-    if (R < 0) {
-      for (int i = 0; i < nc; ++i) out.push_back(i);
-      return;
+  std::vector<int32_t> cstart, clist;
+  gather_lists(p->prob.n, p->h_center, p->h_hw, gather_cell(), cstart, clist);
+  const int ncells = (int)cstart.size() - 1;
+  {
+    hipError_t e = hipSuccess;
+    e = e ? e : dalloc(p, &p->d_cell_start, cstart.size() * 4);
+    e = e ? e : dalloc(p, &p->d_cell_nodes, std::max<size_t>(1, clist.size()) * 4);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(SGQ_ENOMEM, "gather lists: " + std::string(hipGetErrorString(e)));
     }
-    std::vector<char> seen(nc, 0);
-    for (int x = c - R; x <= c + R; ++x) {
-      int cx = ((x % n) + n) % n / C;
-      if (!seen[cx]) { seen[cx] = 1; out.push_back(cx); }
-    }
-  };
-  std::vector<int32_t> count(ncells + 1, 0);
-  std::vector<int> ax, ay, az;
-  for (int pass = 0; pass < 2; ++pass) {
-    std::vector<int32_t> fill;
-    if (pass == 1) fill.assign(count.begin(), count.end() - 1);
-    std::vector<int32_t>* nodes = nullptr;
-    static thread_local std::vector<int32_t> list;
-    if (pass == 1) {
-      list.assign(count[ncells], 0);
-      nodes = &list;
-    }
-    for (int q = 0; q < nq; ++q) {
-      const int c = p->h_center[q], R = p->h_hw[q];
-      axis_cells(c % nx, R, nx, ncx, ax);
-      axis_cells((c / nx) % ny, R, ny, ncy, ay);
-      axis_cells(c / (nx * ny), R, nz, ncz, az);
-      for (int kz : az)
-        for (int ky : ay)
-          for (int kx : ax) {
-            const int cell = kx + ncx * (ky + ncy * kz);
-            if (pass == 0) ++count[cell + 1];
-            else (*nodes)[fill[cell]++] = q;
-          }
-    }
-    if (pass == 0)
-      for (int i = 0; i < ncells; ++i) count[i + 1] += count[i];
-    if (pass == 1) {
-      hipError_t e = hipSuccess;
-      e = e ? e : dalloc(p, &p->d_cell_start, (size_t)(ncells + 1) * 4);
-      e = e ? e : dalloc(p, &p->d_cell_nodes, std::max<size_t>(1, list.size()) * 4);
-      if (e != hipSuccess) return fail(SGQ_ENOMEM, "gather lists: " + std::string(hipGetErrorString(e)));
-      HIP_OR_FAIL(hipMemcpy(p->d_cell_start, count.data(), (ncells + 1) * 4, hipMemcpyHostToDevice));
-      if (!list.empty())
-        HIP_OR_FAIL(hipMemcpy(p->d_cell_nodes, list.data(), list.size() * 4, hipMemcpyHostToDevice));
-      list.clear();
-      list.shrink_to_fit();
-    }
+    HIP_OR_FAIL(hipMemcpy(p->d_cell_start, cstart.data(), cstart.size() * 4, hipMemcpyHostToDevice));
+    if (!clist.empty())
+      HIP_OR_FAIL(hipMemcpy(p->d_cell_nodes, clist.data(), clist.size() * 4, hipMemcpyHostToDevice));
   }
   p->ncells = ncells;
   // two workgroups per CU (node state and adjoint scalars fit twice in a CU's LDS; the
@@ -853,12 +765,9 @@ extern "C" int band_energy_backward(sgq_plan* plan, const double* v_loc, const d
   if (!grad_omega || !dV || (plan->prob.n_nodes > 0 && !node_weight))
     return fail(SGQ_EINVAL, "grad_omega, dV and node_weight are required");
   if (integrand < SGQ_BAND || integrand > SGQ_GRAND) return fail(SGQ_EINVAL, "bad integrand");
-  if (plan->kmax > backward_max_depth())
-    return fail(SGQ_EPLAN, "backward supports Lanczos depths up to " +
-                               std::to_string(backward_max_depth()));
+  if (!plan->bwd_ready)
+    return fail(SGQ_EPLAN, "the backward workspace is not prepared: call sgq_plan_prepare_backward");
   HIP_OR_FAIL(hipSetDevice(plan->device));
-  st = ensure_backward(plan);
-  if (st != SGQ_OK) return st;
   hipStream_t s = (hipStream_t)stream;
   LaunchParams P = base_params(plan, v_loc, atom_R, proj_E, mu, kT);
   P.W = plan->d_Wb;
@@ -876,6 +785,9 @@ extern "C" int band_energy_backward(sgq_plan* plan, const double* v_loc, const d
   // overwrites their u_j rows, so they serve one backward call)
   P.use_retained = plan->retain && plan->ret_valid && plan->ret_key[0] == v_loc &&
                    plan->ret_key[1] == atom_R && plan->ret_key[2] == proj_E;
+  // this call's setup hashes the inputs' contents into the second entry; the kernel takes
+  // the retained rows only when the forward call's hash agrees
+  P.hash_slot = 1;
   plan->ret_valid = false;
   HIP_OR_FAIL(launch_setup(P, plan->fp64, v_loc, plan->d_v, plan->d_chi, plan->d_g0, plan->d_vmax, s));
   if (plan->prob.n_nodes > 0)
@@ -889,6 +801,12 @@ extern "C" int band_energy_backward(sgq_plan* plan, const double* v_loc, const d
                                      plan->ncells, dV, dR_nl, dE, s));
   plan->last = s;
   return SGQ_OK;
+}
+
+extern "C" int sgq_plan_prepare_backward(sgq_plan* plan) {
+  if (!plan) return fail(SGQ_EINVAL, "plan is null");
+  HIP_OR_FAIL(hipSetDevice(plan->device));
+  return ensure_backward(plan);
 }
 
 extern "C" int sgq_vloc_gaussian_backward(sgq_plan* plan, const double* dV, const double* atom_R,
@@ -918,23 +836,5 @@ extern "C" int sgq_plan_status(sgq_plan* plan, int32_t* host_status) {
                  : (bits & kStatusRange)   ? SGQ_ERANGE
                  : (bits & kStatusIndex)   ? SGQ_EINDEX
                                            : SGQ_OK;
-  return SGQ_OK;
-}
-
-extern "C" int sgq_gauss_rule_host(const double* alpha, const double* beta, int K, double* theta,
-                                   double* weight) {
-  if (!alpha || !theta || !weight || K < 1 || K > kMaxDepth || (K > 1 && !beta))
-    return fail(SGQ_EINVAL, "bad arguments");
-  double a[kMaxDepth], b[kMaxDepth], z[kMaxDepth];
-  for (int i = 0; i < K; ++i) a[i] = alpha[i];
-  for (int i = 0; i + 1 < K; ++i) b[i] = beta[i];
-  if (!tridiag_gauss(a, b, z, K)) return fail(SGQ_ENONFINITE, "tridiagonal QR did not converge");
-  std::vector<int> idx(K);
-  std::iota(idx.begin(), idx.end(), 0);
-  std::sort(idx.begin(), idx.end(), [&](int i, int j) { return a[i] < a[j]; });
-  for (int k = 0; k < K; ++k) {
-    theta[k] = a[idx[k]];
-    weight[k] = z[idx[k]] * z[idx[k]];
-  }
   return SGQ_OK;
 }

@@ -5,6 +5,11 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include "host.h"
+
+// host and device code (the tridiagonal solver shared by the kernels and the host)
+#define SGQ_HD __host__ __device__
+
 // Address-space qualifiers for device functions that are not inlined: without them the
 // compiler must use FLAT accesses (and wait on every memory counter at once).
 #define SGQ_G __attribute__((address_space(1)))   // global memory
@@ -16,7 +21,6 @@ constexpr int kWave = 64;            // CDNA wavefront
 constexpr int kFermiBlocks = 512;    // Fermi-level passes: partial sums per pass
 constexpr int kFermiThreads = 256;   //   lanes per workgroup of a pass
 constexpr int kFermiSteps = 64;      //   Newton / bisection steps enqueued per call
-constexpr int kMaxDepth = 128;       // largest Lanczos depth K
 constexpr int kMaxNodeAtoms = 256;   // atoms whose projector box meets one node cube
 
 // Status bits latched by kernels (mapped to sgq_status by the host).
@@ -79,12 +83,25 @@ struct LaunchParams {
   double* dR_part;            // [Nq][kMaxNodeAtoms][3] node partials of dR (nonlocal)
   double* dE_part;            // [Nq][kMaxNodeAtoms][4] node partials of dE
   int32_t* node_atoms;        // [Nq][1 + kMaxNodeAtoms]: count, then the node's atom ids
-  double* zbuf;               // [slots][80*80] eigenvector matrix of T per backward slot
+  double* zbuf;               // [slots][Kb*Kb] eigenvector matrix of T per backward slot
   void* Wr;                   // retained bases [R][npad/64][kmax][64] (NULL: slots only)
   void* Ur;                   // retained u_j = H q_j rows [R][kmax][npad]
   const int32_t* ret_slot;    // [Nq] each node's place among the R retained ones, or -1
   int use_retained;           // backward: take the retained basis instead of recomputing
+  // 64-bit hashes of the inputs' contents (v_loc, atom_R, proj_E): [0] taken by the last
+  // forward call, [1] by the current backward call; setup writes entry hash_slot.  The
+  // backward takes retained bases only when the two agree.
+  unsigned long long* hash;
+  int hash_slot;
 };
+
+// splitmix64 finaliser: mixes the bits of one input value with its index for the input hash.
+__device__ __forceinline__ unsigned long long mix64(unsigned long long z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
 
 // Element index of point p in a vector stored in 64-point blocks with block stride bs
 // (bs = 64: a plain vector; bs = kmax*64: one row of the point-blocked Lanczos basis).

@@ -1,9 +1,15 @@
 // Gauss rule of a symmetric tridiagonal (Golub-Welsch): eigenvalues and the first
 // component of each eigenvector, by implicit-shift QR sweeps with Wilkinson shifts.
 // Written for one thread; the arrays may live in LDS or global memory.
+// SGQ_HD marks it for both the host and the device in the HIP sources (sgq_common.h); the
+// host-only build defines it empty.
 #pragma once
 
-#include "sgq_common.h"
+#include <cmath>
+
+#ifndef SGQ_HD
+#error "define SGQ_HD (include sgq_common.h) before tridiag.h"
+#endif
 
 namespace sgq {
 
@@ -14,7 +20,7 @@ namespace sgq {
 //           non-null the full eigenvector matrix is accumulated as well.
 // Returns false if an unreduced block failed to converge in 40*K sweeps.
 template <typename PA, typename PZ = double*>
-__host__ __device__ inline bool tridiag_gauss(PA a, PA b, PA z, int K, PZ Z = nullptr,
+SGQ_HD inline bool tridiag_gauss(PA a, PA b, PA z, int K, PZ Z = nullptr,
                                               int ld = 0) {
   for (int k = 0; k < K; ++k) z[k] = (k == 0) ? 1.0 : 0.0;
   if (Z) {

@@ -27,7 +27,7 @@ EXPORTED = ("sgq_plan_create", "sgq_plan_destroy", "rho_quadrature", "band_energ
             "sgq_cluster_energy", "sgq_fe_mesh_create", "sgq_fe_mesh_destroy",
             "sgq_fe_reconstruct", "sgq_fe_mesh_location", "sgq_fe_mesh_info", "sgq_lda_xc",
             "sgq_potential_create", "sgq_potential_destroy", "sgq_poisson",
-            "sgq_effective_potential", "sgq_plan_set_retain")
+            "sgq_effective_potential", "sgq_plan_set_retain", "sgq_plan_prepare_backward")
 
 
 class SgqError(RuntimeError):
@@ -62,6 +62,7 @@ def _load():
         "sgq_plan_set_schedule": (I, [P, I]),
         "sgq_plan_set_graph": (I, [P, I]),
         "sgq_plan_set_retain": (I, [P, I, ctypes.c_int64, P]),
+        "sgq_plan_prepare_backward": (I, [P]),
         "sgq_fermi_level": (I, [P, P, P, D, D, D, P, P]),
         "sgq_plan_autotune": (I, [P, P, P, P, D, D, I, P, ctypes.POINTER(ctypes.c_int32)]),
         "sgq_cluster_build": (I, [P, D, P, ctypes.c_int32, D, P, ctypes.c_int64, ctypes.c_int64,
@@ -194,6 +195,11 @@ class Plan:
         _check(_lib.sgq_plan_set_retain(self._h, 1 if enable else 0, int(max_bytes),
                                         ctypes.byref(n)))
         return n.value
+
+    def prepare_backward(self):
+        """sgq_plan_prepare_backward: allocate the backward workspace (synchronous; a no-op
+        once done)."""
+        _check(_lib.sgq_plan_prepare_backward(self._h))
 
     def set_graph(self, enable):
         """Capture and replay the forward launches as a HIP graph (default on)."""
@@ -440,6 +446,7 @@ def energy_backward(prob, kind=SGQ_FREE, grad_omega=1.0, plan=None, device="cuda
     """(dV [z,y,x], dR_nl [M,3], dE [M,4]) of Omega for a ``synth.Problem``."""
     import torch
     plan = plan or Plan.from_problem(prob)
+    plan.prepare_backward()
     v, R, E, w = device_inputs(prob, device)
     g = torch.full((1,), float(grad_omega), dtype=torch.float64, device=device)
     dV = torch.empty_like(v)
@@ -464,6 +471,8 @@ def _autograd():
             e = torch.empty(plan.n_nodes, dtype=torch.float64, device=v_loc.device)
             om = torch.empty(1, dtype=torch.float64, device=v_loc.device)
             v_loc, atom_R, proj_E = v_loc.contiguous(), atom_R.contiguous(), proj_E.contiguous()
+            if ctx.needs_input_grad[0] or ctx.needs_input_grad[1] or ctx.needs_input_grad[2]:
+                plan.prepare_backward()   # set-up: the backward call itself allocates nothing
             band_energy(plan, v_loc, atom_R, proj_E, node_weight, mu, kT, integrand, e, om)
             ctx.save_for_backward(v_loc, atom_R, proj_E, node_weight)
             ctx.plan, ctx.mu, ctx.kT, ctx.integrand, ctx.vloc_model = plan, mu, kT, integrand, vloc_model

@@ -232,3 +232,20 @@ def test_nodes_beyond_every_projector(precision):
     assert _rel(rho.cpu().numpy(), ref_rho) < tol
     assert _rel(dV.cpu().numpy(), rdV) < tol
     assert not torch.any(dR) and not torch.any(dE)
+
+
+def test_deep_adjoint_on_the_uneven_workload():
+    """96^3 uneven-batching workload: three stratified nodes (cubes 25^3..49^3) at depth
+    100, past the former 80 cap of the adjoint; kT = 0.005.  FP64 within 1e-6 and FP32
+    within 1e-4 of the oracle gradient, every output."""
+    from gpu_util import stratified_sample
+    P = synth.make_problem(3)
+    Q = P.subset(stratified_sample(P, 3, seed=31))
+    Q.depth[:] = 100
+    rdV, rdE, rdR = O.band_energy_backward(Q, kind=O.FREE)
+    for precision, tol in (("f64", 1e-6), ("f32", 1e-4)):
+        announce(f"C3 deep adjoint {precision}")
+        dV, dR, dE = _gpu_grad(Q, O.FREE, precision)
+        errs = _rel(dV, rdV), _rel(dR, rdR), _rel(dE, rdE)
+        print("C3 K=100 grad errs", precision, errs)
+        assert max(errs) < tol

@@ -272,8 +272,8 @@ def test_node_over_the_atom_limit_is_reported_and_skipped():
 
 def test_host_checks_of_compute_calls():
     """Calls the host rejects before launching anything: SGQ_EPLAN for a Gauss rule from the
-    plain schedule and for a backward deeper than its eigenvector matrix (K > 80), SGQ_EINVAL
-    for kT <= 0 or a non-finite mu.  The plan stays usable and matches the oracle after."""
+    plain schedule and for a backward before sgq_plan_prepare_backward, SGQ_EINVAL for
+    kT <= 0 or a non-finite mu.  The plan stays usable and matches the oracle after."""
     import torch
     from paper_1907_02604_amd import sgq
     P = synth.make_problem(2, grid=32, n_nodes=2)
@@ -298,17 +298,18 @@ def test_host_checks_of_compute_calls():
     assert plan.status() == sgq.SGQ_OK
     ref, _ = O.rho_quadrature(P)
     assert O.normwise_rel_err(rho.cpu().numpy(), ref) < 1e-4
-    plan.close()
-    deep = synth.make_problem(2, grid=32, n_nodes=1)
-    deep.half_width[:] = 4
-    deep.depth[:] = 81
-    dplan = sgq.Plan.from_problem(deep)
-    v, R, E, w = sgq.device_inputs(deep)
     g = torch.ones(1, dtype=torch.float64, device="cuda")
     dV = torch.empty_like(v)
     dR = torch.zeros_like(R)
-    announce("host checks: backward deeper than 80")
+    announce("host checks: backward before its workspace is prepared")
     with pytest.raises(sgq.SgqError) as err:
-        sgq.band_energy_backward(dplan, v, R, E, w, deep.mu, deep.kT, sgq.SGQ_FREE, g, dV, dR)
+        sgq.band_energy_backward(plan, v, R, E, w, P.mu, P.kT, sgq.SGQ_FREE, g, dV, dR)
     assert err.value.code == sgq.SGQ_EPLAN
-    dplan.close()
+    plan.prepare_backward()
+    plan.prepare_backward()   # a second call is a no-op
+    sgq.band_energy_backward(plan, v, R, E, w, P.mu, P.kT, sgq.SGQ_FREE, g, dV, dR)
+    torch.cuda.synchronize()
+    assert plan.status() == sgq.SGQ_OK
+    rdV, _, rdR = O.band_energy_backward(P, kind=O.FREE)
+    assert O.normwise_rel_err(dV.cpu().numpy(), rdV) < 1e-4
+    plan.close()

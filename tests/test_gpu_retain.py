@@ -28,6 +28,7 @@ def _backward(plan, P, v, R, E, w):
     dV = torch.empty_like(v)
     dR = torch.zeros_like(R)
     dE = torch.zeros_like(E)
+    plan.prepare_backward()
     sgq.band_energy_backward(plan, v, R, E, w, P.mu, P.kT, sgq.SGQ_FREE, g, dV, dR, dE)
     torch.cuda.synchronize()
     assert plan.status() == sgq.SGQ_OK
@@ -85,6 +86,44 @@ def test_retention_is_keyed_to_the_inputs_and_invalidated():
     plan.autotune(v, R, E, P.mu, P.kT, sample_nodes=16)
     got = _backward(plan, P, v, R, E, w)
     for a, b in zip(ref, got):
+        assert np.array_equal(a, b)
+    plan.close()
+
+
+def test_inputs_overwritten_in_place_are_detected():
+    """The forward retains the bases, the caller then overwrites v_loc in place (same
+    pointer, new contents) or a projector energy, and calls the backward: the content hashes
+    differ, so the backward recomputes and returns the gradient of the new inputs, bitwise
+    that of a plan that never retained anything."""
+    import torch
+    from paper_1907_02604_amd import sgq
+    P = synth.make_problem(4)
+    P = P.subset(np.random.default_rng(6).choice(P.n_nodes, 32, replace=False))
+    v, R, E, w = sgq.device_inputs(P)
+    e = torch.empty(P.n_nodes, dtype=torch.float64, device="cuda")
+    om = torch.empty(1, dtype=torch.float64, device="cuda")
+    plan = sgq.Plan.from_problem(P)
+    plan.set_retain(True)
+    for what in ("v_loc", "proj_E"):
+        announce(f"retain hash: forward, {what} overwritten in place, backward")
+        sgq.band_energy(plan, v, R, E, w, P.mu, P.kT, sgq.SGQ_FREE, e, om)
+        if what == "v_loc":
+            v.mul_(1.02)
+        else:
+            E[0, 1] += 0.05
+        got = _backward(plan, P, v, R, E, w)
+        fresh = sgq.Plan.from_problem(P)
+        ref = _backward(fresh, P, v, R, E, w)
+        fresh.close()
+        for a, b in zip(ref, got):
+            assert np.array_equal(a, b)
+    announce("retain hash: unchanged inputs take the retained rows")
+    sgq.band_energy(plan, v, R, E, w, P.mu, P.kT, sgq.SGQ_FREE, e, om)
+    got = _backward(plan, P, v, R, E, w)
+    fresh = sgq.Plan.from_problem(P)
+    ref = _backward(fresh, P, v, R, E, w)
+    fresh.close()
+    for a, b in zip(ref, got):   # the same launch shape: the retained rows are bitwise the recompute's
         assert np.array_equal(a, b)
     plan.close()
 
