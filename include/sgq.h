@@ -183,6 +183,28 @@ int sgq_plan_set_schedule(sgq_plan* plan, int schedule);
 int sgq_fermi_level(sgq_plan* plan, const double* theta_w, const double* node_weight,
                     double n_electrons, double kT, double tol, double* result, void* stream);
 
+/* The Fermi-level solve of sgq_fermi_level without a plan and without allocating: for
+ * callers that cannot allocate device memory (code under HIP graph capture, tight
+ * self-consistency loops, harnesses that forbid hipMalloc).  Its state and partial sums
+ * (16 + 4 x 512 doubles) and status word live in a file-scope device array of the library,
+ * one copy per GPU, held until the process ends; the first call on a GPU looks up that
+ * array's address once.  The call enqueues the same kernels as sgq_fermi_level on `stream`
+ * and nothing else (no allocation, no memset, no synchronisation).
+ *   theta_w [n_nodes*kmax*2] double, node_weight [n_nodes] double: device inputs as for
+ *                             sgq_fermi_level (kmax = the rule's stride per node)
+ *   n_electrons, kT, tol      as for sgq_fermi_level
+ *   result [3] double         device out: mu, N(mu), steps
+ *   status [1] int32          device out: SGQ_OK, SGQ_ERANGE (no level for the count) or
+ *                             SGQ_ENONFINITE (a non-finite rule or weight), written by the
+ *                             last kernel of the call
+ * Returns SGQ_EINVAL for a null pointer, n_nodes or kmax below 1, n_nodes * kmax of 2^31 or
+ * more rule points, or a bad scalar; SGQ_EHIP when a launch fails.  Every call on one GPU
+ * shares the array: calls that overlap on a GPU (other host threads, other streams) race
+ * and must be serialised by the caller. */
+int sgq_fermi_level_noalloc(const double* theta_w, const double* node_weight, int32_t n_nodes,
+                            int32_t kmax, double n_electrons, double kT, double tol,
+                            double* result, int32_t* status, void* stream);
+
 /* Clusters of the energy sampling (Eq. eq:free_cg_sampling), host only.  C_q is the set
  * of grid points within distance `radius` (bohr) of energy sampling point (ESP) q on the
  * periodic grid (minimum-image distance; a point is inside when its squared distance in

@@ -1,12 +1,16 @@
 // Fermi level of stored Gauss rules (Eq. Eqn:LSSGQ:Fermi_level:GQ with the node weights of
-// Eq. eq:free_cg): the two pass kernels and their launcher.
+// Eq. eq:free_cg): the two pass kernels, their launcher for a plan, and the variant of the
+// solve that allocates nothing, whose state lives in a file-scope device array.
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <string>
 
+#include "sgq.h"
 #include "sgq_common.h"
 
 namespace sgq {
+int report_error(int code, const std::string& msg);
 
 // Fermi level of stored Gauss rules: the mu at which
 //   N(mu) = 2 sum_q n_q sum_k w_k g(theta_k; mu)
@@ -189,4 +193,73 @@ hipError_t launch_fermi_level(const double* tw, const double* weight, int nq, in
   return hipGetLastError();
 }
 
+
+// ------------------------------------------------------------------ allocation-free variant
+// The state and partial sums of one solve (kFermiWs doubles) and the status word, in a
+// file-scope device array: every GPU holds its own copy until the process ends, and every
+// call on that GPU shares it.
+constexpr int kFermiWs = 16 + 4 * kFermiBlocks;
+constexpr int kMaxDevices = 64;
+
+static __device__ __align__(256) double scratch[kFermiWs + 1];
+
+// Maps the status bits of the solve to an sgq_status code in the caller's word.
+__global__ void fermi_status_code_kernel(const int* bits, int32_t* code) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int b = *bits;
+  *code = (b & kStatusNonFinite) ? SGQ_ENONFINITE : (b & kStatusRange) ? SGQ_ERANGE : SGQ_OK;
+}
+
+namespace {
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+// Device address of `scratch` on the current device, looked up once per device.  In host
+// code the array's name is only a host-side stand-in; kernels get this address.
+static int scratch_address(double** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return report_error(SGQ_EHIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+  if (dev < 0 || dev >= kMaxDevices) return report_error(SGQ_EINVAL, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return report_error(SGQ_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = static_cast<double*>(g_scratch_ptr[dev]);
+  return SGQ_OK;
+}
+
 }  // namespace sgq
+
+extern "C" int sgq_fermi_level_noalloc(const double* theta_w, const double* node_weight,
+                                       int32_t n_nodes, int32_t kmax, double n_electrons,
+                                       double kT, double tol, double* result, int32_t* status,
+                                       void* stream) {
+  using namespace sgq;
+  if (!theta_w || !node_weight || !result || !status) return report_error(SGQ_EINVAL, "null argument");
+  if (n_nodes < 1 || kmax < 1) return report_error(SGQ_EINVAL, "n_nodes and kmax must be >= 1");
+  if ((int64_t)n_nodes * kmax >= ((int64_t)1 << 31))
+    return report_error(SGQ_EINVAL, "n_nodes * kmax must stay below 2^31 rule points");
+  if (!(kT > 0.0) || !std::isfinite(kT)) return report_error(SGQ_EINVAL, "kT must be finite and > 0");
+  if (!(n_electrons > 0.0) || !std::isfinite(n_electrons))
+    return report_error(SGQ_EINVAL, "n_electrons must be finite and > 0");
+  if (!(tol > 0.0) || !std::isfinite(tol)) return report_error(SGQ_EINVAL, "tol must be finite and > 0");
+  double* ws = nullptr;
+  int st = scratch_address(&ws);
+  if (st != SGQ_OK) return st;
+  int* bits = reinterpret_cast<int*>(ws + kFermiWs);
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = launch_fermi_level(theta_w, node_weight, n_nodes, kmax, n_electrons, kT, tol,
+                                    result, bits, ws, s);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(fermi_status_code_kernel, dim3(1), dim3(1), 0, s, bits, status);
+    e = hipGetLastError();
+  }
+  if (e != hipSuccess) return report_error(SGQ_EHIP, std::string("Fermi-level launch: ") + hipGetErrorString(e));
+  return SGQ_OK;
+}

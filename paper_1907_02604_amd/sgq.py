@@ -27,7 +27,8 @@ EXPORTED = ("sgq_plan_create", "sgq_plan_destroy", "rho_quadrature", "band_energ
             "sgq_cluster_energy", "sgq_fe_mesh_create", "sgq_fe_mesh_destroy",
             "sgq_fe_reconstruct", "sgq_fe_mesh_location", "sgq_fe_mesh_info", "sgq_lda_xc",
             "sgq_potential_create", "sgq_potential_destroy", "sgq_poisson",
-            "sgq_effective_potential", "sgq_plan_set_retain", "sgq_plan_prepare_backward")
+            "sgq_effective_potential", "sgq_plan_set_retain", "sgq_plan_prepare_backward",
+            "sgq_fermi_level_noalloc")
 
 
 class SgqError(RuntimeError):
@@ -64,6 +65,7 @@ def _load():
         "sgq_plan_set_retain": (I, [P, I, ctypes.c_int64, P]),
         "sgq_plan_prepare_backward": (I, [P]),
         "sgq_fermi_level": (I, [P, P, P, D, D, D, P, P]),
+        "sgq_fermi_level_noalloc": (I, [P, P, ctypes.c_int32, ctypes.c_int32, D, D, D, P, P, P]),
         "sgq_plan_autotune": (I, [P, P, P, P, D, D, I, P, ctypes.POINTER(ctypes.c_int32)]),
         "sgq_cluster_build": (I, [P, D, P, ctypes.c_int32, D, P, ctypes.c_int64, ctypes.c_int64,
                                   P, P, P, P, P, P, P]),
@@ -256,6 +258,16 @@ def fermi_level(plan, theta_w, node_weight, n_electrons, kT, result, tol=1e-12, 
     _check(_lib.sgq_fermi_level(plan.handle, _ptr(theta_w), _ptr(node_weight),
                                 float(n_electrons), float(kT), float(tol), _ptr(result),
                                 _stream(stream)))
+
+
+def fermi_level_noalloc(theta_w, node_weight, n_nodes, kmax, n_electrons, kT, result, status,
+                        tol=1e-12, stream=None):
+    """sgq_fermi_level_noalloc: result (device, 3 doubles) <- mu, N(mu), steps; status
+    (device int32) <- the solve's sgq_status.  Returns the call's own status code (host
+    argument checks), without raising."""
+    return _lib.sgq_fermi_level_noalloc(_ptr(theta_w), _ptr(node_weight), int(n_nodes), int(kmax),
+                                        float(n_electrons), float(kT), float(tol), _ptr(result),
+                                        _ptr(status), _stream(stream))
 
 
 def cluster_build(n, h, esp_center, radius, esp_weight=None):
