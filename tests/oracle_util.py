@@ -37,3 +37,37 @@ def smooth_random_potential(N, seed, amp=1.0):
 
 def lin(ix, iy, iz, N):
     return ix + N * (iy + N * iz)
+
+
+_POOL_PROBLEM = None
+
+
+def _pool_init(prob):
+    global _POOL_PROBLEM
+    from threadpoolctl import threadpool_limits
+    threadpool_limits(1)              # one BLAS thread per worker process
+    _POOL_PROBLEM = prob
+
+
+def _pool_node(q):
+    import oracle as O
+    return float(O.rho_quadrature(_POOL_PROBLEM, nodes=[int(q)])[0][0])
+
+
+def oracle_rho_pool(prob, nodes, workers=16):
+    """Oracle densities of the listed nodes on a pool of spawned worker processes (they
+    import only the oracle and the input generator, never the GPU runtime), at most
+    `workers` of them and no more than the host's cores."""
+    import multiprocessing as mp
+    import os
+    n = max(1, min(workers, len(os.sched_getaffinity(0)), len(nodes)))
+    with mp.get_context("spawn").Pool(n, initializer=_pool_init, initargs=(prob,)) as pool:
+        return np.array(pool.map(_pool_node, [int(q) for q in nodes], chunksize=1))
+
+
+def per_node_rel_err(got, ref, floor=1e-3):
+    """Largest per-node relative error over the nodes whose reference exceeds floor times
+    the largest |reference| (the per-node companion of the normwise metric)."""
+    got, ref = np.asarray(got, np.float64), np.asarray(ref, np.float64)
+    sig = np.abs(ref) > floor * np.max(np.abs(ref))
+    return float(np.max(np.abs(got[sig] - ref[sig]) / np.abs(ref[sig])))
