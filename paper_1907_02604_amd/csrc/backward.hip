@@ -155,6 +155,340 @@ __device__ __noinline__ void projector_gradients(const SGQ_G double* proj_E,
   }
 }
 
+// Projector weights of ubar_j = ib qbar_{j+1} + bb q_{j+1} + ahat q_j for the scatter:
+// acoef[a][l] = E_l h^3 chi_l . ubar_j, taken from the linear combination of
+// chi . qbar_{j+1} and chi . q_j (dotted here over each atom's box, accumulated in the
+// storage precision as the forward's overlaps are) and chi . q_{j+1}, which cq holds from
+// the step before; cq then takes chi . q_j.  On the last step (j = K_eff - 1) only the
+// q_j term is present.  One wave per NA atoms, as in the forward's overlaps.
+template <typename T, int BLOCK>
+__device__ __noinline__ void ubar_coefs(const SGQ_G double* proj_E, SGQ_L NodeState<T, BLOCK>& st,
+                                        ProjEval<T> pe, const SGQ_G T* Q0, const SGQ_G T* Wc,
+                                        int wbs, double sc, double ib, double bb, double ahat,
+                                        bool last, double h3, int B, int B3, SGQ_L T (*cq)[4]) {
+  constexpr int NW = BLOCK / kWave;
+  constexpr int UNR = 6;
+  constexpr int NA = 2;
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const int natoms = st.natoms;
+  for (int a0 = NA * wave; a0 < natoms; a0 += NA * NW) {
+    T aq[NA][4], aw[NA][4];
+#pragma unroll
+    for (int t = 0; t < NA; ++t)
+#pragma unroll
+      for (int l = 0; l < 4; ++l) aq[t][l] = aw[t][l] = (T)0;
+    for (int b0 = 0; b0 < B3; b0 += UNR * kWave) {
+      int bc[UNR][3];
+      T vq[NA][UNR], vw[NA][UNR];
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        const int b = b0 + u * kWave + lane;
+        bc[u][0] = b % B;
+        bc[u][1] = (b / B) % B;
+        bc[u][2] = b / (B * B);
+#pragma unroll
+        for (int t = 0; t < NA; ++t) {
+          const int a = a0 + t;
+          const bool live = (b < B3) && (a < natoms);
+          const int lp = live ? box_point(st, a, bc[u][0], bc[u][1], bc[u][2]) : -1;
+          const int lc = lp >= 0 ? lp : 0;
+          vw[t][u] = Wc[bidx(lc, wbs)] * (T)(lp >= 0);
+          vq[t][u] = last ? (T)0 : Q0[lc] * (T)(lp >= 0);
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < NA; ++t) {
+        const int a = a0 + t < natoms ? a0 + t : a0;
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+          T c[4];
+          chi_at(pe, st.afrac[a], bc[u][0], bc[u][1], bc[u][2], c);
+#pragma unroll
+          for (int l = 0; l < 4; ++l) {
+            aq[t][l] += c[l] * vq[t][u];
+            aw[t][l] += c[l] * vw[t][u];
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < NA; ++t) {
+      const int a = a0 + t;
+      if (a >= natoms) break;
+      const int J = st.atom[a];
+#pragma unroll
+      for (int l = 0; l < 4; ++l) {
+        const double cw = sc * (double)wave_sum(aw[t][l]);       // chi_l . q_j
+        const double cb = (double)wave_sum(aq[t][l]);            // chi_l . qbar_{j+1}
+        if (lane == 0) {
+          double cu = ahat * cw;
+          if (!last) cu += ib * cb + bb * (double)cq[a][l];
+          st.acoef[a][l] = (T)(proj_E[4 * J + l] * h3 * cu);
+          cq[a][l] = (T)cw;
+        }
+      }
+    }
+  }
+}
+
+// Rows and coefficients of one reversed step j for reverse_march.
+template <typename T>
+struct RevStep {
+  const SGQ_G T* Q0;    // qbar_{j+1} (plain vector)
+  const SGQ_G T* Wn;    // basis rows j+1, j, j-1, j-2 (block stride wbs)
+  const SGQ_G T* Wc;
+  const SGQ_G T* Wp;
+  const SGQ_G T* Wpp;
+  SGQ_G T* Uj;          // u_j, replaced by ubar_j
+  SGQ_G T* Q1;          // qbar_j so far, completed here
+  SGQ_G T* Q2;          // receives qbar_{j-1} = -beta_{j-1} rbar
+  SGQ_G T* Pq;          // the node dV cube
+  double ib, bb, ahat, al, bprev;
+  double sn, sc, sp, spp;   // scales of rows j+1, j, j-1, j-2 (zero where absent)
+  int wbs;
+  int last;             // j = K_eff - 1: no qbar_{j+1}, and P_q starts here
+  int prev;             // j > 0: qbar_{j-1} is written
+  int ldq1;             // Q1 holds a value to add to (else it starts from zero)
+};
+
+// Element i of a row addressed as a 32-bit byte offset from the row's base (indices of a
+// node's rows stay far below 2^30), which lets a wave-uniform base stay in scalar registers.
+template <typename T>
+__device__ __forceinline__ T ld_off(const SGQ_G T* base, int i) {
+  return *(const SGQ_G T*)((const SGQ_G char*)base + (unsigned)i * (unsigned)sizeof(T));
+}
+template <typename T>
+__device__ __forceinline__ void st_off(SGQ_G T* base, int i, T v) {
+  *(SGQ_G T*)((SGQ_G char*)base + (unsigned)i * (unsigned)sizeof(T)) = v;
+}
+
+// A wave-uniform value moved to scalar registers (arguments of a non-inlined call arrive
+// in vector registers, where the fields of RevStep would stay for the whole march).
+template <typename X>
+__device__ __forceinline__ X to_sgpr(X v) {
+  static_assert(sizeof(X) % 4 == 0, "whole dwords");
+  union {
+    X x;
+    int i[sizeof(X) / 4];
+  } u;
+  u.x = v;
+#pragma unroll
+  for (int k = 0; k < (int)(sizeof(X) / 4); ++k) u.i[k] = __builtin_amdgcn_readfirstlane(u.i[k]);
+  return u.x;
+}
+
+// One reversed step of the recurrence as a single march through the z planes of a
+// Dirichlet cube (FP32 nodes whose parallel projector group is added plane by plane; the
+// other atoms, if any, were scattered into Q1 before).  When plane z+5 enters the register
+// ring, each of its points gets
+//   rbar = ib qbar_{j+1} + bb q_{j+1},  ubar_j = rbar + ahat q_j   (FP64, stored rounded),
+// ubar_j replaces u_j, P_q += ubar_j q_j, qbar_{j-1} = -beta_{j-1} rbar is written, and
+// qbar_j - alpha_j rbar + ahat u_j waits in a second register ring; when plane z is
+// reached, H ubar_j (the stencil and potential on the ring of ubar_j, the group term from
+// the plane correction) is added to it and qbar_j is stored.  The same pass accumulates
+// the FP64 products that step j-1 starts from (qbar_j . q_j, qbar_j . q_{j-1},
+// qbar_j . q_{j-2}, q_j . q_{j-1}, q_j . q_{j-2}) into st.red.  Per step this reads six rows
+// and writes four, against ten reads and seven writes for separate dot, update and
+// operator passes.  Plane order, ring lengths and the LDS plane as in stencil_march.
+template <typename T, int BLOCK, int PPT>
+__device__ __noinline__ void reverse_march(int gnx, int gny, int gnz, SGQ_L NodeState<T, BLOCK>& st,
+                                           const SGQ_G T* __restrict__ V, T kin, ProjEval<T> pe,
+                                           int B, RevStep<T> Sv) {
+  RevStep<T> S;
+  S.Q0 = to_sgpr(Sv.Q0);
+  S.Wn = to_sgpr(Sv.Wn);
+  S.Wc = to_sgpr(Sv.Wc);
+  S.Wp = to_sgpr(Sv.Wp);
+  S.Wpp = to_sgpr(Sv.Wpp);
+  S.Uj = to_sgpr(Sv.Uj);
+  S.Q1 = to_sgpr(Sv.Q1);
+  S.Q2 = to_sgpr(Sv.Q2);
+  S.Pq = to_sgpr(Sv.Pq);
+  S.ib = to_sgpr(Sv.ib);
+  S.bb = to_sgpr(Sv.bb);
+  S.ahat = to_sgpr(Sv.ahat);
+  S.al = to_sgpr(Sv.al);
+  S.bprev = to_sgpr(Sv.bprev);
+  S.sn = to_sgpr(Sv.sn);
+  S.sc = to_sgpr(Sv.sc);
+  S.sp = to_sgpr(Sv.sp);
+  S.spp = to_sgpr(Sv.spp);
+  S.wbs = to_sgpr(Sv.wbs);
+  S.last = to_sgpr(Sv.last);
+  S.prev = to_sgpr(Sv.prev);
+  S.ldq1 = to_sgpr(Sv.ldq1);
+  constexpr int NQ = 8;    // ring of ubar planes z-3 .. z+4 (z+4 arrives after plane z)
+  constexpr int LEAD = 4;  // plane z+LEAD is loaded while plane z is computed
+  const int sx = st.sx, sy = st.sy, sz = st.sz, sxy = sx * sy;
+  const int rx = sx + 6;
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+  const int vplane = gnx * gny;
+  const T w1 = (T)kFd1, w2 = (T)kFd2, w3 = (T)kFd3;
+  const bool proj = st.natoms > 0;
+  for (int i = tid; i < 2 * kMarchPad; i += BLOCK) (&st.plane[0][0])[i] = (T)0;
+  if (proj)
+    for (int i = tid; i < 2 * NodeState<T, BLOCK>::kCorr; i += BLOCK) (&st.corr[0][0])[i] = (T)0;
+  __syncthreads();
+  if (proj) plane_group_term<T, BLOCK>(st, pe, 0, B, st.corr[0]);
+  T ring[PPT][NQ];    // ubar_j
+  T part[PPT][NQ];    // qbar_j - alpha_j rbar + ahat u_j
+  T vcur[PPT];        // V on plane z
+  int li[PPT], vrow[PPT];
+  bool own[PPT];
+  const int gz0 = st.oz < 0 ? st.oz + gnz : st.oz;
+  auto vz = [&](int z) {   // global z of local plane z (clamped into the cube)
+    int gz = gz0 + (z < sz ? z : sz - 1);
+    return gz >= gnz ? gz - gnz : gz;
+  };
+  // Raw values of plane zf of point column k.  fill_load issues the loads at the top of
+  // an iteration and fill_apply uses them after the plane's output, so they are in flight
+  // while the plane is computed.  fill_apply gives the ring values and, for a plane inside
+  // the cube, makes the point updates (planes outside are read clamped and only feed
+  // masked neighbours).
+  struct Raw {
+    T wc, q0, wn, uj, q1, pq;
+  };
+  auto point_of = [&](int k, int zf) {
+    const int zc = zf < 0 ? 0 : (zf < sz ? zf : sz - 1);
+    return (own[k] ? tid + k * BLOCK : 0) + zc * sxy;
+  };
+  auto fill_load = [&](int k, int zf, Raw& w) {
+    // every row is read (the absent ones point at rows that exist) and the values not
+    // wanted are replaced by zero, so the loads of an iteration form one branch-free run
+    const int p = point_of(k, zf);
+    const int pb = bidx(p, S.wbs);
+    w.wc = ld_off(S.Wc, pb);
+    w.uj = ld_off(S.Uj, p);
+    const T q0 = ld_off(S.Q0, p), wn = ld_off(S.Wn, pb), pq = ld_off(S.Pq, p);
+    const T q1 = ld_off(S.Q1, p);
+    w.q0 = S.last ? (T)0 : q0;
+    w.wn = S.last ? (T)0 : wn;
+    w.pq = S.last ? (T)0 : pq;
+    w.q1 = S.ldq1 ? q1 : (T)0;
+  };
+  auto fill_apply = [&](int k, int zf, const Raw& w, T& u, T& pt) {
+    const double qc = S.sc * (double)w.wc;
+    // ib = bb = 0 on the last step, where the raw q0 and wn are zero
+    const double rb = (double)w.q0 * S.ib + S.bb * S.sn * (double)w.wn;
+    const double ub = rb + S.ahat * qc;
+    u = (T)ub;
+    pt = (T)((double)w.q1 - S.al * rb + S.ahat * (double)w.uj);
+    if (own[k] && zf >= 0 && zf < sz) {
+      const int p = point_of(k, zf);
+      st_off(S.Uj, p, u);
+      st_off(S.Pq, p, (T)((double)w.pq + ub * qc));
+      if (S.prev) st_off(S.Q2, p, (T)(-S.bprev * rb));
+    }
+  };
+#pragma unroll
+  for (int k = 0; k < PPT; ++k) {
+    const int p2 = tid + k * BLOCK;
+    own[k] = p2 < sxy;
+    const int pc = own[k] ? p2 : 0;
+    const int y = pc / sx, x = pc - y * sx;
+    li[k] = (y + 3) * rx + (x + 3);
+    int gx = st.ox + x, gy = st.oy + y;
+    gx = gx < 0 ? gx + gnx : (gx >= gnx ? gx - gnx : gx);
+    gy = gy < 0 ? gy + gny : (gy >= gny ? gy - gny : gy);
+    vrow[k] = gx + gnx * gy;
+    // slot d holds plane d (d < LEAD) or plane d - NQ (below the cube); the planes below
+    // are filled after plane 0, whose u_j they would read already replaced, and feed only
+    // masked neighbours
+#pragma unroll
+    for (int d = 0; d < NQ; ++d) {
+      const int zf = d < LEAD ? d : d - NQ;
+      Raw w;
+      fill_load(k, zf, w);
+      fill_apply(k, zf, w, ring[k][d], part[k][d]);
+    }
+    vcur[k] = ld_off(V, vrow[k] + vplane * vz(0));
+  }
+  double d0 = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0, d4 = 0.0;
+  for (int z0 = 0; z0 < sz; z0 += NQ) {
+#pragma unroll
+    for (int r = 0; r < NQ; ++r) {
+      const int z = z0 + r;
+      if (z < sz) {
+        // loads first: plane z+LEAD for the ring, plane z of the basis rows for the
+        // products, the potential of plane z+1
+        const int zf = z + LEAD;
+        Raw raw[PPT];
+        T dwc[PPT], dwp[PPT], dwpp[PPT], vnext[PPT];
+        const int gzn = vz(z + 1);
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+          fill_load(k, zf, raw[k]);
+          vnext[k] = ld_off(V, vrow[k] + vplane * gzn);
+          // (on step 0 the products are formed and not used)
+          const int pb = bidx(point_of(k, z), S.wbs);
+          dwc[k] = ld_off(S.Wc, pb);
+          dwp[k] = ld_off(S.Wp, pb);
+          dwpp[k] = ld_off(S.Wpp, pb);
+        }
+        SGQ_L T* plane = st.plane[z & 1];
+#pragma unroll
+        for (int k = 0; k < PPT; ++k)
+          if (own[k]) plane[li[k]] = ring[k][r];
+        __syncthreads();
+        const T mz1 = (T)(z >= 1), pz1 = (T)(z + 1 < sz);
+        const T mz2 = (T)(z >= 2), pz2 = (T)(z + 2 < sz);
+        const T mz3 = (T)(z >= 3), pz3 = (T)(z + 3 < sz);
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+          const SGQ_L T* c0 = plane + li[k];
+          const T c = ring[k][r];
+          const T l1 = ((mz1 * ring[k][(r + NQ - 1) % NQ] - c) + (pz1 * ring[k][(r + 1) % NQ] - c)) +
+                       ((c0[-1] - c) + (c0[1] - c)) + ((c0[-rx] - c) + (c0[rx] - c));
+          const T l2 = ((mz2 * ring[k][(r + NQ - 2) % NQ] - c) + (pz2 * ring[k][(r + 2) % NQ] - c)) +
+                       ((c0[-2] - c) + (c0[2] - c)) + ((c0[-2 * rx] - c) + (c0[2 * rx] - c));
+          const T l3 = ((mz3 * ring[k][(r + NQ - 3) % NQ] - c) + (pz3 * ring[k][(r + 3) % NQ] - c)) +
+                       ((c0[-3] - c) + (c0[3] - c)) + ((c0[-3 * rx] - c) + (c0[3 * rx] - c));
+          const T lap = w1 * l1 + w2 * l2 + w3 * l3;
+          T add = kin * lap + vcur[k] * c;
+          if (own[k]) {
+            const int p2 = tid + k * BLOCK;
+            if (proj) {
+              SGQ_L T* cz = st.corr[z & 1];
+              add += cz[p2];
+              cz[p2] = (T)0;
+            }
+            const T out = part[k][r] + add;
+            st_off(S.Q1, p2 + z * sxy, out);
+            const double qn = S.sc * (double)dwc[k];
+            const double qc = S.sp * (double)dwp[k];
+            const double qp = S.spp * (double)dwpp[k];
+            const double qb = (double)out;
+            d0 += qb * qn;
+            d1 += qb * qc;
+            d2 += qb * qp;
+            d3 += qn * qc;
+            d4 += qn * qp;
+          }
+        }
+        if (proj && z + 1 < sz) plane_group_term<T, BLOCK>(st, pe, z + 1, B, st.corr[(z + 1) & 1]);
+        // plane z+LEAD takes the slot of plane z+LEAD-NQ, which no later plane reads
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+          fill_apply(k, zf, raw[k], ring[k][(r + LEAD) % NQ], part[k][(r + LEAD) % NQ]);
+          vcur[k] = vnext[k];
+        }
+      }
+    }
+  }
+  d0 = wave_sum(d0);
+  d1 = wave_sum(d1);
+  d2 = wave_sum(d2);
+  d3 = wave_sum(d3);
+  d4 = wave_sum(d4);
+  if (lane == 0) {
+    st.red[wave][0] = d0;
+    st.red[wave][1] = d1;
+    st.red[wave][2] = d2;
+    st.red[wave][3] = d3;
+    st.red[wave][4] = d4;
+  }
+}
+
 // Implicit-shift QR of the tridiagonal (a, b) accumulating all eigenvectors in Z.
 // Run by one whole wave: every lane computes the same rotations from the LDS copies of
 // a and b (lane 0 writes them back) and updates its rows of Z.
@@ -232,6 +566,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2, 2))) v
   constexpr int NW = BLOCK / kWave;
   __shared__ NodeState<T, BLOCK> st_shared;
   __shared__ BwdState bs_shared;
+  // chi . q_{j+1} of every node atom, carried between the fused reverse steps
+  __shared__ T cq_shared[NodeState<T, BLOCK>::kFuse ? kMaxNodeAtoms : 1][4];
+  SGQ_L T(*cq)[4] = (SGQ_L T(*)[4])(&cq_shared[0][0]);
   SGQ_L NodeState<T, BLOCK>& st = *(SGQ_L NodeState<T, BLOCK>*)(&st_shared);
   SGQ_L BwdState& bs = *(SGQ_L BwdState*)(&bs_shared);
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
@@ -346,9 +683,85 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2, 2))) v
       else bs.bbar[o - keff] = 2.0 * v;
     }
     __syncthreads();
-    // ---- reverse recurrence
+    // ---- reverse recurrence: one fused march per step where the node's stencil is the
+    // FP32 plane march and its projector group is added inside it; otherwise separate
+    // dot, update and operator passes
+    bool rev_fused = false;
+    if constexpr (NodeState<T, BLOCK>::kFuse)
+      rev_fused = !st.periodic && uses_march(st, BLOCK) && (natoms == 0 || st.fuse);
+    if constexpr (NodeState<T, BLOCK>::kFuse) {
+      if (rev_fused) {
+        int r0 = 0, r1 = 1, r2 = 2;
+        for (int j = keff - 1; j >= 0; --j) {
+          const bool last = (j == keff - 1);
+          if (tid == 0) {
+            if (!last) {
+              // the products step j+1's march left in st.red
+              double D[5] = {0, 0, 0, 0, 0};
+              for (int w = 0; w < NW; ++w)
+                for (int c = 0; c < 5; ++c) D[c] += st.red[w][c];
+              const double bj = st.beta[j];
+              const double bb = bs.bbar[j] - D[0] / bj;
+              const double rqc = D[1] / bj + bb * D[3];
+              const double rqp = D[2] / bj + bb * D[4];
+              bs.sc[0] = 1.0 / bj;
+              bs.sc[1] = bb;
+              bs.sc[2] = bs.abar[j] - rqc;
+              if (j > 0) bs.bbar[j - 1] -= rqp;
+            } else {
+              bs.sc[0] = 0.0;
+              bs.sc[1] = 0.0;
+              bs.sc[2] = bs.abar[j];
+            }
+          }
+          __syncthreads();
+          RevStep<T> S;
+          S.Q0 = R[r0];
+          S.Wn = Wq + 64 * (last ? j : j + 1);     // (row j+1 does not exist on the last step)
+          S.Wc = Wq + 64 * j;
+          S.Wp = Wq + 64 * (j >= 1 ? j - 1 : 0);
+          S.Wpp = Wq + 64 * (j >= 2 ? j - 2 : 0);
+          S.Uj = Uq + (size_t)j * npad;
+          S.Q1 = R[r1];
+          S.Q2 = R[r2];
+          S.Pq = Pq;
+          S.ib = bs.sc[0];
+          S.bb = bs.sc[1];
+          S.ahat = bs.sc[2];
+          S.al = st.alpha[j];
+          S.bprev = j > 0 ? st.beta[j - 1] : 0.0;
+          S.sn = (j + 1 < keff) ? st.scale[j + 1] : 0.0;
+          S.sc = st.scale[j];
+          S.sp = j >= 1 ? st.scale[j - 1] : 0.0;
+          S.spp = j >= 2 ? st.scale[j - 2] : 0.0;
+          S.wbs = wbs;
+          S.last = last;
+          S.prev = j > 0;
+          S.ldq1 = !last || natoms > st.ngrp;
+          if (natoms > 0) {
+            ubar_coefs<T, BLOCK>(proj_E, st, pe, S.Q0, S.Wc, wbs, S.sc, S.ib, S.bb, S.ahat, last,
+                                 h3, B, B3, cq);
+            __syncthreads();
+            if (natoms > st.ngrp) {
+              // the atoms outside the group are added to qbar_j before the march
+              if (last) {
+                for (int p = tid; p < n; p += BLOCK) S.Q1[p] = (T)0;
+                __syncthreads();
+              }
+              apply_scatter<T, BLOCK>(P, st, pe, S.Q1, B, B3, false);
+            }
+          }
+          reverse_march<T, BLOCK, 5>(P.nx, P.ny, P.nz, st, V, kin, pe, B, S);
+          __syncthreads();
+          const int t0 = r0;
+          r0 = r1;
+          r1 = r2;
+          r2 = t0;
+        }
+      }
+    }
     int r0 = 0, r1 = 1, r2 = 2;
-    for (int j = keff - 1; j >= 0; --j) {
+    for (int j = rev_fused ? -1 : keff - 1; j >= 0; --j) {
       // rows of the point-blocked basis (block stride wbs)
       const SGQ_G T* Wc = Wq + 64 * j;
       const SGQ_G T* Wn = Wq + 64 * (j + 1);
