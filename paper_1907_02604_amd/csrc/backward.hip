@@ -155,28 +155,35 @@ __device__ __noinline__ void projector_gradients(const SGQ_G double* proj_E,
   }
 }
 
-// Projector weights of ubar_j = ib qbar_{j+1} + bb q_{j+1} + ahat q_j for the scatter:
-// acoef[a][l] = E_l h^3 chi_l . ubar_j, taken from the linear combination of
-// chi . qbar_{j+1} and chi . q_j (dotted here over each atom's box, accumulated in the
-// storage precision as the forward's overlaps are) and chi . q_{j+1}, which cq holds from
-// the step before; cq then takes chi . q_j.  On the last step (j = K_eff - 1) only the
-// q_j term is present.  One wave per NA atoms, as in the forward's overlaps.
+// Projector terms of step j of the fused reverse recurrence, for
+// ubar_j = ib qbar_{j+1} + bb q_{j+1} + ahat q_j.  For every node atom the sixteen box sums
+// m_r(v) = phi_r . v, phi = [chi_0..3 ; d chi_l / d d_a] (the functions of the projector
+// adjoints), are formed for v = qbar_{j+1} and v = q_j (accumulated in the storage
+// precision); m_r(q_{j+1}) is carried in cq from the step before, and
+// m_r(ubar_j) = ib m_r(qbar_{j+1}) + bb m_r(q_{j+1}) + ahat m_r(q_j).  Then
+//   acoef[a][l] = E_l h^3 m_l(ubar_j)                      (weights of the scatter of H ubar_j)
+//   Ebar_l += h^3 m_l(ubar_j) m_l(q_j),
+//   Rbar_a -= h^3 sum_l E_l (m_{4+3l+a}(ubar_j) m_l(q_j) + m_l(ubar_j) m_{4+3l+a}(q_j)),
+// the per-step terms of the projector adjoints, added into the node's partials (dEp, dRp;
+// set on the last step j = K_eff - 1, which comes first), and cq takes m_r(q_j).  On the
+// last step only the q_j term of ubar_j is present.  One wave per NA atoms.
 template <typename T, int BLOCK>
 __device__ __noinline__ void ubar_coefs(const SGQ_G double* proj_E, SGQ_L NodeState<T, BLOCK>& st,
                                         ProjEval<T> pe, const SGQ_G T* Q0, const SGQ_G T* Wc,
                                         int wbs, double sc, double ib, double bb, double ahat,
-                                        bool last, double h3, int B, int B3, SGQ_L T (*cq)[4]) {
+                                        bool last, double h3, int B, int B3, SGQ_L T (*cq)[16],
+                                        double* dEp, double* dRp) {
   constexpr int NW = BLOCK / kWave;
-  constexpr int UNR = 6;
-  constexpr int NA = 2;
+  constexpr int UNR = 4;
+  constexpr int NA = 1;
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   const int natoms = st.natoms;
   for (int a0 = NA * wave; a0 < natoms; a0 += NA * NW) {
-    T aq[NA][4], aw[NA][4];
+    T aq[NA][16], aw[NA][16];
 #pragma unroll
     for (int t = 0; t < NA; ++t)
 #pragma unroll
-      for (int l = 0; l < 4; ++l) aq[t][l] = aw[t][l] = (T)0;
+      for (int r = 0; r < 16; ++r) aq[t][r] = aw[t][r] = (T)0;
     for (int b0 = 0; b0 < B3; b0 += UNR * kWave) {
       int bc[UNR][3];
       T vq[NA][UNR], vw[NA][UNR];
@@ -201,12 +208,13 @@ __device__ __noinline__ void ubar_coefs(const SGQ_G double* proj_E, SGQ_L NodeSt
         const int a = a0 + t < natoms ? a0 + t : a0;
 #pragma unroll
         for (int u = 0; u < UNR; ++u) {
-          T c[4];
-          chi_at(pe, st.afrac[a], bc[u][0], bc[u][1], bc[u][2], c);
+          T c[4], g[12];
+          chi_grad_at(pe, st.afrac[a], bc[u][0], bc[u][1], bc[u][2], c, g);
 #pragma unroll
-          for (int l = 0; l < 4; ++l) {
-            aq[t][l] += c[l] * vq[t][u];
-            aw[t][l] += c[l] * vw[t][u];
+          for (int r = 0; r < 16; ++r) {
+            const T f = r < 4 ? c[r] : g[r - 4];
+            aq[t][r] += f * vq[t][u];
+            aw[t][r] += f * vw[t][u];
           }
         }
       }
@@ -216,16 +224,31 @@ __device__ __noinline__ void ubar_coefs(const SGQ_G double* proj_E, SGQ_L NodeSt
       const int a = a0 + t;
       if (a >= natoms) break;
       const int J = st.atom[a];
+      double mq[16], mu[16];
 #pragma unroll
-      for (int l = 0; l < 4; ++l) {
-        const double cw = sc * (double)wave_sum(aw[t][l]);       // chi_l . q_j
-        const double cb = (double)wave_sum(aq[t][l]);            // chi_l . qbar_{j+1}
-        if (lane == 0) {
-          double cu = ahat * cw;
-          if (!last) cu += ib * cb + bb * (double)cq[a][l];
-          st.acoef[a][l] = (T)(proj_E[4 * J + l] * h3 * cu);
-          cq[a][l] = (T)cw;
+      for (int r = 0; r < 16; ++r) {
+        mq[r] = sc * (double)wave_sum(aw[t][r]);                 // m_r(q_j)
+        const double mb = (double)wave_sum(aq[t][r]);            // m_r(qbar_{j+1})
+        mu[r] = ahat * mq[r];
+        if (!last) mu[r] += ib * mb + bb * (double)cq[a][r];
+      }
+      if (lane == 0) {
+        double eb[4], rb[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int l = 0; l < 4; ++l) {
+          const double El = proj_E[4 * J + l];
+          st.acoef[a][l] = (T)(El * h3 * mu[l]);
+          eb[l] = h3 * mu[l] * mq[l];
+#pragma unroll
+          for (int ax = 0; ax < 3; ++ax)
+            rb[ax] -= h3 * El * (mu[4 + 3 * l + ax] * mq[l] + mu[l] * mq[4 + 3 * l + ax]);
         }
+#pragma unroll
+        for (int l = 0; l < 4; ++l) dEp[4 * a + l] = (last ? 0.0 : dEp[4 * a + l]) + eb[l];
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) dRp[3 * a + ax] = (last ? 0.0 : dRp[3 * a + ax]) + rb[ax];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) cq[a][r] = (T)mq[r];
       }
     }
   }
@@ -566,9 +589,10 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2, 2))) v
   constexpr int NW = BLOCK / kWave;
   __shared__ NodeState<T, BLOCK> st_shared;
   __shared__ BwdState bs_shared;
-  // chi . q_{j+1} of every node atom, carried between the fused reverse steps
-  __shared__ T cq_shared[NodeState<T, BLOCK>::kFuse ? kMaxNodeAtoms : 1][4];
-  SGQ_L T(*cq)[4] = (SGQ_L T(*)[4])(&cq_shared[0][0]);
+  // the projector box sums of q_{j+1} of every node atom, carried between the fused
+  // reverse steps
+  __shared__ T cq_shared[NodeState<T, BLOCK>::kFuse ? kMaxNodeAtoms : 1][16];
+  SGQ_L T(*cq)[16] = (SGQ_L T(*)[16])(&cq_shared[0][0]);
   SGQ_L NodeState<T, BLOCK>& st = *(SGQ_L NodeState<T, BLOCK>*)(&st_shared);
   SGQ_L BwdState& bs = *(SGQ_L BwdState*)(&bs_shared);
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
@@ -683,6 +707,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2, 2))) v
       else bs.bbar[o - keff] = 2.0 * v;
     }
     __syncthreads();
+    double* dEp = P.dE_part + (size_t)q * kMaxNodeAtoms * 4;
+    double* dRp = P.dR_part + (size_t)q * kMaxNodeAtoms * 3;
     // ---- reverse recurrence: one fused march per step where the node's stencil is the
     // FP32 plane march and its projector group is added inside it; otherwise separate
     // dot, update and operator passes
@@ -740,7 +766,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2, 2))) v
           S.ldq1 = !last || natoms > st.ngrp;
           if (natoms > 0) {
             ubar_coefs<T, BLOCK>(proj_E, st, pe, S.Q0, S.Wc, wbs, S.sc, S.ib, S.bb, S.ahat, last,
-                                 h3, B, B3, cq);
+                                 h3, B, B3, cq, dEp, dRp);
             __syncthreads();
             if (natoms > st.ngrp) {
               // the atoms outside the group are added to qbar_j before the march
@@ -874,10 +900,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2, 2))) v
       r2 = t0;
     }
     // ---- per-node projector adjoints (matrix cores), staged through the march's plane
-    // buffers, which are idle after the reverse recurrence
-    double* dEp = P.dE_part + (size_t)q * kMaxNodeAtoms * 4;
-    double* dRp = P.dR_part + (size_t)q * kMaxNodeAtoms * 3;
-    if (natoms > 0) {
+    // buffers, which are idle after the reverse recurrence (the fused steps added them
+    // step by step)
+    if (natoms > 0 && !rev_fused) {
       static_assert(sizeof(st.plane) >= NW * 256 * sizeof(T),
                     "the plane buffers must hold a 16 x 16 tile per wave");
       __syncthreads();
