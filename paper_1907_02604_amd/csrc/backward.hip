@@ -17,10 +17,13 @@
 //        qbar_j += -alpha_j rbar + ahat u_j + H ubar_j
 //        qbar_{j-1} = -beta_{j-1} rbar,  betabar_{j-1} -= rbar.q_{j-1}
 //      accumulating the node's dV cube P_q = sum_j ubar_j o q_j; ubar_j replaces u_j in
-//      the workspace once step j is done;
+//      the workspace once step j is done.  FP32 nodes on the plane march run each step as
+//      one fused march (reverse_march); the others as separate dot, update and operator
+//      passes;
 //   4. the projector adjoints Ebar_Jl = h^3 sum_j (chi.ubar_j)(chi.q_j) and
 //      Rbar_J = h^3 E sum_j [(ubar_j.dchi)(chi.q_j) + (ubar_j.chi)(dchi.q_j)]
-//      (dchi = d chi / d R) come from one dense product per atom,
+//      (dchi = d chi / d R): in the fused steps from the box sums each step forms anyway
+//      (ubar_coefs); otherwise from one dense product per atom,
 //      M = [chi; d chi] (16 x box points) . [ubar_j | q_j], on the matrix cores (16x16x4
 //      MFMA, accumulation in the storage precision), one wave per atom;
 //   5. a gather kernel sums the node cubes into dV in a fixed order (deterministic,
