@@ -33,6 +33,8 @@
 namespace sgq {
 
 constexpr int kBwdMaxDepth = kMaxDepth;   // largest depth of the adjoint (eigenvector matrix K x K)
+// per backward slot: the K x K eigenvector matrix, then the weighted divided differences
+constexpr size_t kBwdSlotDoubles = 2 * (size_t)kBwdMaxDepth * kBwdMaxDepth;
 constexpr int kGatherCell = 8;     // dV gather cell edge (points)
 
 struct BwdState {
@@ -169,91 +171,134 @@ __device__ __noinline__ void projector_gradients(const SGQ_G double* proj_E,
 //   Rbar_a -= h^3 sum_l E_l (m_{4+3l+a}(ubar_j) m_l(q_j) + m_l(ubar_j) m_{4+3l+a}(q_j)),
 // the per-step terms of the projector adjoints, added into the node's partials (dEp, dRp;
 // set on the last step j = K_eff - 1, which comes first), and cq takes m_r(q_j).  On the
-// last step only the q_j term of ubar_j is present.  One wave per NA atoms.
+// last step only the q_j term of ubar_j is present.
+// The atoms are dealt round-robin to the waves, NA at a time.  A wave requests the box
+// values of its NA atoms and their seven partials (one per lane) together, so the step
+// waits on memory once per NA atoms; the totals and the step's terms pass through the
+// wave's 64 doubles of wsb (LDS).
 template <typename T, int BLOCK>
 __device__ __noinline__ void ubar_coefs(const SGQ_G double* proj_E, SGQ_L NodeState<T, BLOCK>& st,
                                         ProjEval<T> pe, const SGQ_G T* Q0, const SGQ_G T* Wc,
                                         int wbs, double sc, double ib, double bb, double ahat,
                                         bool last, double h3, int B, int B3, SGQ_L T (*cq)[16],
-                                        double* dEp, double* dRp) {
+                                        double* dEp, double* dRp, SGQ_L double* wsb) {
   constexpr int NW = BLOCK / kWave;
-  constexpr int UNR = 4;
-  constexpr int NA = 1;
+  constexpr int UNR = 6;    // 6 x 64 box points cover the 7^3 box of h = rc/3
+  constexpr int NA = 3;     // atoms whose box values are requested together
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   const int natoms = st.natoms;
-  for (int a0 = NA * wave; a0 < natoms; a0 += NA * NW) {
-    T aq[NA][16], aw[NA][16];
+  SGQ_L double* ws = wsb + wave * 64;      // [0, 32): the totals; [32, 32 + 7 NA): terms
+  auto atom_of = [&](int t) { return wave + NW * t; };
+  // box value of atom a at box point b: (q_j, qbar_{j+1}), zero outside the cube
+  auto load = [&](int a, int b, T& vw, T& vq) {
+    const int lp = (b < B3 && a < natoms) ? box_point(st, a < natoms ? a : 0, b, B) : -1;
+    const int lc = lp >= 0 ? lp : 0;
+    vw = Wc[bidx(lc, wbs)] * (T)(lp >= 0);
+    vq = last ? (T)0 : Q0[lc] * (T)(lp >= 0);
+  };
+  auto accumulate = [&](int a, int b, T vw, T vq, T (&aw)[16], T (&aq)[16]) {
+    T c[4], g[12];
+    chi_grad_at(pe, st.afrac[a], b % B, (b / B) % B, b / (B * B), c, g);
 #pragma unroll
-    for (int t = 0; t < NA; ++t)
+    for (int r = 0; r < 16; ++r) {
+      const T f = r < 4 ? c[r] : g[r - 4];
+      aq[r] += f * vq;
+      aw[r] += f * vw;
+    }
+  };
+  // the sums of atom a (batch slot t) are complete: its weights, its step terms, the carry
+  auto finish = [&](int a, int t, const T (&aw)[16], const T (&aq)[16]) {
 #pragma unroll
-      for (int r = 0; r < 16; ++r) aq[t][r] = aw[t][r] = (T)0;
-    for (int b0 = 0; b0 < B3; b0 += UNR * kWave) {
-      int bc[UNR][3];
+    for (int r = 0; r < 16; ++r) {
+      const T sw = wave_sum(aw[r]), sq = wave_sum(aq[r]);
+      if (lane == 0) {
+        ws[r] = (double)sw;
+        ws[16 + r] = (double)sq;
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    if (lane == 0) {
+      const int J = st.atom[a];
+      auto mq = [&](int r) { return sc * ws[r]; };                              // m_r(q_j)
+      auto mu = [&](int r) {                                                    // m_r(ubar_j)
+        double v = ahat * mq(r);
+        if (!last) v += ib * ws[16 + r] + bb * (double)cq[a][r];
+        return v;
+      };
+      double rb[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+      for (int l = 0; l < 4; ++l) {
+        const double El = proj_E[4 * J + l];
+        const double mql = mq(l), mul = mu(l);
+        st.acoef[a][l] = (T)(El * h3 * mul);
+        ws[32 + 7 * t + l] = h3 * mul * mql;
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+          const int ra = 4 + 3 * l + ax;
+          rb[ax] -= h3 * El * (mu(ra) * mql + mul * mq(ra));
+        }
+      }
+#pragma unroll
+      for (int ax = 0; ax < 3; ++ax) ws[32 + 7 * t + 4 + ax] = rb[ax];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) cq[a][r] = (T)mq(r);
+    }
+    // ws[0, 32) is rewritten for the next atom only after lane 0 has read it
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+  };
+  const int tl = lane / 7, il = lane - 7 * tl;        // the partial this lane carries
+  for (int t0 = 0; atom_of(t0) < natoms; t0 += NA) {
+    // partial il of the batch's atom tl (Ebar_0..3, then Rbar_x,y,z)
+    const int al = atom_of(t0 + tl);
+    const bool carry = lane < 7 * NA && al < natoms;
+    double part = 0.0;
+    if (carry && !last) part = il < 4 ? dEp[4 * al + il] : dRp[3 * al + il - 4];
+    if (B3 <= UNR * kWave) {
+      // one round covers the box: every box value of the batch is requested at once
       T vq[NA][UNR], vw[NA][UNR];
 #pragma unroll
-      for (int u = 0; u < UNR; ++u) {
-        const int b = b0 + u * kWave + lane;
-        bc[u][0] = b % B;
-        bc[u][1] = (b / B) % B;
-        bc[u][2] = b / (B * B);
+      for (int t = 0; t < NA; ++t)
 #pragma unroll
-        for (int t = 0; t < NA; ++t) {
-          const int a = a0 + t;
-          const bool live = (b < B3) && (a < natoms);
-          const int lp = live ? box_point(st, a, bc[u][0], bc[u][1], bc[u][2]) : -1;
-          const int lc = lp >= 0 ? lp : 0;
-          vw[t][u] = Wc[bidx(lc, wbs)] * (T)(lp >= 0);
-          vq[t][u] = last ? (T)0 : Q0[lc] * (T)(lp >= 0);
-        }
-      }
+        for (int u = 0; u < UNR; ++u) load(atom_of(t0 + t), u * kWave + lane, vw[t][u], vq[t][u]);
 #pragma unroll
       for (int t = 0; t < NA; ++t) {
-        const int a = a0 + t < natoms ? a0 + t : a0;
+        const int a = atom_of(t0 + t);
+        if (a >= natoms) break;
+        T aq[16], aw[16];
 #pragma unroll
-        for (int u = 0; u < UNR; ++u) {
-          T c[4], g[12];
-          chi_grad_at(pe, st.afrac[a], bc[u][0], bc[u][1], bc[u][2], c, g);
+        for (int r = 0; r < 16; ++r) aq[r] = aw[r] = (T)0;
 #pragma unroll
-          for (int r = 0; r < 16; ++r) {
-            const T f = r < 4 ? c[r] : g[r - 4];
-            aq[t][r] += f * vq[t][u];
-            aw[t][r] += f * vw[t][u];
-          }
+        for (int u = 0; u < UNR; ++u) accumulate(a, u * kWave + lane, vw[t][u], vq[t][u], aw, aq);
+        finish(a, t, aw, aq);
+      }
+    } else {
+      // larger boxes: one atom at a time, UNR x 64 box points per round
+      for (int t = 0; t < NA; ++t) {
+        const int a = atom_of(t0 + t);
+        if (a >= natoms) break;
+        T aq[16], aw[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) aq[r] = aw[r] = (T)0;
+        for (int b0 = 0; b0 < B3; b0 += UNR * kWave) {
+          T vq[UNR], vw[UNR];
+#pragma unroll
+          for (int u = 0; u < UNR; ++u) load(a, b0 + u * kWave + lane, vw[u], vq[u]);
+#pragma unroll
+          for (int u = 0; u < UNR; ++u) accumulate(a, b0 + u * kWave + lane, vw[u], vq[u], aw, aq);
         }
+        finish(a, t, aw, aq);
       }
     }
-#pragma unroll
-    for (int t = 0; t < NA; ++t) {
-      const int a = a0 + t;
-      if (a >= natoms) break;
-      const int J = st.atom[a];
-      double mq[16], mu[16];
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        mq[r] = sc * (double)wave_sum(aw[t][r]);                 // m_r(q_j)
-        const double mb = (double)wave_sum(aq[t][r]);            // m_r(qbar_{j+1})
-        mu[r] = ahat * mq[r];
-        if (!last) mu[r] += ib * mb + bb * (double)cq[a][r];
-      }
-      if (lane == 0) {
-        double eb[4], rb[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-        for (int l = 0; l < 4; ++l) {
-          const double El = proj_E[4 * J + l];
-          st.acoef[a][l] = (T)(El * h3 * mu[l]);
-          eb[l] = h3 * mu[l] * mq[l];
-#pragma unroll
-          for (int ax = 0; ax < 3; ++ax)
-            rb[ax] -= h3 * El * (mu[4 + 3 * l + ax] * mq[l] + mu[l] * mq[4 + 3 * l + ax]);
-        }
-#pragma unroll
-        for (int l = 0; l < 4; ++l) dEp[4 * a + l] = (last ? 0.0 : dEp[4 * a + l]) + eb[l];
-#pragma unroll
-        for (int ax = 0; ax < 3; ++ax) dRp[3 * a + ax] = (last ? 0.0 : dRp[3 * a + ax]) + rb[ax];
-#pragma unroll
-        for (int r = 0; r < 16; ++r) cq[a][r] = (T)mq[r];
-      }
+    if (carry) {
+      const double v = part + ws[32 + 7 * tl + il];
+      if (il < 4) dEp[4 * al + il] = v;
+      else dRp[3 * al + il - 4] = v;
     }
+    // ws is rewritten by the next batch only after every lane has read its term
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
   }
 }
 
@@ -516,12 +561,17 @@ __device__ __noinline__ void reverse_march(int gnx, int gny, int gnz, SGQ_L Node
 }
 
 // Implicit-shift QR of the tridiagonal (a, b) accumulating all eigenvectors in Z.
-// Run by one whole wave: every lane computes the same rotations from the LDS copies of
-// a and b (lane 0 writes them back) and updates its rows of Z.
-// Z (global, per workgroup slot): Z[i*K + k] is component i of eigenvector k.  Each lane
-// owns rows i = lane (mod 64) of Z, so its updates need no synchronisation with the
-// other lanes.
-__device__ bool tridiag_eig_wave(SGQ_L double* a, SGQ_L double* b, SGQ_G double* Z, int K) {
+// Run by one whole wave.  Each sweep first forms its chain of Givens rotations: every lane
+// computes the same rotations from the LDS copies of a and b, carrying the entries the
+// previous rotation changed in registers (a rotation reads only entries no earlier one of
+// the sweep has written), lane 0 writes the results back and the (c, s) pairs to rot.
+// Then each lane applies the sweep's rotations to its rows of Z with the loads of eight
+// columns issued together, so the sweep waits on memory once per eight rotations rather
+// than once per rotation.
+// Z (global, per workgroup slot): Z[i*K + k] is component i of eigenvector k; each lane
+// owns rows i = lane (mod 64).  rot: 2 (K - 1) doubles of LDS.
+__device__ bool tridiag_eig_wave(SGQ_L double* a, SGQ_L double* b, SGQ_G double* Z, int K,
+                                 SGQ_L double* rot) {
   const int lane = threadIdx.x & (kWave - 1);
   for (int i = lane; i < K; i += kWave)
     for (int k = 0; k < K; ++k) Z[i * K + k] = (i == k) ? 1.0 : 0.0;
@@ -536,30 +586,40 @@ __device__ bool tridiag_eig_wave(SGQ_L double* a, SGQ_L double* b, SGQ_G double*
       --m;
       continue;
     }
-    int l = m - 1;
-    while (l > 0 && fabs(b[l - 1]) > eps * (fabs(a[l - 1]) + fabs(a[l]))) --l;
+    // l: the start of the unreduced block ending at m, one split test per lane (index
+    // i = w + 64 c tests b[i-1]); the largest split index below m wins
+    int l = 0;
+    for (int c0 = 0; c0 < m; c0 += kWave) {
+      const int i = c0 + lane;
+      const bool split = i >= 1 && i < m && fabs(b[i - 1]) <= eps * (fabs(a[i - 1]) + fabs(a[i]));
+      const unsigned long long mask = __ballot(split);
+      if (mask) l = c0 + 63 - __clzll(mask);
+    }
     if (l > 0 && lane == 0) b[l - 1] = 0.0;
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
     if (++sweeps > 40 * K) return false;
-    double d = 0.5 * (a[m - 1] - a[m]);
-    double bm = b[m - 1];
-    double den = d + copysign(hypot(d, bm), d == 0.0 ? 1.0 : d);
-    double shift = a[m] - bm * bm / den;
+    const double d = 0.5 * (a[m - 1] - a[m]);
+    const double bm = b[m - 1];
+    const double den = d + copysign(hypot(d, bm), d == 0.0 ? 1.0 : d);
+    const double shift = a[m] - bm * bm / den;
+    // the chain: (ak, bk) are a[k], b[k] as the previous rotation left them
     double x = a[l] - shift;
     double y = b[l];
+    double ak = a[l], bk = b[l];
+    // (a[k+1], b[k+1]) of the next rotation are read one rotation ahead; the entries of T
+    // stay far inside the double range, so r = sqrt(x^2 + y^2) needs no scaling
+    double ak1 = a[l + 1];
+    double bk1 = l + 1 < m ? b[l + 1] : 0.0;
     for (int k = l; k < m; ++k) {
-      double r = hypot(x, y);
+      const double ak1n = k + 2 <= m ? a[k + 2] : 0.0;
+      const double bk1n = k + 2 < m ? b[k + 2] : 0.0;
+      const double r = sqrt(x * x + y * y);
       double c = 1.0, s = 0.0;
       if (r != 0.0) {
-        c = x / r;
-        s = -y / r;
-      }
-      double ak = a[k], ak1 = a[k + 1], bk = b[k];
-      double bulge = 0.0, bk1 = 0.0;
-      if (k + 1 < m) {
-        bk1 = b[k + 1];
-        bulge = -s * bk1;
+        const double ir = 1.0 / r;
+        c = x * ir;
+        s = -y * ir;
       }
       const double nak = c * c * ak - 2.0 * c * s * bk + s * s * ak1;
       const double nak1 = s * s * ak + 2.0 * c * s * bk + c * c * ak1;
@@ -567,22 +627,43 @@ __device__ bool tridiag_eig_wave(SGQ_L double* a, SGQ_L double* b, SGQ_G double*
       if (lane == 0) {
         if (k > l) b[k - 1] = r;
         a[k] = nak;
-        a[k + 1] = nak1;
         b[k] = nbk;
-        if (k + 1 < m) b[k + 1] = c * bk1;
-      }
-      // lane 0's LDS writes must be ordered before the next rotation's reads by the
-      // other lanes: without the fence the compiler may hoist those reads
-      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      for (int i = lane; i < K; i += kWave) {
-        double u0 = Z[i * K + k], u1 = Z[i * K + k + 1];
-        Z[i * K + k] = c * u0 - s * u1;
-        Z[i * K + k + 1] = s * u0 + c * u1;
+        rot[2 * (k - l)] = c;
+        rot[2 * (k - l) + 1] = s;
       }
       x = nbk;
-      y = bulge;
+      y = -s * bk1;      // the bulge
+      ak = nak1;
+      bk = c * bk1;
+      ak1 = ak1n;
+      bk1 = bk1n;
     }
+    if (lane == 0) a[m] = ak;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    // the rotations on the rows of Z: column k+1's old value is loaded before rotation k
+    // writes column k, and its new value is carried to rotation k+1
+    for (int i = lane; i < K; i += kWave) {
+      SGQ_G double* zi = Z + (size_t)i * K;
+      double u0 = zi[l];
+      for (int k0 = l; k0 < m; k0 += 8) {
+        double u1[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) u1[t] = k0 + t < m ? zi[k0 + t + 1] : 0.0;
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+          if (k0 + t < m) {
+            const double c = rot[2 * (k0 + t - l)], s = rot[2 * (k0 + t - l) + 1];
+            zi[k0 + t] = c * u0 - s * u1[t];
+            u0 = s * u0 + c * u1[t];
+          }
+        }
+      }
+      zi[m] = u0;
+    }
+    // rot is rewritten by the next sweep only after every lane has read it
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
   }
   return true;
 }
@@ -604,7 +685,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2, 2))) v
   const int wbs = P.wbs;
   SGQ_G T* __restrict__ W = (SGQ_G T*)P.W + (size_t)blockIdx.x * P.slot_stride;
   SGQ_G T* __restrict__ Ubase = W + (size_t)kmax * npad;
-  SGQ_G double* __restrict__ Z = (SGQ_G double*)P.zbuf + (size_t)blockIdx.x * kBwdMaxDepth * kBwdMaxDepth;
+  SGQ_G double* __restrict__ Z =
+      (SGQ_G double*)P.zbuf + (size_t)blockIdx.x * kBwdSlotDoubles;
   SGQ_G T* __restrict__ R[3] = {Ubase + (size_t)kmax * npad, Ubase + (size_t)(kmax + 1) * npad,
                                 Ubase + (size_t)(kmax + 2) * npad};
   const SGQ_G T* __restrict__ V = (const SGQ_G T*)P.v;
@@ -666,7 +748,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2, 2))) v
     }
     __syncthreads();
     if (wave == 0) {
-      bool ok = tridiag_eig_wave(st.ta, st.tb, Z, keff);
+      bool ok = tridiag_eig_wave(st.ta, st.tb, Z, keff, bs.part);
       if (!ok && lane == 0) atomicOr(P.status, kStatusNonFinite);
     }
     __syncthreads();
@@ -676,38 +758,52 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2, 2))) v
       bs.Fd[k] = integrand_deriv(st.ta[k], P.mu, P.kT, P.integrand);
     }
     __syncthreads();
-    // output o < keff: alphabar_o; o >= keff: betabar_{o-keff}; two threads per output
-    for (int t = tid; t < 2 * (2 * keff - 1); t += BLOCK) {
-      const int o = t >> 1, half = t & 1;
-      const int j = o < keff ? o : o - keff;
-      const int m = o < keff ? o : o - keff + 1;
-      double acc = 0.0;
-      for (int k = half; k < keff; k += 2) {
-        const double tk = st.ta[k];
-        const double ak = Z[j * keff + k] * Z[k];
-        double inner = 0.0;
-        for (int l = 0; l < keff; ++l) {
-          const double tl = st.ta[l];
-          const double diff = tk - tl;
-          double D;
-          if (l == k) {
-            D = bs.Fd[k];
-          } else if (fabs(diff) <= 1e-6 * fmax(P.kT, fmax(fabs(tk), fabs(tl)))) {
-            D = integrand_deriv(0.5 * (tk + tl), P.mu, P.kT, P.integrand);
-          } else {
-            D = (bs.Fv[k] - bs.Fv[l]) / diff;
-          }
-          inner += D * Z[l] * Z[m * keff + l];
-        }
-        acc += ak * inner;
+    // G_kl = s1_k D_kl s1_l (s1 the first row of S, D the divided differences of F), in
+    // the second half of the slot; then alphabar_j = cscale sum_kl S_jk G_kl S_jl and
+    // betabar_j = 2 cscale sum_kl S_jk G_kl S_j+1,l.  Thread (j, c) forms
+    // y_jl = sum_k S_jk G_lk (G is symmetric) for the columns l = c (mod nch) and its two
+    // partial sums; the partials are added in a fixed order.
+    SGQ_G double* __restrict__ G = Z + (size_t)kBwdMaxDepth * kBwdMaxDepth;
+    for (int t = tid; t < keff * keff; t += BLOCK) {
+      const int k = t / keff, l = t - k * keff;
+      const double tk = st.ta[k], tl = st.ta[l];
+      const double diff = tk - tl;
+      double D;
+      if (l == k) {
+        D = bs.Fd[k];
+      } else if (fabs(diff) <= 1e-6 * fmax(P.kT, fmax(fabs(tk), fabs(tl)))) {
+        D = integrand_deriv(0.5 * (tk + tl), P.mu, P.kT, P.integrand);
+      } else {
+        D = (bs.Fv[k] - bs.Fv[l]) / diff;
       }
-      bs.part[t] = acc;
+      G[t] = Z[k] * D * Z[l];
     }
     __syncthreads();
-    for (int o = tid; o < 2 * keff - 1; o += BLOCK) {
-      const double v = cscale * (bs.part[2 * o] + bs.part[2 * o + 1]);
-      if (o < keff) bs.abar[o] = v;
-      else bs.bbar[o - keff] = 2.0 * v;
+    const int nch = keff * 8 <= 4 * kBwdMaxDepth / 2 ? 8 : (4 * kBwdMaxDepth / 2) / keff;
+    for (int t = tid; t < keff * nch; t += BLOCK) {
+      const int j = t / nch, c = t - j * nch;
+      const SGQ_G double* zj = Z + (size_t)j * keff;
+      const SGQ_G double* zj1 = Z + (size_t)(j + 1 < keff ? j + 1 : j) * keff;
+      double pa = 0.0, pb = 0.0;
+      for (int l = c; l < keff; l += nch) {
+        const SGQ_G double* gl = G + (size_t)l * keff;
+        double y = 0.0;
+        for (int k = 0; k < keff; ++k) y += zj[k] * gl[k];
+        pa += y * zj[l];
+        pb += y * zj1[l];
+      }
+      bs.part[2 * t] = pa;
+      bs.part[2 * t + 1] = pb;
+    }
+    __syncthreads();
+    for (int j = tid; j < keff; j += BLOCK) {
+      double sa = 0.0, sb = 0.0;
+      for (int c = 0; c < nch; ++c) {
+        sa += bs.part[2 * (j * nch + c)];
+        sb += bs.part[2 * (j * nch + c) + 1];
+      }
+      bs.abar[j] = cscale * sa;
+      if (j + 1 < keff) bs.bbar[j] = 2.0 * cscale * sb;
     }
     __syncthreads();
     double* dEp = P.dE_part + (size_t)q * kMaxNodeAtoms * 4;
@@ -769,7 +865,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2, 2))) v
           S.ldq1 = !last || natoms > st.ngrp;
           if (natoms > 0) {
             ubar_coefs<T, BLOCK>(proj_E, st, pe, S.Q0, S.Wc, wbs, S.sc, S.ib, S.bb, S.ahat, last,
-                                 h3, B, B3, cq, dEp, dRp);
+                                 h3, B, B3, cq, dEp, dRp, bs.part);
             __syncthreads();
             if (natoms > st.ngrp) {
               // the atoms outside the group are added to qbar_j before the march
@@ -1090,6 +1186,7 @@ hipError_t launch_zero(double* p, size_t n, hipStream_t s) {
 }
 
 int backward_max_depth() { return kBwdMaxDepth; }
+size_t backward_slot_doubles() { return kBwdSlotDoubles; }
 int gather_cell() { return kGatherCell; }
 
 }  // namespace sgq

@@ -39,6 +39,7 @@ hipError_t launch_plain(const LaunchParams& P, bool fp64, const int32_t* h_cente
                         const int32_t* h_hw, const int32_t* h_depth, void* scratch, hipStream_t s);
 size_t plain_scratch_bytes(size_t npad, int kmax, bool fp64);
 int backward_max_depth();
+size_t backward_slot_doubles();
 int gather_cell();
 hipError_t launch_vloc_backward(const double* dV, const double* R, int M, int nx, int ny, int nz,
                                 double h, double depth, double sigma, double cutoff, double* dR,
@@ -741,7 +742,7 @@ static int ensure_backward(sgq_plan* p) {
   p->bwd_slot_stride = (size_t)(2 * p->kmax + 3) * p->npad;
   hipError_t e = hipSuccess;
   e = e ? e : dalloc(p, &p->d_Wb, (size_t)p->grid_bwd * p->bwd_slot_stride * es);
-  e = e ? e : dalloc(p, &p->d_Zb, (size_t)p->grid_bwd * backward_max_depth() * backward_max_depth() * 8);
+  e = e ? e : dalloc(p, &p->d_Zb, (size_t)p->grid_bwd * backward_slot_doubles() * 8);
   e = e ? e : dalloc(p, &p->d_P, (size_t)std::max<int64_t>(1, off[nq]) * es);
   e = e ? e : dalloc(p, &p->d_cube_off, (size_t)(nq + 1) * 8);
   e = e ? e : dalloc(p, &p->d_dRp, (size_t)nq * kMaxNodeAtoms * 3 * 8);

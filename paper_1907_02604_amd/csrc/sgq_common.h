@@ -83,7 +83,8 @@ struct LaunchParams {
   double* dR_part;            // [Nq][kMaxNodeAtoms][3] node partials of dR (nonlocal)
   double* dE_part;            // [Nq][kMaxNodeAtoms][4] node partials of dE
   int32_t* node_atoms;        // [Nq][1 + kMaxNodeAtoms]: count, then the node's atom ids
-  double* zbuf;               // [slots][Kb*Kb] eigenvector matrix of T per backward slot
+  double* zbuf;               // [slots][2*Kb*Kb] eigenvectors of T, then the weighted
+                              // divided differences (per backward slot)
   void* Wr;                   // retained bases [R][npad/64][kmax][64] (NULL: slots only)
   void* Ur;                   // retained u_j = H q_j rows [R][kmax][npad]
   const int32_t* ret_slot;    // [Nq] each node's place among the R retained ones, or -1
