@@ -668,6 +668,128 @@ __device__ bool tridiag_eig_wave(SGQ_L double* a, SGQ_L double* b, SGQ_G double*
   return true;
 }
 
+// alphabar_j = Tbar_jj and betabar_j = 2 Tbar_j,j+1 of one node, Tbar = cscale S (D o s1 s1^T) S^T
+// (Daleckii-Krein), from the eigenvalues ta and eigenvectors S of T (Z[i*K + k]: component i
+// of eigenvector k).  G_kl = s1_k D_kl s1_l (s1 the first row of S, D the divided
+// differences of F, F' on the diagonal and for nearly equal eigenvalues) goes to the second
+// half of the slot; thread (j, c) then forms y_jl = sum_k S_jk G_lk (G is symmetric) for the
+// columns l = c (mod nch) and its parts of alphabar_j and betabar_j, which are added in a
+// fixed order.  Run by the NT threads of a workgroup; Fv, Fd: K values, part: 4 kBwdMaxDepth.
+template <int NT>
+__device__ void daleckii_krein(const LaunchParams& P, SGQ_L const double* ta, SGQ_L double* Fv,
+                               SGQ_L double* Fd, SGQ_L double* part, SGQ_G double* Z, int keff,
+                               double cscale, SGQ_L double* abar, SGQ_L double* bbar) {
+  const int tid = threadIdx.x;
+  for (int k = tid; k < keff; k += NT) {
+    Fv[k] = integrand_value(ta[k], P.mu, P.kT, P.integrand);
+    Fd[k] = integrand_deriv(ta[k], P.mu, P.kT, P.integrand);
+  }
+  __syncthreads();
+  SGQ_G double* __restrict__ G = Z + (size_t)keff * keff;
+  for (int t = tid; t < keff * keff; t += NT) {
+    const int k = t / keff, l = t - k * keff;
+    const double tk = ta[k], tl = ta[l];
+    const double diff = tk - tl;
+    double D;
+    if (l == k) {
+      D = Fd[k];
+    } else if (fabs(diff) <= 1e-6 * fmax(P.kT, fmax(fabs(tk), fabs(tl)))) {
+      D = integrand_deriv(0.5 * (tk + tl), P.mu, P.kT, P.integrand);
+    } else {
+      D = (Fv[k] - Fv[l]) / diff;
+    }
+    G[t] = Z[k] * D * Z[l];
+  }
+  __syncthreads();
+  const int nch = keff * 8 <= 2 * kBwdMaxDepth ? 8 : (2 * kBwdMaxDepth) / keff;
+  for (int t = tid; t < keff * nch; t += NT) {
+    const int j = t / nch, c = t - j * nch;
+    const SGQ_G double* zj = Z + (size_t)j * keff;
+    const SGQ_G double* zj1 = Z + (size_t)(j + 1 < keff ? j + 1 : j) * keff;
+    double pa = 0.0, pb = 0.0;
+    for (int l = c; l < keff; l += nch) {
+      const SGQ_G double* gl = G + (size_t)l * keff;
+      double y = 0.0;
+      for (int k = 0; k < keff; ++k) y += zj[k] * gl[k];
+      pa += y * zj[l];
+      pb += y * zj1[l];
+    }
+    part[2 * t] = pa;
+    part[2 * t + 1] = pb;
+  }
+  __syncthreads();
+  for (int j = tid; j < keff; j += NT) {
+    double sa = 0.0, sb = 0.0;
+    for (int c = 0; c < nch; ++c) {
+      sa += part[2 * (j * nch + c)];
+      sb += part[2 * (j * nch + c) + 1];
+    }
+    abar[j] = cscale * sa;
+    if (j + 1 < keff) bbar[j] = 2.0 * cscale * sb;
+  }
+  __syncthreads();
+}
+
+// The eigensolve and Daleckii-Krein step of every node as a pass of its own, before the
+// backward kernel: one wave per workgroup, many per CU, so the serial rotation chains of
+// the QR sweeps of different nodes overlap.  Each node's tridiagonal is the one the forward
+// call stored (alpha, beta, K_eff); it serves only when the forward saw these inputs
+// (hash[0] == hash[1]), and the backward kernel takes a node's result only when its own
+// K_eff agrees (tbar_k).  Z: 2 K_max^2 doubles per workgroup.
+__global__ __launch_bounds__(kWave) void tbar_kernel(LaunchParams P, double* zscratch,
+                                                      size_t zstride, double* tbar,
+                                                      int32_t* tbar_k) {
+  __shared__ double ta_s[kBwdMaxDepth], tb_s[kBwdMaxDepth], Fv_s[kBwdMaxDepth], Fd_s[kBwdMaxDepth];
+  __shared__ double part_s[4 * kBwdMaxDepth];
+  __shared__ double abar_s[kBwdMaxDepth], bbar_s[kBwdMaxDepth];
+  __shared__ int node;
+  SGQ_L double* ta = (SGQ_L double*)ta_s;
+  SGQ_L double* tb = (SGQ_L double*)tb_s;
+  SGQ_L double* Fv = (SGQ_L double*)Fv_s;
+  SGQ_L double* Fd = (SGQ_L double*)Fd_s;
+  SGQ_L double* part = (SGQ_L double*)part_s;
+  SGQ_L double* abar = (SGQ_L double*)abar_s;
+  SGQ_L double* bbar = (SGQ_L double*)bbar_s;
+  const int tid = threadIdx.x;
+  const int kmax = P.kmax_out;
+  SGQ_G double* Z = (SGQ_G double*)zscratch + (size_t)blockIdx.x * zstride;
+  const bool same = P.hash[0] == P.hash[1];
+  const double gomega = *P.grad_omega;
+  for (;;) {
+    if (tid == 0) node = atomicAdd(P.queue + 1, 1);
+    __syncthreads();
+    const int qi = node;
+    if (qi >= P.n_nodes) break;
+    const int q = P.order[qi];
+    const int keff = same ? P.tri_k[q] : -1;
+    if (keff < 1 || keff > kmax) {
+      if (tid == 0) tbar_k[q] = -1;
+      __syncthreads();
+      continue;
+    }
+    const double* tri = P.tri + (size_t)q * 2 * kmax;
+    for (int k = tid; k < keff; k += kWave) {
+      ta[k] = tri[k];
+      tb[k] = k + 1 < keff ? tri[kmax + k] : 0.0;
+    }
+    __syncthreads();
+    const bool ok = tridiag_eig_wave(ta, tb, Z, keff, part);
+    __syncthreads();
+    if (ok) {
+      daleckii_krein<kWave>(P, ta, Fv, Fd, part, Z, keff, 2.0 * P.node_weight[q] * gomega, abar,
+                            bbar);
+      double* out = tbar + (size_t)q * 2 * kmax;
+      for (int k = tid; k < keff; k += kWave) {
+        out[k] = abar[k];
+        if (k + 1 < keff) out[kmax + k] = bbar[k];
+      }
+    }
+    // (a node whose sweeps did not converge is left to the backward kernel, which reports it)
+    if (tid == 0) tbar_k[q] = ok ? keff : -1;
+    __syncthreads();
+  }
+}
+
 template <typename T, int BLOCK, int KG>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2, 2))) void lanczos_backward_kernel(LaunchParams P) {
   constexpr int NW = BLOCK / kWave;
@@ -741,71 +863,30 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2, 2))) v
     } else {
       keff = run_lanczos<T, BLOCK, KG>(P, st, W, Ubase, npad, P.depth[q]);
     }
-    // ---- eigenvectors of T and the Daleckii-Krein adjoint
-    for (int k = tid; k < keff; k += BLOCK) {
-      st.ta[k] = st.alpha[k];
-      st.tb[k] = k + 1 < keff ? st.beta[k] : 0.0;
-    }
-    __syncthreads();
-    if (wave == 0) {
-      bool ok = tridiag_eig_wave(st.ta, st.tb, Z, keff, bs.part);
-      if (!ok && lane == 0) atomicOr(P.status, kStatusNonFinite);
-    }
-    __syncthreads();
-    const double cscale = 2.0 * P.node_weight[q] * gomega;
-    for (int k = tid; k < keff; k += BLOCK) {
-      bs.Fv[k] = integrand_value(st.ta[k], P.mu, P.kT, P.integrand);
-      bs.Fd[k] = integrand_deriv(st.ta[k], P.mu, P.kT, P.integrand);
-    }
-    __syncthreads();
-    // G_kl = s1_k D_kl s1_l (s1 the first row of S, D the divided differences of F), in
-    // the second half of the slot; then alphabar_j = cscale sum_kl S_jk G_kl S_jl and
-    // betabar_j = 2 cscale sum_kl S_jk G_kl S_j+1,l.  Thread (j, c) forms
-    // y_jl = sum_k S_jk G_lk (G is symmetric) for the columns l = c (mod nch) and its two
-    // partial sums; the partials are added in a fixed order.
-    SGQ_G double* __restrict__ G = Z + (size_t)kBwdMaxDepth * kBwdMaxDepth;
-    for (int t = tid; t < keff * keff; t += BLOCK) {
-      const int k = t / keff, l = t - k * keff;
-      const double tk = st.ta[k], tl = st.ta[l];
-      const double diff = tk - tl;
-      double D;
-      if (l == k) {
-        D = bs.Fd[k];
-      } else if (fabs(diff) <= 1e-6 * fmax(P.kT, fmax(fabs(tk), fabs(tl)))) {
-        D = integrand_deriv(0.5 * (tk + tl), P.mu, P.kT, P.integrand);
-      } else {
-        D = (bs.Fv[k] - bs.Fv[l]) / diff;
+    // ---- eigenvectors of T and the Daleckii-Krein adjoint: from the pre-pass when it
+    // solved this node's tridiagonal (the forward's, for these inputs and this K_eff), else
+    // here
+    if (P.tbar_k && P.tbar_k[q] == keff) {
+      const double* tq = P.tbar + (size_t)q * 2 * kmax;
+      for (int k = tid; k < keff; k += BLOCK) {
+        bs.abar[k] = tq[k];
+        if (k + 1 < keff) bs.bbar[k] = tq[kmax + k];
       }
-      G[t] = Z[k] * D * Z[l];
-    }
-    __syncthreads();
-    const int nch = keff * 8 <= 4 * kBwdMaxDepth / 2 ? 8 : (4 * kBwdMaxDepth / 2) / keff;
-    for (int t = tid; t < keff * nch; t += BLOCK) {
-      const int j = t / nch, c = t - j * nch;
-      const SGQ_G double* zj = Z + (size_t)j * keff;
-      const SGQ_G double* zj1 = Z + (size_t)(j + 1 < keff ? j + 1 : j) * keff;
-      double pa = 0.0, pb = 0.0;
-      for (int l = c; l < keff; l += nch) {
-        const SGQ_G double* gl = G + (size_t)l * keff;
-        double y = 0.0;
-        for (int k = 0; k < keff; ++k) y += zj[k] * gl[k];
-        pa += y * zj[l];
-        pb += y * zj1[l];
+      __syncthreads();
+    } else {
+      for (int k = tid; k < keff; k += BLOCK) {
+        st.ta[k] = st.alpha[k];
+        st.tb[k] = k + 1 < keff ? st.beta[k] : 0.0;
       }
-      bs.part[2 * t] = pa;
-      bs.part[2 * t + 1] = pb;
-    }
-    __syncthreads();
-    for (int j = tid; j < keff; j += BLOCK) {
-      double sa = 0.0, sb = 0.0;
-      for (int c = 0; c < nch; ++c) {
-        sa += bs.part[2 * (j * nch + c)];
-        sb += bs.part[2 * (j * nch + c) + 1];
+      __syncthreads();
+      if (wave == 0) {
+        bool ok = tridiag_eig_wave(st.ta, st.tb, Z, keff, bs.part);
+        if (!ok && lane == 0) atomicOr(P.status, kStatusNonFinite);
       }
-      bs.abar[j] = cscale * sa;
-      if (j + 1 < keff) bs.bbar[j] = 2.0 * cscale * sb;
+      __syncthreads();
+      daleckii_krein<BLOCK>(P, st.ta, bs.Fv, bs.Fd, bs.part, Z, keff,
+                            2.0 * P.node_weight[q] * gomega, bs.abar, bs.bbar);
     }
-    __syncthreads();
     double* dEp = P.dE_part + (size_t)q * kMaxNodeAtoms * 4;
     double* dRp = P.dR_part + (size_t)q * kMaxNodeAtoms * 3;
     // ---- reverse recurrence: one fused march per step where the node's stencil is the
@@ -1147,6 +1228,12 @@ hipError_t launch_backward(const LaunchParams& P, bool fp64, int grid, int block
                            hipStream_t s) {
   (void)block;
   return fp64 ? launch_backward_t<double>(P, grid, kg, s) : launch_backward_t<float>(P, grid, kg, s);
+}
+
+hipError_t launch_tbar(const LaunchParams& P, int grid, double* zscratch, size_t zstride,
+                       double* tbar, int32_t* tbar_k, hipStream_t s) {
+  hipLaunchKernelGGL(tbar_kernel, dim3(grid), dim3(kWave), 0, s, P, zscratch, zstride, tbar, tbar_k);
+  return hipGetLastError();
 }
 
 hipError_t launch_backward_gather(const LaunchParams& P, bool fp64, const int32_t* cell_start,

@@ -139,7 +139,8 @@ __global__ void gauss_rule_kernel(LaunchParams P) {
 // ------------------------------------------------------------------ setup kernels
 __global__ void reset_kernel(int* queue, int* status, double* vmax, unsigned long long* hash) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
-    *queue = 0;
+    queue[0] = 0;     // the persistent kernels' node queue
+    queue[1] = 0;     // the backward's eigensolve pre-pass queue
     *status = 0;
     *vmax = 0.0;
     *hash = 0ull;

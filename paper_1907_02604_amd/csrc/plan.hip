@@ -31,6 +31,8 @@ hipError_t launch_fermi_level(const double* tw, const double* weight, int nq, in
                               double* ws, hipStream_t s);
 hipError_t launch_backward(const LaunchParams& P, bool fp64, int grid, int block, int kg,
                            hipStream_t s);
+hipError_t launch_tbar(const LaunchParams& P, int grid, double* zscratch, size_t zstride,
+                       double* tbar, int32_t* tbar_k, hipStream_t s);
 hipError_t launch_backward_gather(const LaunchParams& P, bool fp64, const int32_t* cell_start,
                                   const int32_t* cell_nodes, int ncells, double* dV, double* dR,
                                   double* dE, hipStream_t s);
@@ -87,6 +89,10 @@ struct sgq_plan {
   // input pointers, consumed by the next backward call
   bool retain = false, ret_valid = false;
   const void* ret_key[3] = {nullptr, nullptr, nullptr};
+  // the last forward launch covered every node with these inputs, so the tridiagonals it
+  // stored serve the backward's eigensolve pre-pass
+  bool tri_valid = false;
+  const void* tri_key[3] = {nullptr, nullptr, nullptr};
   void* d_Wr = nullptr;
   void* d_Ur = nullptr;
   int32_t* d_ret_slot = nullptr;   // [Nq] place of each node in the retained storage, or -1
@@ -97,6 +103,11 @@ struct sgq_plan {
   size_t bwd_slot_stride = 0;
   void* d_Wb = nullptr;
   double* d_Zb = nullptr;
+  double* d_tbar = nullptr;      // pre-pass alphabar / betabar per node
+  int32_t* d_tbar_k = nullptr;
+  double* d_zpre = nullptr;      // pre-pass eigenvector scratch per workgroup
+  size_t zpre_stride = 0;
+  int grid_pre = 0;
   void* d_P = nullptr;
   int64_t* d_cube_off = nullptr;
   double* d_dRp = nullptr;
@@ -344,11 +355,16 @@ static void mark_retained(sgq_plan* p, const double* v_loc, const LaunchParams& 
   p->ret_key[0] = v_loc;
   p->ret_key[1] = P.atom_R;
   p->ret_key[2] = P.proj_E;
+  p->tri_valid = true;
+  p->tri_key[0] = v_loc;
+  p->tri_key[1] = P.atom_R;
+  p->tri_key[2] = P.proj_E;
 }
 
 static int run_forward(sgq_plan* p, int kind, LaunchParams& P, const double* v_loc,
                        const double* node_weight, double* omega, hipStream_t s) {
   p->ret_valid = false;
+  p->tri_valid = false;
   HIP_OR_FAIL(hipSetDevice(p->device));
   p->last = s;
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
@@ -410,6 +426,7 @@ extern "C" int rho_quadrature(sgq_plan* plan, const double* v_loc, const double*
     P.slot_stride = (size_t)plan->kmax * plan->npad;
     HIP_OR_FAIL(launch_setup(P, plan->fp64, v_loc, plan->d_v, plan->d_chi, plan->d_g0, plan->d_vmax, s));
     plan->ret_valid = false;
+    plan->tri_valid = false;
     HIP_OR_FAIL(launch_plain(P, plan->fp64, plan->h_center.data(), plan->h_hw.data(),
                              plan->h_depth.data(), plan->d_plain, s));
     plan->last = s;
@@ -614,6 +631,7 @@ extern "C" int sgq_plan_autotune(sgq_plan* plan, const double* v_loc, const doub
   if (sample_nodes < 1) return fail(SGQ_EINVAL, "sample_nodes must be >= 1");
   HIP_OR_FAIL(hipSetDevice(plan->device));
   plan->ret_valid = false;   // the timing launches overwrite sampled nodes' retained bases
+  plan->tri_valid = false;   // and their stored tridiagonals
   hipStream_t s = (hipStream_t)stream;
   const int nq = plan->prob.n_nodes;
   std::vector<std::pair<int, int>> cand;
@@ -748,6 +766,13 @@ static int ensure_backward(sgq_plan* p) {
   e = e ? e : dalloc(p, &p->d_dRp, (size_t)nq * kMaxNodeAtoms * 3 * 8);
   e = e ? e : dalloc(p, &p->d_dEp, (size_t)nq * kMaxNodeAtoms * 4 * 8);
   e = e ? e : dalloc(p, &p->d_node_atoms, (size_t)nq * (kMaxNodeAtoms + 1) * 4);
+  // the eigensolve pre-pass: 16 one-wave workgroups per CU, each with the eigenvectors and
+  // weighted divided differences of one node (2 kmax^2 doubles), and the per-node results
+  p->grid_pre = std::max(1, std::min(nq, 16 * p->ncu));
+  p->zpre_stride = 2 * (size_t)p->kmax * p->kmax;
+  e = e ? e : dalloc(p, &p->d_zpre, (size_t)p->grid_pre * p->zpre_stride * 8);
+  e = e ? e : dalloc(p, &p->d_tbar, (size_t)nq * 2 * p->kmax * 8);
+  e = e ? e : dalloc(p, &p->d_tbar_k, (size_t)nq * 4);
   if (e != hipSuccess) {
     (void)hipGetLastError();
     return fail(SGQ_ENOMEM, std::string("backward workspace: ") + hipGetErrorString(e));
@@ -790,9 +815,19 @@ extern "C" int band_energy_backward(sgq_plan* plan, const double* v_loc, const d
   // the retained rows only when the forward call's hash agrees
   P.hash_slot = 1;
   plan->ret_valid = false;
+  // the eigensolves of the nodes' tridiagonals run as a pass of their own when the last
+  // forward launch stored them for these inputs (the pass checks the contents hash)
+  const bool pre = plan->tri_valid && plan->tri_key[0] == v_loc && plan->tri_key[1] == atom_R &&
+                   plan->tri_key[2] == proj_E;
+  P.tbar = pre ? plan->d_tbar : nullptr;
+  P.tbar_k = pre ? plan->d_tbar_k : nullptr;
   HIP_OR_FAIL(launch_setup(P, plan->fp64, v_loc, plan->d_v, plan->d_chi, plan->d_g0, plan->d_vmax, s));
-  if (plan->prob.n_nodes > 0)
+  if (plan->prob.n_nodes > 0) {
+    if (pre)
+      HIP_OR_FAIL(launch_tbar(P, plan->grid_pre, plan->d_zpre, plan->zpre_stride, plan->d_tbar,
+                              plan->d_tbar_k, s));
     HIP_OR_FAIL(launch_backward(P, plan->fp64, plan->grid_bwd, 256, plan->kg, s));
+  }
   const bool have_proj = plan->prob.n_proj > 0 && plan->prob.n_atoms > 0;
   if (!have_proj) {
     HIP_OR_FAIL(launch_zero(dR_nl, dR_nl ? (size_t)plan->prob.n_atoms * 3 : 0, s));

@@ -94,6 +94,10 @@ struct LaunchParams {
   // backward takes retained bases only when the two agree.
   unsigned long long* hash;
   int hash_slot;
+  // backward: alphabar / betabar of each node from the eigensolve pre-pass ([Nq][2*kmax_out])
+  // and the K_eff it solved for (-1: not solved there); tbar_k NULL: no pre-pass
+  double* tbar;
+  int32_t* tbar_k;
 };
 
 // splitmix64 finaliser: mixes the bits of one input value with its index for the input hash.
