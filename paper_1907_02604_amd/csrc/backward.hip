@@ -16,10 +16,10 @@
 //        ahat = alphabar_j - rbar.q_j,   ubar_j = rbar + ahat q_j
 //        qbar_j += -alpha_j rbar + ahat u_j + H ubar_j
 //        qbar_{j-1} = -beta_{j-1} rbar,  betabar_{j-1} -= rbar.q_{j-1}
-//      accumulating the node's dV cube P_q = sum_j ubar_j o q_j; ubar_j replaces u_j in
-//      the workspace once step j is done.  FP32 nodes on the plane march run each step as
-//      one fused march (reverse_march); the others as separate dot, update and operator
-//      passes;
+//      accumulating the node's dV cube P_q = sum_j ubar_j o q_j.  FP32 nodes on the
+//      plane march run each step as one fused march (reverse_march); the others as
+//      separate dot, update and operator passes, where ubar_j replaces u_j in the
+//      workspace once step j is done;
 //   4. the projector adjoints Ebar_Jl = h^3 sum_j (chi.ubar_j)(chi.q_j) and
 //      Rbar_J = h^3 E sum_j [(ubar_j.dchi)(chi.q_j) + (ubar_j.chi)(dchi.q_j)]
 //      (dchi = d chi / d R): in the fused steps from the box sums each step forms anyway
@@ -310,7 +310,7 @@ struct RevStep {
   const SGQ_G T* Wc;
   const SGQ_G T* Wp;
   const SGQ_G T* Wpp;
-  SGQ_G T* Uj;          // u_j, replaced by ubar_j
+  const SGQ_G T* Uj;    // u_j
   SGQ_G T* Q1;          // qbar_j so far, completed here
   SGQ_G T* Q2;          // receives qbar_{j-1} = -beta_{j-1} rbar
   SGQ_G T* Pq;          // the node dV cube
@@ -350,16 +350,17 @@ __device__ __forceinline__ X to_sgpr(X v) {
 
 // One reversed step of the recurrence as a single march through the z planes of a
 // Dirichlet cube (FP32 nodes whose parallel projector group is added plane by plane; the
-// other atoms, if any, were scattered into Q1 before).  When plane z+5 enters the register
+// other atoms, if any, were scattered into Q1 before).  When plane z+4 enters the register
 // ring, each of its points gets
 //   rbar = ib qbar_{j+1} + bb q_{j+1},  ubar_j = rbar + ahat q_j   (FP64, stored rounded),
-// ubar_j replaces u_j, P_q += ubar_j q_j, qbar_{j-1} = -beta_{j-1} rbar is written, and
+// P_q += ubar_j q_j and qbar_{j-1} = -beta_{j-1} rbar are written, and
 // qbar_j - alpha_j rbar + ahat u_j waits in a second register ring; when plane z is
 // reached, H ubar_j (the stencil and potential on the ring of ubar_j, the group term from
-// the plane correction) is added to it and qbar_j is stored.  The same pass accumulates
-// the FP64 products that step j-1 starts from (qbar_j . q_j, qbar_j . q_{j-1},
-// qbar_j . q_{j-2}, q_j . q_{j-1}, q_j . q_{j-2}) into st.red.  Per step this reads six rows
-// and writes four, against ten reads and seven writes for separate dot, update and
+// the plane correction) is added to it and qbar_j is stored.  ubar_j itself is not stored:
+// the step's projector sums already hold what the adjoints need of it.  The same pass
+// accumulates the FP64 products that step j-1 starts from (qbar_j . q_j, qbar_j . q_{j-1},
+// qbar_j . q_{j-2}, q_j . q_{j-1}, q_j . q_{j-2}) into st.red.  Per step this reads nine rows
+// and writes three, against ten reads and seven writes for separate dot, update and
 // operator passes.  Plane order, ring lengths and the LDS plane as in stencil_march.
 template <typename T, int BLOCK, int PPT>
 __device__ __noinline__ void reverse_march(int gnx, int gny, int gnz, SGQ_L NodeState<T, BLOCK>& st,
@@ -446,7 +447,6 @@ __device__ __noinline__ void reverse_march(int gnx, int gny, int gnz, SGQ_L Node
     pt = (T)((double)w.q1 - S.al * rb + S.ahat * (double)w.uj);
     if (own[k] && zf >= 0 && zf < sz) {
       const int p = point_of(k, zf);
-      st_off(S.Uj, p, u);
       st_off(S.Pq, p, (T)((double)w.pq + ub * qc));
       if (S.prev) st_off(S.Q2, p, (T)(-S.bprev * rb));
     }
