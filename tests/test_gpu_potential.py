@@ -32,10 +32,11 @@ def test_lda_xc_matches_oracle():
 
 
 @pytest.mark.parametrize("shape", [(12, 10, 8), (16, 16, 16), (9, 20, 30), (5, 6, 1), (1, 1, 1),
-                                   (25, 24, 27), (64, 64, 64), (128, 96, 80)])
+                                   (25, 24, 27), (64, 64, 64), (128, 96, 80), (8, 256, 256)])
 def test_poisson_matches_oracle(shape):
     """phi against the oracle's FFT solve (every radix 4, 2, 3, 5 and degenerate axes), the
-    reported mean, and the real-space stencil residual of the device result."""
+    reported mean, and the real-space stencil residual of the device result (the last shape:
+    256-point x and y lines, the longest tiles of the line passes)."""
     import torch
     from paper_1907_02604_amd import sgq
     nz, ny, nx = shape
