@@ -120,16 +120,20 @@ int band_energy(sgq_plan* plan, const double* v_loc, const double* atom_R,
 
 /* Backward workspace of a plan: the per-workgroup adjoint slots, the per-node dV cubes
  * (one cube of the node's points per node: 15.9 GB for 110592 nodes of 33^3 points in
- * FP32), the per-node atom partials and the lists that gather the cubes into dV.  Allocates
- * and uploads them (host geometry, hipMalloc, blocking copies), so it is synchronous; call it
- * once before the first band_energy_backward.  Returns SGQ_ENOMEM when the workspace does
- * not fit, SGQ_EPLAN when the plan's depth exceeds the adjoint's (80); calling it again is a
- * no-op. */
+ * FP32), the per-node atom partials, the lists that gather the cubes into dV, and the
+ * eigensolve pre-pass's buffers (per node 2 K_max doubles of alphabar / betabar; per
+ * pre-pass workgroup, 16 per CU, 2 K_max^2 doubles).  Allocates and uploads them (host
+ * geometry, hipMalloc, blocking copies), so it is synchronous; call it once before the
+ * first band_energy_backward.  Returns SGQ_ENOMEM when the workspace does not fit,
+ * SGQ_EPLAN when the plan's depth exceeds the adjoint's (128, every depth a plan
+ * accepts); calling it again is a no-op. */
 int sgq_plan_prepare_backward(sgq_plan* plan);
 
 /* Adjoint of Omega (reverse mode through the Lanczos recurrence; the Lanczos vectors
  * of each node are recomputed from the start vector, the only checkpoint kept, unless the
- * forward call retained them, see sgq_plan_set_retain).  Requires
+ * forward call retained them, see sgq_plan_set_retain).  When the plan's last forward call
+ * (rho_quadrature or band_energy over all nodes) saw the same inputs, the eigensolves of
+ * the nodes' tridiagonals run as a pre-pass over the tridiagonals it stored.  Requires
  * sgq_plan_prepare_backward (SGQ_EPLAN otherwise); the call itself allocates nothing and
  * does not synchronise: it only enqueues kernels on `stream`.
  *   grad_omega [1] double        upstream dL/dOmega
