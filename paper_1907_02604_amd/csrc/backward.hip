@@ -397,7 +397,7 @@ __device__ __noinline__ void reverse_march(int gnx, int gny, int gnz, SGQ_L Node
   const int vplane = gnx * gny;
   const T w1 = (T)kFd1, w2 = (T)kFd2, w3 = (T)kFd3;
   const bool proj = st.natoms > 0;
-  for (int i = tid; i < 2 * kMarchPad; i += BLOCK) (&st.plane[0][0])[i] = (T)0;
+  for (int i = tid; i < 2 * NodeState<T, BLOCK>::kMarchPad; i += BLOCK) (&st.plane[0][0])[i] = (T)0;
   if (proj)
     for (int i = tid; i < 2 * NodeState<T, BLOCK>::kCorr; i += BLOCK) (&st.corr[0][0])[i] = (T)0;
   __syncthreads();
@@ -1208,26 +1208,29 @@ __global__ __launch_bounds__(256) void vloc_backward_kernel(const double* __rest
 }
 
 // ------------------------------------------------------------------ host launchers
-template <typename T>
+template <typename T, int BLOCK>
 static hipError_t launch_backward_t(const LaunchParams& P, int grid, int kg, hipStream_t s) {
   switch (kg) {
     case 8:
-      hipLaunchKernelGGL((lanczos_backward_kernel<T, 256, 8>), dim3(grid), dim3(256), 0, s, P);
+      hipLaunchKernelGGL((lanczos_backward_kernel<T, BLOCK, 8>), dim3(grid), dim3(BLOCK), 0, s, P);
       break;
     case 16:
-      hipLaunchKernelGGL((lanczos_backward_kernel<T, 256, 16>), dim3(grid), dim3(256), 0, s, P);
+      hipLaunchKernelGGL((lanczos_backward_kernel<T, BLOCK, 16>), dim3(grid), dim3(BLOCK), 0, s, P);
       break;
     default:
-      hipLaunchKernelGGL((lanczos_backward_kernel<T, 256, 32>), dim3(grid), dim3(256), 0, s, P);
+      hipLaunchKernelGGL((lanczos_backward_kernel<T, BLOCK, 32>), dim3(grid), dim3(BLOCK), 0, s, P);
       break;
   }
   return hipGetLastError();
 }
 
+// 256 lanes per node (two workgroups per CU) or, in FP32, 512 (one per CU: the wide-plane
+// march of cubes up to 49 points across); FP64 nodes take 256.
 hipError_t launch_backward(const LaunchParams& P, bool fp64, int grid, int block, int kg,
                            hipStream_t s) {
-  (void)block;
-  return fp64 ? launch_backward_t<double>(P, grid, kg, s) : launch_backward_t<float>(P, grid, kg, s);
+  if (fp64) return launch_backward_t<double, 256>(P, grid, kg, s);
+  if (block == 512) return launch_backward_t<float, 512>(P, grid, kg, s);
+  return launch_backward_t<float, 256>(P, grid, kg, s);
 }
 
 hipError_t launch_tbar(const LaunchParams& P, int grid, double* zscratch, size_t zstride,

@@ -9,8 +9,6 @@
 namespace sgq {
 
 
-constexpr int kMarchPad = 1700;  // padded plane (sx + 6)(sy + 6) of the plane march (sx <= 35)
-
 constexpr int kFnzBlocks = 2048;   // 64-point blocks tracked per node (cubes up to 131072 points)
 constexpr int kNoRow = 255;        // no nonzero row in the block yet
 
@@ -21,9 +19,13 @@ struct NodeState {
   // lists and a double-buffered plane correction); FP64 keeps the separate scatter so that
   // two FP64 workgroups still fit a CU's LDS
   static constexpr bool kFuse = sizeof(T) == 4;
-  static constexpr int kPlanes = kFuse ? 35 : 1;   // cube edges of the plane march
-  static constexpr int kPlaneAtoms = 32;           // group atoms crossing one plane
-  static constexpr int kCorr = kFuse ? 35 * 35 : 1;
+  // widest plane of the march: 49 points for the FP32 512-lane state (one workgroup per
+  // CU: five points per lane cover 49^2), 35 otherwise (two workgroups per CU must fit)
+  static constexpr int kMarchEdge = kFuse && BLOCK >= 512 ? 49 : 35;
+  static constexpr int kMarchPad = (kMarchEdge + 6) * (kMarchEdge + 6);   // zero halo of 3
+  static constexpr int kPlanes = kFuse ? kMarchEdge : 1;   // cube edges of the plane march
+  static constexpr int kPlaneAtoms = 32;                   // group atoms crossing one plane
+  static constexpr int kCorr = kFuse ? kMarchEdge * kMarchEdge : 1;
   int node;
   int sx, sy, sz, ox, oy, oz, periodic, n, start, natoms, abort;
   int atom[kMaxNodeAtoms];
@@ -59,9 +61,10 @@ struct NodeState {
 };
 
 // Whether the node's stencil runs as the plane march (the condition apply_local uses).
-template <typename S>
-__device__ __forceinline__ bool uses_march(const S& st, int block) {
-  return !st.periodic && st.sx * st.sy <= 5 * block && (st.sx + 6) * (st.sy + 6) <= kMarchPad;
+template <typename T, int BLOCK>
+__device__ __forceinline__ bool uses_march(const SGQ_L NodeState<T, BLOCK>& st, int block) {
+  return !st.periodic && st.sx * st.sy <= 5 * block &&
+         (st.sx + 6) * (st.sy + 6) <= NodeState<T, BLOCK>::kMarchPad;
 }
 
 // local linear index -> (x, y, z) of a cube with extents sx, sy
@@ -770,7 +773,7 @@ __device__ __noinline__ double stencil_march(int gnx, int gny, int gnz,
   const int tid = threadIdx.x;
   const int vplane = gnx * gny;
   const T w1 = (T)kFd1, w2 = (T)kFd2, w3 = (T)kFd3;
-  for (int i = tid; i < 2 * kMarchPad; i += BLOCK) (&st.plane[0][0])[i] = (T)0;
+  for (int i = tid; i < 2 * NodeState<T, BLOCK>::kMarchPad; i += BLOCK) (&st.plane[0][0])[i] = (T)0;
   if (PROJ)
     for (int i = tid; i < 2 * NodeState<T, BLOCK>::kCorr; i += BLOCK) (&st.corr[0][0])[i] = (T)0;
   __syncthreads();

@@ -826,7 +826,11 @@ extern "C" int band_energy_backward(sgq_plan* plan, const double* v_loc, const d
     if (pre)
       HIP_OR_FAIL(launch_tbar(P, plan->grid_pre, plan->d_zpre, plan->zpre_stride, plan->d_tbar,
                               plan->d_tbar_k, s));
-    HIP_OR_FAIL(launch_backward(P, plan->fp64, plan->grid_bwd, 256, plan->kg, s));
+    // the forward's lanes per node when they are 512 (one workgroup per CU), else 256 (two)
+    const int bblock = !plan->fp64 && plan->block == 512 ? 512 : 256;
+    const int bgrid = bblock == 512 ? std::max(1, std::min(plan->grid_bwd, plan->ncu))
+                                    : plan->grid_bwd;
+    HIP_OR_FAIL(launch_backward(P, plan->fp64, bgrid, bblock, plan->kg, s));
   }
   const bool have_proj = plan->prob.n_proj > 0 && plan->prob.n_atoms > 0;
   if (!have_proj) {

@@ -60,10 +60,10 @@ def test_prepass_gives_the_in_place_solve_bit_for_bit(precision):
 
 
 def test_prepass_takes_the_forward_tridiagonal(monkeypatch):
-    """After a 512-lane forward (the autotuner's shape for large cubes) the pre-pass solves
-    the forward's tridiagonals, whose last bits differ from the 256-lane recompute's: the
-    gradient is not the in-place one bit for bit (so the pass ran) and agrees with it to
-    the FP32 bar."""
+    """After a 128-lane forward (another autotuner candidate; the backward recomputes with
+    256 lanes, as for every shape but 512) the pre-pass solves the forward's tridiagonals,
+    whose last bits differ from the recompute's: the gradient is not the in-place one bit
+    for bit (so the pass ran) and agrees with it to the FP32 bar."""
     from paper_1907_02604_amd import sgq
     P = _problem("f32", n=48, seed=13)
     v, R, E, w = sgq.device_inputs(P)
@@ -71,12 +71,12 @@ def test_prepass_takes_the_forward_tridiagonal(monkeypatch):
     plan = sgq.Plan.from_problem(P)
     ref = _backward(plan, P, v, R, E, w, forward_first=False)
     plan.close()
-    monkeypatch.setenv("SGQ_BLOCK", "512")
-    monkeypatch.setenv("SGQ_WG_PER_CU", "1")
+    monkeypatch.setenv("SGQ_BLOCK", "128")
+    monkeypatch.setenv("SGQ_WG_PER_CU", "2")
     plan = sgq.Plan.from_problem(P)
     monkeypatch.delenv("SGQ_BLOCK")
     monkeypatch.delenv("SGQ_WG_PER_CU")
-    announce("prepass: 512-lane forward + backward")
+    announce("prepass: 128-lane forward + backward")
     got = _backward(plan, P, v, R, E, w, forward_first=True)
     plan.close()
     assert any(not np.array_equal(a, b) for a, b in zip(got, ref))
@@ -86,11 +86,11 @@ def test_prepass_takes_the_forward_tridiagonal(monkeypatch):
         assert err <= 1e-4, (name, err)
 
 
-def test_prepass_skips_stale_tridiagonals():
+def test_prepass_skips_stale_tridiagonals(monkeypatch):
     """The stored tridiagonals serve only the inputs the forward saw: after v_loc is
     overwritten in place (same pointer, new contents), and after autotuning (whose timing
     launches rewrite the sampled nodes' tridiagonals), the backward equals a backward alone
-    on the current inputs, bit for bit."""
+    on the current inputs with the same launch shape, bit for bit."""
     import torch
     from paper_1907_02604_amd import sgq
     P = _problem("f32", n=40, seed=14)
@@ -111,8 +111,16 @@ def test_prepass_skips_stale_tridiagonals():
         assert np.array_equal(a, b), ("in-place change", name)
     announce("prepass stale: forward, then autotune")
     sgq.band_energy(plan, v, R, E, w, P.mu, P.kT, sgq.SGQ_FREE, e, om)
-    plan.autotune(v, R, E, P.mu, P.kT, sample_nodes=16)
+    lanes, wg_per_cu = plan.autotune(v, R, E, P.mu, P.kT, sample_nodes=16)
     got = _backward(plan, P, v, R, E, w, forward_first=False)
+    plan.close()
+    # the backward recomputes with the plan's lanes per node when they are 512
+    monkeypatch.setenv("SGQ_BLOCK", str(lanes))
+    monkeypatch.setenv("SGQ_WG_PER_CU", str(wg_per_cu))
+    fresh = sgq.Plan.from_problem(P)
+    monkeypatch.delenv("SGQ_BLOCK")
+    monkeypatch.delenv("SGQ_WG_PER_CU")
+    ref = _backward(fresh, P, v, R, E, w, forward_first=False)
+    fresh.close()
     for a, b, name in zip(got, ref, ("dV", "dR", "dE")):
         assert np.array_equal(a, b), ("autotune", name)
-    plan.close()
