@@ -249,3 +249,56 @@ def test_deep_adjoint_on_the_uneven_workload():
         errs = _rel(dV, rdV), _rel(dR, rdR), _rel(dE, rdE)
         print("C3 K=100 grad errs", precision, errs)
         assert max(errs) < tol
+
+
+def test_wide_planes_with_512_lanes(monkeypatch):
+    """A 512-lane plan (the autotuner's shape on the 128^3 screw lattice) recomputes with 512
+    lanes in its backward, whose reverse march then takes planes up to 49 points wide.
+    Three stratified nodes of that workload (cubes 25^3, 41^3 and 49^3, K = 80), FP32: the
+    adjoint by recompute and the adjoint after a forward that retained the nodes' rows are
+    both within 1e-4 of the oracle gradient, and equal bit for bit, since the forward and
+    the recompute run the same 512-lane sweeps."""
+    import torch
+    from paper_1907_02604_amd import sgq
+    from gpu_util import stratified_sample
+    P = synth.make_problem(5)
+    Q = P.subset(stratified_sample(P, 3, seed=42))
+    assert sorted(2 * Q.half_width + 1) == [25, 41, 49]
+    rdV, rdE, rdR = O.band_energy_backward(Q, kind=O.FREE)
+    monkeypatch.setenv("SGQ_BLOCK", "512")
+    monkeypatch.setenv("SGQ_WG_PER_CU", "1")
+    plan = sgq.Plan.from_problem(Q)
+    monkeypatch.delenv("SGQ_BLOCK")
+    monkeypatch.delenv("SGQ_WG_PER_CU")
+    announce("C5 wide planes: 512-lane recompute adjoint")
+    rec = _gpu_grad_on(plan, Q)
+    print("C5 512-lane grad errs", _rel(rec[0], rdV), _rel(rec[1], rdR), _rel(rec[2], rdE))
+    for got, ref in zip(rec, (rdV, rdR, rdE)):
+        assert _rel(got, ref) < 1e-4
+    plan.set_retain(True)
+    v, R, E, w = sgq.device_inputs(Q)
+    e = torch.empty(Q.n_nodes, dtype=torch.float64, device="cuda")
+    om = torch.empty(1, dtype=torch.float64, device="cuda")
+    announce("C5 wide planes: 512-lane forward, retained adjoint")
+    sgq.band_energy(plan, v, R, E, w, Q.mu, Q.kT, sgq.SGQ_FREE, e, om)
+    ret = _gpu_grad_on(plan, Q, (v, R, E, w))
+    plan.close()
+    for a, b, name in zip(ret, rec, ("dV", "dR", "dE")):
+        assert np.array_equal(a, b), name
+
+
+def _gpu_grad_on(plan, P, inputs=None):
+    """(dV, dR, dE) on host through an existing plan, on the given device inputs (the ones a
+    forward saw, for its retained rows) or fresh copies."""
+    import torch
+    from paper_1907_02604_amd import sgq
+    v, R, E, w = inputs or sgq.device_inputs(P)
+    plan.prepare_backward()
+    g = torch.ones(1, dtype=torch.float64, device="cuda")
+    dV = torch.empty_like(v)
+    dR = torch.zeros_like(R)
+    dE = torch.zeros_like(E)
+    sgq.band_energy_backward(plan, v, R, E, w, P.mu, P.kT, sgq.SGQ_FREE, g, dV, dR, dE)
+    torch.cuda.synchronize()
+    assert plan.status() == sgq.SGQ_OK
+    return dV.cpu().numpy(), dR.cpu().numpy(), dE.cpu().numpy()

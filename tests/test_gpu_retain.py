@@ -162,8 +162,9 @@ def test_retention_within_a_byte_limit_keeps_the_costliest_nodes():
 
 def test_retained_rows_of_another_launch_shape_agree_within_rounding(monkeypatch):
     """A forward with 512 lanes per node (an autotuned shape) sums its sweeps in another
-    order than the backward's 256-lane recompute, so its retained rows differ by rounding:
-    the gradient agrees with the recompute's to the FP32 bar, 1e-4 normwise."""
+    order than a 256-lane plan's forward and recompute, so its retained rows differ from
+    theirs by rounding: the gradient agrees with the 256-lane one to the FP32 bar, 1e-4
+    normwise."""
     from paper_1907_02604_amd import sgq
     P = synth.make_problem(4)
     P = P.subset(np.random.default_rng(6).choice(P.n_nodes, 48, replace=False))
