@@ -689,8 +689,9 @@ def main():
                     "retained_nodes": n_ret, "budget_GB": budget / 1e9, "forward_s": tf,
                     "forward_plus_backward_nodes_per_s": Pk.n_nodes / (tf + tb),
                     "forward_plus_recompute_backward_nodes_per_s": Pk.n_nodes / (tk + ta),
-                    # the forward ran with the autotuned lanes per node, the recompute with
-                    # the backward's 256: the two gradients differ by FP32 rounding only
+                    # the forward ran with the autotuned lanes per node and the recompute
+                    # with the backward's, which follow each node's cube: where the two
+                    # differ, so do the gradients, by FP32 rounding only
                     "dV_normwise_rel_diff_vs_recompute":
                         float((dV - dV_re).abs().max() / dV_re.abs().max())}
                 print(f"[bench] C{cfg} checkpointed adjoint {Pk.n_nodes / tb:.1f} nodes/s "

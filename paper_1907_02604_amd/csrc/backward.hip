@@ -560,6 +560,21 @@ __device__ __noinline__ void reverse_march(int gnx, int gny, int gnz, SGQ_L Node
   }
 }
 
+// A node's K x K eigenvector matrix, Z(i, k) = component i of eigenvector k: by rows in
+// a global slot (the backward kernel) or by columns in LDS (the pre-pass), where the lanes
+// of a wave, one component each, then touch consecutive words.  The arithmetic on it is
+// the same either way.
+struct ZRows {
+  SGQ_G double* p;
+  int K;
+  __device__ SGQ_G double& operator()(int i, int k) const { return p[(size_t)i * K + k]; }
+};
+struct ZCols {
+  SGQ_L double* p;
+  int K;
+  __device__ SGQ_L double& operator()(int i, int k) const { return p[k * K + i]; }
+};
+
 // Implicit-shift QR of the tridiagonal (a, b) accumulating all eigenvectors in Z.
 // Run by one whole wave.  Each sweep first forms its chain of Givens rotations: every lane
 // computes the same rotations from the LDS copies of a and b, carrying the entries the
@@ -568,13 +583,14 @@ __device__ __noinline__ void reverse_march(int gnx, int gny, int gnz, SGQ_L Node
 // Then each lane applies the sweep's rotations to its rows of Z with the loads of eight
 // columns issued together, so the sweep waits on memory once per eight rotations rather
 // than once per rotation.
-// Z (global, per workgroup slot): Z[i*K + k] is component i of eigenvector k; each lane
-// owns rows i = lane (mod 64).  rot: 2 (K - 1) doubles of LDS.
-__device__ bool tridiag_eig_wave(SGQ_L double* a, SGQ_L double* b, SGQ_G double* Z, int K,
+// Z (ZRows or ZCols): Z(i, k) is component i of eigenvector k; each lane owns the
+// components i = lane (mod 64).  rot: 2 (K - 1) doubles of LDS.
+template <typename ZA>
+__device__ bool tridiag_eig_wave(SGQ_L double* a, SGQ_L double* b, ZA Z, int K,
                                  SGQ_L double* rot) {
   const int lane = threadIdx.x & (kWave - 1);
   for (int i = lane; i < K; i += kWave)
-    for (int k = 0; k < K; ++k) Z[i * K + k] = (i == k) ? 1.0 : 0.0;
+    for (int k = 0; k < K; ++k) Z(i, k) = (i == k) ? 1.0 : 0.0;
   const double eps = 2.220446049250313e-16;
   int m = K - 1;
   int sweeps = 0;
@@ -644,22 +660,21 @@ __device__ bool tridiag_eig_wave(SGQ_L double* a, SGQ_L double* b, SGQ_G double*
     // the rotations on the rows of Z: column k+1's old value is loaded before rotation k
     // writes column k, and its new value is carried to rotation k+1
     for (int i = lane; i < K; i += kWave) {
-      SGQ_G double* zi = Z + (size_t)i * K;
-      double u0 = zi[l];
+      double u0 = Z(i, l);
       for (int k0 = l; k0 < m; k0 += 8) {
         double u1[8];
 #pragma unroll
-        for (int t = 0; t < 8; ++t) u1[t] = k0 + t < m ? zi[k0 + t + 1] : 0.0;
+        for (int t = 0; t < 8; ++t) u1[t] = k0 + t < m ? Z(i, k0 + t + 1) : 0.0;
 #pragma unroll
         for (int t = 0; t < 8; ++t) {
           if (k0 + t < m) {
             const double c = rot[2 * (k0 + t - l)], s = rot[2 * (k0 + t - l) + 1];
-            zi[k0 + t] = c * u0 - s * u1[t];
+            Z(i, k0 + t) = c * u0 - s * u1[t];
             u0 = s * u0 + c * u1[t];
           }
         }
       }
-      zi[m] = u0;
+      Z(i, m) = u0;
     }
     // rot is rewritten by the next sweep only after every lane has read it
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -671,21 +686,21 @@ __device__ bool tridiag_eig_wave(SGQ_L double* a, SGQ_L double* b, SGQ_G double*
 // alphabar_j = Tbar_jj and betabar_j = 2 Tbar_j,j+1 of one node, Tbar = cscale S (D o s1 s1^T) S^T
 // (Daleckii-Krein), from the eigenvalues ta and eigenvectors S of T (Z[i*K + k]: component i
 // of eigenvector k).  G_kl = s1_k D_kl s1_l (s1 the first row of S, D the divided
-// differences of F, F' on the diagonal and for nearly equal eigenvalues) goes to the second
-// half of the slot; thread (j, c) then forms y_jl = sum_k S_jk G_lk (G is symmetric) for the
+// differences of F, F' on the diagonal and for nearly equal eigenvalues) goes to G (K^2
+// doubles, global); thread (j, c) then forms y_jl = sum_k S_jk G_lk (G is symmetric) for the
 // columns l = c (mod nch) and its parts of alphabar_j and betabar_j, which are added in a
 // fixed order.  Run by the NT threads of a workgroup; Fv, Fd: K values, part: 4 kBwdMaxDepth.
-template <int NT>
+template <int NT, typename ZA>
 __device__ void daleckii_krein(const LaunchParams& P, SGQ_L const double* ta, SGQ_L double* Fv,
-                               SGQ_L double* Fd, SGQ_L double* part, SGQ_G double* Z, int keff,
-                               double cscale, SGQ_L double* abar, SGQ_L double* bbar) {
+                               SGQ_L double* Fd, SGQ_L double* part, ZA Z,
+                               SGQ_G double* __restrict__ G, int keff, double cscale,
+                               SGQ_L double* abar, SGQ_L double* bbar) {
   const int tid = threadIdx.x;
   for (int k = tid; k < keff; k += NT) {
     Fv[k] = integrand_value(ta[k], P.mu, P.kT, P.integrand);
     Fd[k] = integrand_deriv(ta[k], P.mu, P.kT, P.integrand);
   }
   __syncthreads();
-  SGQ_G double* __restrict__ G = Z + (size_t)keff * keff;
   for (int t = tid; t < keff * keff; t += NT) {
     const int k = t / keff, l = t - k * keff;
     const double tk = ta[k], tl = ta[l];
@@ -698,21 +713,20 @@ __device__ void daleckii_krein(const LaunchParams& P, SGQ_L const double* ta, SG
     } else {
       D = (Fv[k] - Fv[l]) / diff;
     }
-    G[t] = Z[k] * D * Z[l];
+    G[t] = Z(0, k) * D * Z(0, l);
   }
   __syncthreads();
   const int nch = keff * 8 <= 2 * kBwdMaxDepth ? 8 : (2 * kBwdMaxDepth) / keff;
   for (int t = tid; t < keff * nch; t += NT) {
     const int j = t / nch, c = t - j * nch;
-    const SGQ_G double* zj = Z + (size_t)j * keff;
-    const SGQ_G double* zj1 = Z + (size_t)(j + 1 < keff ? j + 1 : j) * keff;
+    const int j1 = j + 1 < keff ? j + 1 : j;
     double pa = 0.0, pb = 0.0;
     for (int l = c; l < keff; l += nch) {
       const SGQ_G double* gl = G + (size_t)l * keff;
       double y = 0.0;
-      for (int k = 0; k < keff; ++k) y += zj[k] * gl[k];
-      pa += y * zj[l];
-      pb += y * zj1[l];
+      for (int k = 0; k < keff; ++k) y += Z(j, k) * gl[k];
+      pa += y * Z(j, l);
+      pb += y * Z(j1, l);
     }
     part[2 * t] = pa;
     part[2 * t + 1] = pb;
@@ -735,10 +749,14 @@ __device__ void daleckii_krein(const LaunchParams& P, SGQ_L const double* ta, SG
 // the QR sweeps of different nodes overlap.  Each node's tridiagonal is the one the forward
 // call stored (alpha, beta, K_eff); it serves only when the forward saw these inputs
 // (hash[0] == hash[1]), and the backward kernel takes a node's result only when its own
-// K_eff agrees (tbar_k).  Z: 2 K_max^2 doubles per workgroup.
+// K_eff agrees (tbar_k).  zscratch: 2 K_max^2 doubles per workgroup.  With LDSZ the
+// eigenvectors stay in the workgroup's dynamic LDS (K_max^2 doubles) for all the sweeps and
+// only G goes to zscratch; otherwise both are in zscratch.
+template <bool LDSZ>
 __global__ __launch_bounds__(kWave) void tbar_kernel(LaunchParams P, double* zscratch,
                                                       size_t zstride, double* tbar,
                                                       int32_t* tbar_k) {
+  extern __shared__ double zdyn_s[];
   __shared__ double ta_s[kBwdMaxDepth], tb_s[kBwdMaxDepth], Fv_s[kBwdMaxDepth], Fd_s[kBwdMaxDepth];
   __shared__ double part_s[4 * kBwdMaxDepth];
   __shared__ double abar_s[kBwdMaxDepth], bbar_s[kBwdMaxDepth];
@@ -773,11 +791,22 @@ __global__ __launch_bounds__(kWave) void tbar_kernel(LaunchParams P, double* zsc
       tb[k] = k + 1 < keff ? tri[kmax + k] : 0.0;
     }
     __syncthreads();
-    const bool ok = tridiag_eig_wave(ta, tb, Z, keff, part);
-    __syncthreads();
+    const double cscale = 2.0 * P.node_weight[q] * gomega;
+    bool ok;
+    if constexpr (LDSZ) {
+      const ZCols Zl{(SGQ_L double*)zdyn_s, keff};
+      ok = tridiag_eig_wave(ta, tb, Zl, keff, part);
+      __syncthreads();
+      if (ok) daleckii_krein<kWave>(P, ta, Fv, Fd, part, Zl, Z, keff, cscale, abar, bbar);
+    } else {
+      const ZRows Zg{Z, keff};
+      ok = tridiag_eig_wave(ta, tb, Zg, keff, part);
+      __syncthreads();
+      if (ok)
+        daleckii_krein<kWave>(P, ta, Fv, Fd, part, Zg, Z + (size_t)keff * keff, keff, cscale,
+                              abar, bbar);
+    }
     if (ok) {
-      daleckii_krein<kWave>(P, ta, Fv, Fd, part, Z, keff, 2.0 * P.node_weight[q] * gomega, abar,
-                            bbar);
       double* out = tbar + (size_t)q * 2 * kmax;
       for (int k = tid; k < keff; k += kWave) {
         out[k] = abar[k];
@@ -880,12 +909,12 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2, 2))) v
       }
       __syncthreads();
       if (wave == 0) {
-        bool ok = tridiag_eig_wave(st.ta, st.tb, Z, keff, bs.part);
+        bool ok = tridiag_eig_wave(st.ta, st.tb, ZRows{Z, keff}, keff, bs.part);
         if (!ok && lane == 0) atomicOr(P.status, kStatusNonFinite);
       }
       __syncthreads();
-      daleckii_krein<BLOCK>(P, st.ta, bs.Fv, bs.Fd, bs.part, Z, keff,
-                            2.0 * P.node_weight[q] * gomega, bs.abar, bs.bbar);
+      daleckii_krein<BLOCK>(P, st.ta, bs.Fv, bs.Fd, bs.part, ZRows{Z, keff}, Z + (size_t)keff * keff,
+                            keff, 2.0 * P.node_weight[q] * gomega, bs.abar, bs.bbar);
     }
     double* dEp = P.dE_part + (size_t)q * kMaxNodeAtoms * 4;
     double* dRp = P.dR_part + (size_t)q * kMaxNodeAtoms * 3;
@@ -1224,6 +1253,27 @@ static hipError_t launch_backward_t(const LaunchParams& P, int grid, int kg, hip
   return hipGetLastError();
 }
 
+// FP32 Dirichlet nodes whose planes only the 512-lane march takes: wider than the 256-lane
+// march allows (35 points), at most 49 (the same test as uses_march on the device).  The
+// backward reverses them in a 512-lane launch and every other node in a 256-lane one.
+bool backward_wide_node(int half_width) {
+  if (half_width < 0) return false;
+  const int side = 2 * half_width + 1;
+  auto fits = [side](int block, int pad) {
+    return side * side <= 5 * block && (side + 6) * (side + 6) <= pad;
+  };
+  return !fits(256, NodeState<float, 256>::kMarchPad) && fits(512, NodeState<float, 512>::kMarchPad);
+}
+
+__global__ void queue_reset_kernel(int* queue) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *queue = 0;
+}
+
+hipError_t launch_queue_reset(int* queue, hipStream_t s) {
+  hipLaunchKernelGGL(queue_reset_kernel, dim3(1), dim3(1), 0, s, queue);
+  return hipGetLastError();
+}
+
 // 256 lanes per node (two workgroups per CU) or, in FP32, 512 (one per CU: the wide-plane
 // march of cubes up to 49 points across); FP64 nodes take 256.
 hipError_t launch_backward(const LaunchParams& P, bool fp64, int grid, int block, int kg,
@@ -1233,9 +1283,30 @@ hipError_t launch_backward(const LaunchParams& P, bool fp64, int grid, int block
   return launch_backward_t<float, 256>(P, grid, kg, s);
 }
 
+// The pre-pass keeps a node's eigenvectors in LDS when K_max^2 doubles and the kernel's
+// static LDS fit in 64 KiB (K_max <= 83), else in its global slot.
+static size_t tbar_lds_bytes(int kmax) {
+  const size_t z = (size_t)kmax * kmax * 8;
+  return z + 10 * 1024 + 256 <= 64 * 1024 ? z : 0;
+}
+
+// Workgroups of the pre-pass per CU: 16 one-wave workgroups, fewer when each holds its
+// eigenvectors in LDS (160 KiB per CU).
+int tbar_workgroups_per_cu(int kmax) {
+  const size_t z = tbar_lds_bytes(kmax);
+  if (z == 0) return 16;
+  return (int)std::max<size_t>(1, std::min<size_t>(16, (160 * 1024) / (z + 10 * 1024 + 256)));
+}
+
 hipError_t launch_tbar(const LaunchParams& P, int grid, double* zscratch, size_t zstride,
                        double* tbar, int32_t* tbar_k, hipStream_t s) {
-  hipLaunchKernelGGL(tbar_kernel, dim3(grid), dim3(kWave), 0, s, P, zscratch, zstride, tbar, tbar_k);
+  const size_t z = tbar_lds_bytes(P.kmax_out);
+  if (z)
+    hipLaunchKernelGGL(tbar_kernel<true>, dim3(grid), dim3(kWave), z, s, P, zscratch, zstride,
+                       tbar, tbar_k);
+  else
+    hipLaunchKernelGGL(tbar_kernel<false>, dim3(grid), dim3(kWave), 0, s, P, zscratch, zstride,
+                       tbar, tbar_k);
   return hipGetLastError();
 }
 

@@ -31,6 +31,9 @@ hipError_t launch_fermi_level(const double* tw, const double* weight, int nq, in
                               double* ws, hipStream_t s);
 hipError_t launch_backward(const LaunchParams& P, bool fp64, int grid, int block, int kg,
                            hipStream_t s);
+int tbar_workgroups_per_cu(int kmax);
+bool backward_wide_node(int half_width);
+hipError_t launch_queue_reset(int* queue, hipStream_t s);
 hipError_t launch_tbar(const LaunchParams& P, int grid, double* zscratch, size_t zstride,
                        double* tbar, int32_t* tbar_k, hipStream_t s);
 hipError_t launch_backward_gather(const LaunchParams& P, bool fp64, const int32_t* cell_start,
@@ -100,6 +103,10 @@ struct sgq_plan {
   // backward state (allocated on the first backward call)
   bool bwd_ready = false;
   int grid_bwd = 0;
+  // the backward's node queue: the FP32 nodes of the 512-lane launch first (n_bwide), then
+  // the others, each part in cost order
+  int32_t* d_border = nullptr;
+  int n_bwide = 0;
   size_t bwd_slot_stride = 0;
   void* d_Wb = nullptr;
   double* d_Zb = nullptr;
@@ -766,18 +773,28 @@ static int ensure_backward(sgq_plan* p) {
   e = e ? e : dalloc(p, &p->d_dRp, (size_t)nq * kMaxNodeAtoms * 3 * 8);
   e = e ? e : dalloc(p, &p->d_dEp, (size_t)nq * kMaxNodeAtoms * 4 * 8);
   e = e ? e : dalloc(p, &p->d_node_atoms, (size_t)nq * (kMaxNodeAtoms + 1) * 4);
-  // the eigensolve pre-pass: 16 one-wave workgroups per CU, each with the eigenvectors and
-  // weighted divided differences of one node (2 kmax^2 doubles), and the per-node results
-  p->grid_pre = std::max(1, std::min(nq, 16 * p->ncu));
+  // the eigensolve pre-pass: one-wave workgroups, as many per CU as their LDS allows, each
+  // with the eigenvectors and weighted divided differences of one node (2 kmax^2 doubles
+  // of global slot), and the per-node results
+  p->grid_pre = std::max(1, std::min(nq, tbar_workgroups_per_cu(p->kmax) * p->ncu));
   p->zpre_stride = 2 * (size_t)p->kmax * p->kmax;
   e = e ? e : dalloc(p, &p->d_zpre, (size_t)p->grid_pre * p->zpre_stride * 8);
   e = e ? e : dalloc(p, &p->d_tbar, (size_t)nq * 2 * p->kmax * 8);
   e = e ? e : dalloc(p, &p->d_tbar_k, (size_t)nq * 4);
+  e = e ? e : dalloc(p, &p->d_border, (size_t)nq * 4);
   if (e != hipSuccess) {
     (void)hipGetLastError();
     return fail(SGQ_ENOMEM, std::string("backward workspace: ") + hipGetErrorString(e));
   }
   HIP_OR_FAIL(hipMemcpy(p->d_cube_off, off.data(), (nq + 1) * 8, hipMemcpyHostToDevice));
+  // the backward's queue: the nodes of the 512-lane launch, then the rest, in cost order
+  std::vector<int32_t> border(p->h_order);
+  const auto mid = std::stable_partition(border.begin(), border.end(), [p](int32_t q) {
+    return !p->fp64 && backward_wide_node(p->h_hw[(size_t)q]);
+  });
+  p->n_bwide = (int)(mid - border.begin());
+  if (nq > 0)
+    HIP_OR_FAIL(hipMemcpy(p->d_border, border.data(), (size_t)nq * 4, hipMemcpyHostToDevice));
   p->bwd_ready = true;
   return SGQ_OK;
 }
@@ -826,11 +843,23 @@ extern "C" int band_energy_backward(sgq_plan* plan, const double* v_loc, const d
     if (pre)
       HIP_OR_FAIL(launch_tbar(P, plan->grid_pre, plan->d_zpre, plan->zpre_stride, plan->d_tbar,
                               plan->d_tbar_k, s));
-    // the forward's lanes per node when they are 512 (one workgroup per CU), else 256 (two)
-    const int bblock = !plan->fp64 && plan->block == 512 ? 512 : 256;
-    const int bgrid = bblock == 512 ? std::max(1, std::min(plan->grid_bwd, plan->ncu))
-                                    : plan->grid_bwd;
-    HIP_OR_FAIL(launch_backward(P, plan->fp64, bgrid, bblock, plan->kg, s));
+    // the nodes only the wide-plane march takes, with 512 lanes (one workgroup per CU);
+    // then the others with 256 (two), from a fresh queue
+    const int nq = plan->prob.n_nodes, nw = plan->n_bwide;
+    if (nw > 0) {
+      LaunchParams Pw = P;
+      Pw.order = plan->d_border;
+      Pw.n_nodes = nw;
+      HIP_OR_FAIL(launch_backward(Pw, false, std::max(1, std::min(nw, plan->ncu)), 512, plan->kg, s));
+    }
+    if (nq > nw) {
+      if (nw > 0) HIP_OR_FAIL(launch_queue_reset(P.queue, s));
+      LaunchParams Pn = P;
+      Pn.order = plan->d_border + nw;
+      Pn.n_nodes = nq - nw;
+      HIP_OR_FAIL(launch_backward(Pn, plan->fp64, std::max(1, std::min(nq - nw, plan->grid_bwd)),
+                                  256, plan->kg, s));
+    }
   }
   const bool have_proj = plan->prob.n_proj > 0 && plan->prob.n_atoms > 0;
   if (!have_proj) {

@@ -251,39 +251,57 @@ def test_deep_adjoint_on_the_uneven_workload():
         assert max(errs) < tol
 
 
-def test_wide_planes_with_512_lanes(monkeypatch):
-    """A 512-lane plan (the autotuner's shape on the 128^3 screw lattice) recomputes with 512
-    lanes in its backward, whose reverse march then takes planes up to 49 points wide.
-    Three stratified nodes of that workload (cubes 25^3, 41^3 and 49^3, K = 80), FP32: the
-    adjoint by recompute and the adjoint after a forward that retained the nodes' rows are
-    both within 1e-4 of the oracle gradient, and equal bit for bit, since the forward and
-    the recompute run the same 512-lane sweeps."""
+def test_wide_planes_take_the_512_lane_launch(monkeypatch):
+    """The backward reverses FP32 cubes wider than 35 points (up to 49) in a 512-lane launch
+    of their own, whose march takes planes that wide, and the other nodes in a 256-lane one.
+    Three stratified nodes of the 128^3 screw lattice (cubes 25^3, 41^3 and 49^3, K = 80):
+    the adjoint is within 1e-4 of the oracle gradient on every output, and the same bits
+    whatever lanes per node the plan's forward uses.  After a 512-lane forward that retained
+    the rows of the two wide nodes, their adjoint equals the recompute bit for bit, since
+    the forward and the recompute run the same 512-lane sweeps."""
     import torch
     from paper_1907_02604_amd import sgq
     from gpu_util import stratified_sample
     P = synth.make_problem(5)
     Q = P.subset(stratified_sample(P, 3, seed=42))
-    assert sorted(2 * Q.half_width + 1) == [25, 41, 49]
+    side = 2 * Q.half_width + 1
+    assert sorted(side) == [25, 41, 49]
     rdV, rdE, rdR = O.band_energy_backward(Q, kind=O.FREE)
-    monkeypatch.setenv("SGQ_BLOCK", "512")
-    monkeypatch.setenv("SGQ_WG_PER_CU", "1")
+
+    def plan_512(prob):
+        monkeypatch.setenv("SGQ_BLOCK", "512")
+        monkeypatch.setenv("SGQ_WG_PER_CU", "1")
+        plan = sgq.Plan.from_problem(prob)
+        monkeypatch.delenv("SGQ_BLOCK")
+        monkeypatch.delenv("SGQ_WG_PER_CU")
+        return plan
+
+    announce("C5 wide planes: adjoint, 256-lane plan")
     plan = sgq.Plan.from_problem(Q)
-    monkeypatch.delenv("SGQ_BLOCK")
-    monkeypatch.delenv("SGQ_WG_PER_CU")
-    announce("C5 wide planes: 512-lane recompute adjoint")
     rec = _gpu_grad_on(plan, Q)
-    print("C5 512-lane grad errs", _rel(rec[0], rdV), _rel(rec[1], rdR), _rel(rec[2], rdE))
+    plan.close()
+    print("C5 wide-plane grad errs", _rel(rec[0], rdV), _rel(rec[1], rdR), _rel(rec[2], rdE))
     for got, ref in zip(rec, (rdV, rdR, rdE)):
         assert _rel(got, ref) < 1e-4
+    announce("C5 wide planes: adjoint, 512-lane plan")
+    plan = plan_512(Q)
+    rec512 = _gpu_grad_on(plan, Q)
+    plan.close()
+    for a, b, name in zip(rec512, rec, ("dV", "dR", "dE")):
+        assert np.array_equal(a, b), name
+    W = Q.subset(np.nonzero(side > 35)[0])
+    plan = plan_512(W)
+    announce("C5 wide planes: two wide nodes, recompute")
+    wrec = _gpu_grad_on(plan, W)
     plan.set_retain(True)
-    v, R, E, w = sgq.device_inputs(Q)
-    e = torch.empty(Q.n_nodes, dtype=torch.float64, device="cuda")
+    v, R, E, w = sgq.device_inputs(W)
+    e = torch.empty(W.n_nodes, dtype=torch.float64, device="cuda")
     om = torch.empty(1, dtype=torch.float64, device="cuda")
     announce("C5 wide planes: 512-lane forward, retained adjoint")
-    sgq.band_energy(plan, v, R, E, w, Q.mu, Q.kT, sgq.SGQ_FREE, e, om)
-    ret = _gpu_grad_on(plan, Q, (v, R, E, w))
+    sgq.band_energy(plan, v, R, E, w, W.mu, W.kT, sgq.SGQ_FREE, e, om)
+    wret = _gpu_grad_on(plan, W, (v, R, E, w))
     plan.close()
-    for a, b, name in zip(ret, rec, ("dV", "dR", "dE")):
+    for a, b, name in zip(wret, wrec, ("dV", "dR", "dE")):
         assert np.array_equal(a, b), name
 
 

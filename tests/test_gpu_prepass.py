@@ -60,8 +60,9 @@ def test_prepass_gives_the_in_place_solve_bit_for_bit(precision):
 
 
 def test_prepass_takes_the_forward_tridiagonal(monkeypatch):
-    """After a 128-lane forward (another autotuner candidate; the backward recomputes with
-    256 lanes, as for every shape but 512) the pre-pass solves the forward's tridiagonals,
+    """After a 128-lane forward (another autotuner candidate; the backward recomputes these
+    33^3 cubes with 256 lanes whatever the forward's shape) the pre-pass solves the forward's
+    tridiagonals,
     whose last bits differ from the recompute's: the gradient is not the in-place one bit
     for bit (so the pass ran) and agrees with it to the FP32 bar."""
     from paper_1907_02604_amd import sgq
@@ -86,7 +87,7 @@ def test_prepass_takes_the_forward_tridiagonal(monkeypatch):
         assert err <= 1e-4, (name, err)
 
 
-def test_prepass_skips_stale_tridiagonals(monkeypatch):
+def test_prepass_skips_stale_tridiagonals():
     """The stored tridiagonals serve only the inputs the forward saw: after v_loc is
     overwritten in place (same pointer, new contents), and after autotuning (whose timing
     launches rewrite the sampled nodes' tridiagonals), the backward equals a backward alone
@@ -111,15 +112,12 @@ def test_prepass_skips_stale_tridiagonals(monkeypatch):
         assert np.array_equal(a, b), ("in-place change", name)
     announce("prepass stale: forward, then autotune")
     sgq.band_energy(plan, v, R, E, w, P.mu, P.kT, sgq.SGQ_FREE, e, om)
-    lanes, wg_per_cu = plan.autotune(v, R, E, P.mu, P.kT, sample_nodes=16)
+    plan.autotune(v, R, E, P.mu, P.kT, sample_nodes=16)
     got = _backward(plan, P, v, R, E, w, forward_first=False)
     plan.close()
-    # the backward recomputes with the plan's lanes per node when they are 512
-    monkeypatch.setenv("SGQ_BLOCK", str(lanes))
-    monkeypatch.setenv("SGQ_WG_PER_CU", str(wg_per_cu))
+    # the same as a fresh plan's: the backward's lanes per node follow the node's cube, not
+    # the autotuned shape
     fresh = sgq.Plan.from_problem(P)
-    monkeypatch.delenv("SGQ_BLOCK")
-    monkeypatch.delenv("SGQ_WG_PER_CU")
     ref = _backward(fresh, P, v, R, E, w, forward_first=False)
     fresh.close()
     for a, b, name in zip(got, ref, ("dV", "dR", "dE")):

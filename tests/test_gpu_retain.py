@@ -63,7 +63,8 @@ def test_retained_backward_is_bitwise_the_recompute(precision):
 
 def test_retention_is_keyed_to_the_inputs_and_invalidated():
     """A forward with other input pointers, or an autotune in between, leaves the backward
-    to recompute: the gradients stay those of the backward's own inputs."""
+    to recompute: the gradients stay those of the backward's own inputs, bit for bit (the
+    backward's lanes per node follow the node's cube, not the autotuned shape)."""
     import torch
     from paper_1907_02604_amd import sgq
     P = synth.make_problem(4)
@@ -129,12 +130,15 @@ def test_inputs_overwritten_in_place_are_detected():
 
 
 def test_retention_within_a_byte_limit_keeps_the_costliest_nodes():
-    """Dislocation-shaped nodes (cubes 25^3..49^3, K = 80): a limit that holds a third of
+    """Dislocation-shaped nodes with cubes of 25^3, 29^3 and 33^3 (K = 80; the backward reverses
+    them with 256 lanes, as the default forward runs them): a limit that holds a third of
     the nodes' rows retains that many, the backward takes them and recomputes the rest, and
     the gradient is bitwise the full recompute's.  A limit below one node is rejected."""
     from paper_1907_02604_amd import sgq
     P5 = synth.make_problem(5)
-    P = P5.subset(np.random.default_rng(5).choice(P5.n_nodes, 36, replace=False))
+    narrow = np.nonzero(2 * P5.half_width + 1 <= 35)[0]
+    P = P5.subset(np.sort(np.random.default_rng(5).choice(narrow, 36, replace=False)))
+    assert len(set(P.half_width.tolist())) == 3
     v, R, E, w = sgq.device_inputs(P)
     announce("retain limit: recompute reference")
     ref_plan = sgq.Plan.from_problem(P)
@@ -184,6 +188,32 @@ def test_retained_rows_of_another_launch_shape_agree_within_rounding(monkeypatch
     plan.close()
     for a, b, name in zip(ref, got, ("e_node", "dV", "dR", "dE")):
         err = np.max(np.abs(a - b)) / np.max(np.abs(a))
+        assert err <= 1e-4, (name, err)
+
+
+def test_retained_wide_nodes_of_a_256_lane_forward_agree_within_rounding():
+    """Dislocation nodes with cubes of 25^3..49^3 after a default (256-lane) forward that
+    retained them all: the backward reverses the cubes wider than 35 points with 512 lanes,
+    whose sweeps sum in another order than the forward's, so the gradient agrees with the
+    full recompute's to the FP32 bar, 1e-4 normwise, on every output."""
+    from paper_1907_02604_amd import sgq
+    P5 = synth.make_problem(5)
+    P = P5.subset(np.sort(np.random.default_rng(9).choice(P5.n_nodes, 24, replace=False)))
+    assert (2 * P.half_width + 1 > 35).any() and (2 * P.half_width + 1 <= 35).any()
+    v, R, E, w = sgq.device_inputs(P)
+    announce("retain wide: recompute reference")
+    ref_plan = sgq.Plan.from_problem(P)
+    ref = _forward_backward(ref_plan, P, v, R, E, w)
+    ref_plan.close()
+    plan = sgq.Plan.from_problem(P)
+    assert plan.set_retain(True) == P.n_nodes
+    announce("retain wide: 256-lane forward, retained backward")
+    got = _forward_backward(plan, P, v, R, E, w)
+    plan.close()
+    assert np.array_equal(ref[0], got[0])
+    for a, b, name in zip(ref[1:], got[1:], ("dV", "dR", "dE")):
+        err = np.max(np.abs(a - b)) / np.max(np.abs(a))
+        print("retain wide", name, err)
         assert err <= 1e-4, (name, err)
 
 
