@@ -122,7 +122,9 @@ int band_energy(sgq_plan* plan, const double* v_loc, const double* atom_R,
  * (one cube of the node's points per node: 15.9 GB for 110592 nodes of 33^3 points in
  * FP32), the per-node atom partials, the lists that gather the cubes into dV, and the
  * eigensolve pre-pass's buffers (per node 2 K_max doubles of alphabar / betabar; per
- * pre-pass workgroup, 16 per CU, 2 K_max^2 doubles).  Allocates and uploads them (host
+ * pre-pass workgroup, up to 16 per CU, 2 K_max^2 doubles), and the backward's node
+ * queue (FP32 cubes of 37 to 49 points first, reversed with 512 lanes per node, then the
+ * others, with 256).  Allocates and uploads them (host
  * geometry, hipMalloc, blocking copies), so it is synchronous; call it once before the
  * first band_energy_backward.  Returns SGQ_ENOMEM when the workspace does not fit,
  * SGQ_EPLAN when the plan's depth exceeds the adjoint's (128, every depth a plan
@@ -343,9 +345,10 @@ int sgq_effective_potential(sgq_potential* pot, const double* rho, const double*
  * retained rows of those nodes instead of recomputing their forward Lanczos and recomputes
  * the others; both calls hash the contents of those inputs on the device (64-bit, order
  * independent), and when the hashes differ (inputs overwritten in place in between) the
- * backward recomputes every node.  The result is bitwise the full recompute's when the forward ran with 256
- * lanes per node, the backward's own launch shape; after another autotuned shape the
- * retained rows differ from a recompute by rounding only.  The backward consumes them (it overwrites the
+ * backward recomputes every node.  The result is bitwise the full recompute's when the
+ * forward ran each node with the backward's lanes for it (512 for FP32 cubes of 37 to 49
+ * points, 256 for the others); after another autotuned shape the retained rows differ
+ * from a recompute by rounding only.  The backward consumes them (it overwrites the
  * u_j rows), and any other call that runs a forward launch (sgq_plan_autotune, the plain
  * schedule) invalidates them; an invalid or mismatched retention falls back to the
  * recompute.  Every call first waits for the device and frees the storage a

@@ -8,7 +8,8 @@
 //      (sgq_plan_set_retain, for all nodes or the costliest ones within a byte limit),
 //      those are taken with alpha, beta and K_eff from the forward's tridiagonal buffer
 //      (the same values bit for bit);
-//   2. the eigenvectors S of T (wave-parallel QR sweeps, FP64, in LDS) give the
+//   2. the eigenvectors S of T (wave-parallel QR sweeps, FP64, S in a global slot; in a
+//      pre-pass over the forward's tridiagonals when it stored them, S in LDS) give the
 //      Daleckii-Krein adjoint Tbar = 2 n_q Omegabar S (D o s1 s1^T) S^T, D the divided
 //      differences of F; alphabar_j = Tbar_jj, betabar_j = 2 Tbar_j,j+1;
 //   3. the exact-arithmetic three-term recurrence is reversed, j = K-1 .. 0:
