@@ -1284,15 +1284,18 @@ hipError_t launch_backward(const LaunchParams& P, bool fp64, int grid, int block
   return launch_backward_t<float, 256>(P, grid, kg, s);
 }
 
-// The pre-pass keeps a node's eigenvectors in LDS when K_max^2 doubles and the kernel's
-// static LDS fit in 64 KiB (K_max <= 83), else in its global slot.
+// The pre-pass keeps a node's eigenvectors in LDS when K_max^2 doubles beside the kernel's
+// static LDS still let four workgroups share a CU's 160 KiB (K_max <= 60), else in its
+// global slot.  With fewer nodes in flight the latency of the rotation chains decides: at
+// K = 80 (two workgroups per CU) the LDS form took 485 ms for 65536 nodes, the global form
+// 314 ms; at K = 60 the LDS form took 15.1 ms for 8192 nodes, the global form 17.6 ms.
 static size_t tbar_lds_bytes(int kmax) {
   const size_t z = (size_t)kmax * kmax * 8;
-  return z + 10 * 1024 + 256 <= 64 * 1024 ? z : 0;
+  return 4 * (z + 10 * 1024 + 256) <= 160 * 1024 ? z : 0;
 }
 
 // Workgroups of the pre-pass per CU: 16 one-wave workgroups, fewer when each holds its
-// eigenvectors in LDS (160 KiB per CU).
+// eigenvectors in LDS.
 int tbar_workgroups_per_cu(int kmax) {
   const size_t z = tbar_lds_bytes(kmax);
   if (z == 0) return 16;

@@ -13,10 +13,13 @@ from gpu_util import announce, needs_gpu
 pytestmark = [pytest.mark.gpu, needs_gpu]
 
 
-def _problem(precision="f32", n=40, seed=12):
+def _problem(precision="f32", n=40, seed=12, cfg=4):
+    """n seeded nodes of the workload; of the dislocation workload only cubes of at most 35
+    points, which the backward reverses with the default forward's 256 lanes."""
     import dataclasses
-    P = synth.make_problem(4)
-    P = P.subset(np.sort(np.random.default_rng(seed).choice(P.n_nodes, n, replace=False)))
+    P = synth.make_problem(cfg)
+    pool = np.nonzero(2 * P.half_width + 1 <= 35)[0]
+    P = P.subset(np.sort(np.random.default_rng(seed).choice(pool, n, replace=False)))
     return dataclasses.replace(P, precision=precision)
 
 
@@ -40,12 +43,15 @@ def _backward(plan, P, v, R, E, w, forward_first):
     return dV.cpu().numpy(), dR.cpu().numpy(), dE.cpu().numpy()
 
 
-@pytest.mark.parametrize("precision", ["f32", "f64"])
-def test_prepass_gives_the_in_place_solve_bit_for_bit(precision):
+@pytest.mark.parametrize("cfg,precision", [(4, "f32"), (4, "f64"), (5, "f32")])
+def test_prepass_gives_the_in_place_solve_bit_for_bit(cfg, precision):
     """A forward then a backward (pre-pass over the forward's tridiagonals) against a
-    backward alone (eigensolves in place), both with the 256-lane recompute: same bits."""
+    backward alone (eigensolves in place), both with the default 256-lane forward: same
+    bits.  K = 60 (differentiation workload) takes the pre-pass form with the eigenvectors
+    in LDS, K = 80 (dislocation workload, cubes of 25^3..33^3) the form with them in global
+    memory; the in-place solve keeps them in global memory."""
     from paper_1907_02604_amd import sgq
-    P = _problem(precision)
+    P = _problem(precision, n=40 if cfg == 4 else 12, cfg=cfg)
     v, R, E, w = sgq.device_inputs(P)
     announce(f"prepass {precision}: forward + backward")
     plan = sgq.Plan.from_problem(P)
