@@ -122,7 +122,7 @@ int band_energy(sgq_plan* plan, const double* v_loc, const double* atom_R,
  * (one cube of the node's points per node: 15.9 GB for 110592 nodes of 33^3 points in
  * FP32), the per-node atom partials, the lists that gather the cubes into dV, and the
  * eigensolve pre-pass's buffers (per node 2 K_max doubles of alphabar / betabar; per
- * pre-pass workgroup, up to 16 per CU, 2 K_max^2 doubles), and the backward's node
+ * pre-pass workgroup, 16 per CU, 2 K_max^2 doubles), and the backward's node
  * queue (FP32 cubes of 37 to 49 points first, reversed with 512 lanes per node, then the
  * others, with 256).  Allocates and uploads them (host
  * geometry, hipMalloc, blocking copies), so it is synchronous; call it once before the

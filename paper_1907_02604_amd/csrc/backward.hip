@@ -9,7 +9,7 @@
 //      those are taken with alpha, beta and K_eff from the forward's tridiagonal buffer
 //      (the same values bit for bit);
 //   2. the eigenvectors S of T (wave-parallel QR sweeps, FP64, S in a global slot; in a
-//      pre-pass over the forward's tridiagonals when it stored them, S in LDS) give the
+//      pre-pass over the forward's tridiagonals when it stored them) give the
 //      Daleckii-Krein adjoint Tbar = 2 n_q Omegabar S (D o s1 s1^T) S^T, D the divided
 //      differences of F; alphabar_j = Tbar_jj, betabar_j = 2 Tbar_j,j+1;
 //   3. the exact-arithmetic three-term recurrence is reversed, j = K-1 .. 0:
@@ -561,19 +561,16 @@ __device__ __noinline__ void reverse_march(int gnx, int gny, int gnz, SGQ_L Node
   }
 }
 
-// A node's K x K eigenvector matrix, Z(i, k) = component i of eigenvector k: by rows in
-// a global slot (the backward kernel) or by columns in LDS (the pre-pass), where the lanes
-// of a wave, one component each, then touch consecutive words.  The arithmetic on it is
-// the same either way.
-struct ZRows {
-  SGQ_G double* p;
-  int K;
-  __device__ SGQ_G double& operator()(int i, int k) const { return p[(size_t)i * K + k]; }
-};
+// A node's K x K eigenvector matrix by columns, Z(i, k) = component i of eigenvector k at
+// p[k K + i]: the lanes of a wave, one component each, read and write one contiguous run
+// per column.  (By rows, each access of a wave touched 64 cache lines, and the pre-pass
+// took twice as long; holding the matrix in LDS allowed a quarter as many nodes in flight
+// and lost to this form at every depth.)
+template <typename Ptr>
 struct ZCols {
-  SGQ_L double* p;
+  Ptr p;
   int K;
-  __device__ SGQ_L double& operator()(int i, int k) const { return p[k * K + i]; }
+  __device__ decltype(auto) operator()(int i, int k) const { return p[(size_t)k * K + i]; }
 };
 
 // Implicit-shift QR of the tridiagonal (a, b) accumulating all eigenvectors in Z.
@@ -584,8 +581,8 @@ struct ZCols {
 // Then each lane applies the sweep's rotations to its rows of Z with the loads of eight
 // columns issued together, so the sweep waits on memory once per eight rotations rather
 // than once per rotation.
-// Z (ZRows or ZCols): Z(i, k) is component i of eigenvector k; each lane owns the
-// components i = lane (mod 64).  rot: 2 (K - 1) doubles of LDS.
+// Z (ZCols): Z(i, k) is component i of eigenvector k; each lane owns the components
+// i = lane (mod 64).  rot: 2 (K - 1) doubles of LDS.
 template <typename ZA>
 __device__ bool tridiag_eig_wave(SGQ_L double* a, SGQ_L double* b, ZA Z, int K,
                                  SGQ_L double* rot) {
@@ -625,16 +622,19 @@ __device__ bool tridiag_eig_wave(SGQ_L double* a, SGQ_L double* b, ZA Z, int K,
     double y = b[l];
     double ak = a[l], bk = b[l];
     // (a[k+1], b[k+1]) of the next rotation are read one rotation ahead; the entries of T
-    // stay far inside the double range, so r = sqrt(x^2 + y^2) needs no scaling
+    // stay far inside the double range, so x^2 + y^2 needs no scaling.  One reciprocal
+    // square root gives c, s and r: the chain's latency is the solve's time, and a square
+    // root followed by a division is about four times as long a dependent sequence
     double ak1 = a[l + 1];
     double bk1 = l + 1 < m ? b[l + 1] : 0.0;
     for (int k = l; k < m; ++k) {
       const double ak1n = k + 2 <= m ? a[k + 2] : 0.0;
       const double bk1n = k + 2 < m ? b[k + 2] : 0.0;
-      const double r = sqrt(x * x + y * y);
-      double c = 1.0, s = 0.0;
-      if (r != 0.0) {
-        const double ir = 1.0 / r;
+      const double r2 = x * x + y * y;
+      double c = 1.0, s = 0.0, r = 0.0;
+      if (r2 != 0.0) {
+        const double ir = rsqrt(r2);
+        r = r2 * ir;
         c = x * ir;
         s = -y * ir;
       }
@@ -750,14 +750,11 @@ __device__ void daleckii_krein(const LaunchParams& P, SGQ_L const double* ta, SG
 // the QR sweeps of different nodes overlap.  Each node's tridiagonal is the one the forward
 // call stored (alpha, beta, K_eff); it serves only when the forward saw these inputs
 // (hash[0] == hash[1]), and the backward kernel takes a node's result only when its own
-// K_eff agrees (tbar_k).  zscratch: 2 K_max^2 doubles per workgroup.  With LDSZ the
-// eigenvectors stay in the workgroup's dynamic LDS (K_max^2 doubles) for all the sweeps and
-// only G goes to zscratch; otherwise both are in zscratch.
-template <bool LDSZ>
+// K_eff agrees (tbar_k).  zscratch: 2 K_max^2 doubles per workgroup, the eigenvectors by
+// columns and then G.
 __global__ __launch_bounds__(kWave) void tbar_kernel(LaunchParams P, double* zscratch,
                                                       size_t zstride, double* tbar,
                                                       int32_t* tbar_k) {
-  extern __shared__ double zdyn_s[];
   __shared__ double ta_s[kBwdMaxDepth], tb_s[kBwdMaxDepth], Fv_s[kBwdMaxDepth], Fd_s[kBwdMaxDepth];
   __shared__ double part_s[4 * kBwdMaxDepth];
   __shared__ double abar_s[kBwdMaxDepth], bbar_s[kBwdMaxDepth];
@@ -792,22 +789,12 @@ __global__ __launch_bounds__(kWave) void tbar_kernel(LaunchParams P, double* zsc
       tb[k] = k + 1 < keff ? tri[kmax + k] : 0.0;
     }
     __syncthreads();
-    const double cscale = 2.0 * P.node_weight[q] * gomega;
-    bool ok;
-    if constexpr (LDSZ) {
-      const ZCols Zl{(SGQ_L double*)zdyn_s, keff};
-      ok = tridiag_eig_wave(ta, tb, Zl, keff, part);
-      __syncthreads();
-      if (ok) daleckii_krein<kWave>(P, ta, Fv, Fd, part, Zl, Z, keff, cscale, abar, bbar);
-    } else {
-      const ZRows Zg{Z, keff};
-      ok = tridiag_eig_wave(ta, tb, Zg, keff, part);
-      __syncthreads();
-      if (ok)
-        daleckii_krein<kWave>(P, ta, Fv, Fd, part, Zg, Z + (size_t)keff * keff, keff, cscale,
-                              abar, bbar);
-    }
+    const ZCols<SGQ_G double*> Zg{Z, keff};
+    const bool ok = tridiag_eig_wave(ta, tb, Zg, keff, part);
+    __syncthreads();
     if (ok) {
+      daleckii_krein<kWave>(P, ta, Fv, Fd, part, Zg, Z + (size_t)keff * keff, keff,
+                            2.0 * P.node_weight[q] * gomega, abar, bbar);
       double* out = tbar + (size_t)q * 2 * kmax;
       for (int k = tid; k < keff; k += kWave) {
         out[k] = abar[k];
@@ -910,12 +897,13 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2, 2))) v
       }
       __syncthreads();
       if (wave == 0) {
-        bool ok = tridiag_eig_wave(st.ta, st.tb, ZRows{Z, keff}, keff, bs.part);
+        bool ok = tridiag_eig_wave(st.ta, st.tb, ZCols<SGQ_G double*>{Z, keff}, keff, bs.part);
         if (!ok && lane == 0) atomicOr(P.status, kStatusNonFinite);
       }
       __syncthreads();
-      daleckii_krein<BLOCK>(P, st.ta, bs.Fv, bs.Fd, bs.part, ZRows{Z, keff}, Z + (size_t)keff * keff,
-                            keff, 2.0 * P.node_weight[q] * gomega, bs.abar, bs.bbar);
+      daleckii_krein<BLOCK>(P, st.ta, bs.Fv, bs.Fd, bs.part, ZCols<SGQ_G double*>{Z, keff},
+                            Z + (size_t)keff * keff, keff, 2.0 * P.node_weight[q] * gomega,
+                            bs.abar, bs.bbar);
     }
     double* dEp = P.dE_part + (size_t)q * kMaxNodeAtoms * 4;
     double* dRp = P.dR_part + (size_t)q * kMaxNodeAtoms * 3;
@@ -1284,33 +1272,10 @@ hipError_t launch_backward(const LaunchParams& P, bool fp64, int grid, int block
   return launch_backward_t<float, 256>(P, grid, kg, s);
 }
 
-// The pre-pass keeps a node's eigenvectors in LDS when K_max^2 doubles beside the kernel's
-// static LDS still let four workgroups share a CU's 160 KiB (K_max <= 60), else in its
-// global slot.  With fewer nodes in flight the latency of the rotation chains decides: at
-// K = 80 (two workgroups per CU) the LDS form took 485 ms for 65536 nodes, the global form
-// 314 ms; at K = 60 the LDS form took 15.1 ms for 8192 nodes, the global form 17.6 ms.
-static size_t tbar_lds_bytes(int kmax) {
-  const size_t z = (size_t)kmax * kmax * 8;
-  return 4 * (z + 10 * 1024 + 256) <= 160 * 1024 ? z : 0;
-}
-
-// Workgroups of the pre-pass per CU: 16 one-wave workgroups, fewer when each holds its
-// eigenvectors in LDS.
-int tbar_workgroups_per_cu(int kmax) {
-  const size_t z = tbar_lds_bytes(kmax);
-  if (z == 0) return 16;
-  return (int)std::max<size_t>(1, std::min<size_t>(16, (160 * 1024) / (z + 10 * 1024 + 256)));
-}
-
 hipError_t launch_tbar(const LaunchParams& P, int grid, double* zscratch, size_t zstride,
                        double* tbar, int32_t* tbar_k, hipStream_t s) {
-  const size_t z = tbar_lds_bytes(P.kmax_out);
-  if (z)
-    hipLaunchKernelGGL(tbar_kernel<true>, dim3(grid), dim3(kWave), z, s, P, zscratch, zstride,
-                       tbar, tbar_k);
-  else
-    hipLaunchKernelGGL(tbar_kernel<false>, dim3(grid), dim3(kWave), 0, s, P, zscratch, zstride,
-                       tbar, tbar_k);
+  hipLaunchKernelGGL(tbar_kernel, dim3(grid), dim3(kWave), 0, s, P, zscratch, zstride, tbar,
+                     tbar_k);
   return hipGetLastError();
 }
 

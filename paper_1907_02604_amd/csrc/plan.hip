@@ -31,7 +31,6 @@ hipError_t launch_fermi_level(const double* tw, const double* weight, int nq, in
                               double* ws, hipStream_t s);
 hipError_t launch_backward(const LaunchParams& P, bool fp64, int grid, int block, int kg,
                            hipStream_t s);
-int tbar_workgroups_per_cu(int kmax);
 bool backward_wide_node(int half_width);
 hipError_t launch_queue_reset(int* queue, hipStream_t s);
 hipError_t launch_tbar(const LaunchParams& P, int grid, double* zscratch, size_t zstride,
@@ -773,10 +772,9 @@ static int ensure_backward(sgq_plan* p) {
   e = e ? e : dalloc(p, &p->d_dRp, (size_t)nq * kMaxNodeAtoms * 3 * 8);
   e = e ? e : dalloc(p, &p->d_dEp, (size_t)nq * kMaxNodeAtoms * 4 * 8);
   e = e ? e : dalloc(p, &p->d_node_atoms, (size_t)nq * (kMaxNodeAtoms + 1) * 4);
-  // the eigensolve pre-pass: one-wave workgroups, as many per CU as their LDS allows, each
-  // with the eigenvectors and weighted divided differences of one node (2 kmax^2 doubles
-  // of global slot), and the per-node results
-  p->grid_pre = std::max(1, std::min(nq, tbar_workgroups_per_cu(p->kmax) * p->ncu));
+  // the eigensolve pre-pass: 16 one-wave workgroups per CU, each with the eigenvectors and
+  // weighted divided differences of one node (2 kmax^2 doubles), and the per-node results
+  p->grid_pre = std::max(1, std::min(nq, 16 * p->ncu));
   p->zpre_stride = 2 * (size_t)p->kmax * p->kmax;
   e = e ? e : dalloc(p, &p->d_zpre, (size_t)p->grid_pre * p->zpre_stride * 8);
   e = e ? e : dalloc(p, &p->d_tbar, (size_t)nq * 2 * p->kmax * 8);

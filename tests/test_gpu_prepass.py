@@ -47,9 +47,8 @@ def _backward(plan, P, v, R, E, w, forward_first):
 def test_prepass_gives_the_in_place_solve_bit_for_bit(cfg, precision):
     """A forward then a backward (pre-pass over the forward's tridiagonals) against a
     backward alone (eigensolves in place), both with the default 256-lane forward: same
-    bits.  K = 60 (differentiation workload) takes the pre-pass form with the eigenvectors
-    in LDS, K = 80 (dislocation workload, cubes of 25^3..33^3) the form with them in global
-    memory; the in-place solve keeps them in global memory."""
+    bits, at K = 60 (differentiation workload) and K = 80 (dislocation workload, cubes of
+    25^3..33^3)."""
     from paper_1907_02604_amd import sgq
     P = _problem(precision, n=40 if cfg == 4 else 12, cfg=cfg)
     v, R, E, w = sgq.device_inputs(P)
