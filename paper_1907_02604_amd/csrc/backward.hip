@@ -1113,41 +1113,77 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2, 2))) v
   }
 }
 
-// dV(x) = sum over the nodes whose cube contains x of P_q(x), in ascending node order.
-// One workgroup per 8^3 cell of the grid; cell_nodes lists the nodes meeting each cell.
+// dV(x) = sum over the nodes whose cube contains x of P_q(x).  One workgroup per 8^3 cell
+// of the grid; cell_nodes lists the nodes meeting each cell in ascending order.  Wave w of
+// the eight takes the nodes w, w + 8, ... of the cell's list, in that order, and each lane
+// adds the eight points of one column of the cell (x = lane % 8, y = lane / 8, every z)
+// per node, four nodes' loads at a time: where one lane per point and the whole workgroup
+// on each node made the loop one chain of dependent loads per node.  The eight partial
+// sums are added in wave order, so dV is reproducible bit for bit.
 template <typename T>
 __global__ __launch_bounds__(512) void gather_dv_kernel(LaunchParams P, const int32_t* cell_start,
                                                       const int32_t* cell_nodes, double* dV) {
-  const int C = kGatherCell;
+  constexpr int C = kGatherCell;
+  constexpr int NW = 512 / kWave;
+  static_assert(C * C == kWave && C == NW, "a lane per column of the cell, a wave per eighth");
+  __shared__ double part_s[NW][C * C * C];
   const int ncx = (P.nx + C - 1) / C, ncy = (P.ny + C - 1) / C;
   const int cell = blockIdx.x;
   const int cx = cell % ncx, cy = (cell / ncx) % ncy, cz = cell / (ncx * ncy);
-  const int x = cx * C + (threadIdx.x % C);
-  const int y = cy * C + (threadIdx.x / C) % C;
-  const int z = cz * C + threadIdx.x / (C * C);
-  const bool inside = x < P.nx && y < P.ny && z < P.nz;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int x = cx * C + lane % C, y = cy * C + lane / C, z0 = cz * C;
+  const bool col = x < P.nx && y < P.ny;
   const SGQ_G T* Pc = (const SGQ_G T*)P.P_cube;
-  double acc = 0.0;
+  double acc[C];
+#pragma unroll
+  for (int k = 0; k < C; ++k) acc[k] = 0.0;
+  // the loads of U nodes are issued together and their values added in list order
+  constexpr int U = 4;
   const int e0 = cell_start[cell], e1 = cell_start[cell + 1];
-  for (int e = e0; e < e1; ++e) {
-    const int q = cell_nodes[e];
-    const int R = P.half_width[q];
-    const int c = P.center[q];
-    int lx, ly, lz, s;
-    if (R < 0) {
-      lx = x; ly = y; lz = z;
-      if (!inside) continue;
-      acc += (double)Pc[P.cube_offset[q] + lx + P.nx * (ly + P.ny * lz)];
-      continue;
+  for (int e = e0 + wave; e < e1; e += U * NW) {
+    T v[U][C];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int eu = e + u * NW;
+      const int q = cell_nodes[eu < e1 ? eu : e];
+      const int R = P.half_width[q];
+      const SGQ_G T* Pq = Pc + P.cube_offset[q];
+      const int c = P.center[q];
+      const int s = 2 * R + 1;
+      const int lx = wrap_index(x - (c % P.nx - R), P.nx);
+      const int ly = wrap_index(y - ((c / P.nx) % P.ny - R), P.ny);
+      const int lz0 = wrap_index(z0 - (c / (P.nx * P.ny) - R), P.nz);   // cube plane of z0
+      const bool live = eu < e1 && col;
+      const bool in = live && lx < s && ly < s;
+      const SGQ_G T* rq = Pq + lx + s * ly;
+#pragma unroll
+      for (int k = 0; k < C; ++k) {
+        const int z = z0 + k;
+        if (R < 0) {   // the whole periodic grid
+          v[u][k] = live && z < P.nz ? Pq[x + P.nx * (y + P.ny * z)] : (T)0;
+        } else {
+          const int lz = lz0 + k < P.nz ? lz0 + k : lz0 + k - P.nz;
+          v[u][k] = in && z < P.nz && lz < s ? rq[(size_t)s * s * lz] : (T)0;
+        }
+      }
     }
-    s = 2 * R + 1;
-    lx = wrap_index(x - (c % P.nx - R), P.nx);
-    ly = wrap_index(y - ((c / P.nx) % P.ny - R), P.ny);
-    lz = wrap_index(z - (c / (P.nx * P.ny) - R), P.nz);
-    if (inside && lx < s && ly < s && lz < s)
-      acc += (double)Pc[P.cube_offset[q] + lx + s * (ly + s * lz)];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int k = 0; k < C; ++k) acc[k] += (double)v[u][k];
   }
-  if (inside) dV[x + P.nx * (y + P.ny * z)] = acc;
+  SGQ_L double(*part)[C * C * C] = (SGQ_L double(*)[C * C * C])part_s;
+#pragma unroll
+  for (int k = 0; k < C; ++k) part[wave][lane + kWave * k] = acc[k];
+  __syncthreads();
+  const int t = threadIdx.x;
+  const int px = cx * C + t % C, py = cy * C + (t / C) % C, pz = z0 + t / (C * C);
+  if (px < P.nx && py < P.ny && pz < P.nz) {
+    double sum = 0.0;
+    for (int w = 0; w < NW; ++w) sum += part[w][t];
+    dV[px + P.nx * (py + P.ny * pz)] = sum;
+  }
 }
 
 // dE[J], dR_nl[J]: sum over nodes (ascending) of the node partials of atom J, found by
