@@ -2,7 +2,9 @@
 // the total-energy expression, weighted as in the coarse-grained energy sum), with
 // respect to the local potential, the projector energies and the atom positions.
 //
-// Per node (one workgroup, persistent queue as in the forward kernel):
+// Per node (one workgroup, persistent queue as in the forward kernel; FP32 cubes of 37 to
+// 49 points in a 512-lane launch, whose plane march takes planes that wide, then every
+// other node in a 256-lane launch):
 //   1. the forward Lanczos run is recomputed from the start vector, keeping every
 //      u_j = H q_j; or, when the forward call retained the node's basis and u_j rows
 //      (sgq_plan_set_retain, for all nodes or the costliest ones within a byte limit),
