@@ -579,18 +579,77 @@ struct ZCols {
 // Run by one whole wave.  Each sweep first forms its chain of Givens rotations: every lane
 // computes the same rotations from the LDS copies of a and b, carrying the entries the
 // previous rotation changed in registers (a rotation reads only entries no earlier one of
-// the sweep has written), lane 0 writes the results back and the (c, s) pairs to rot.
-// Then each lane applies the sweep's rotations to its rows of Z with the loads of eight
-// columns issued together, so the sweep waits on memory once per eight rotations rather
-// than once per rotation.
+// the sweep has written), and lane 0 writes the results back and the (c, s) pairs to rot.
+// The rotations of up to four consecutive sweeps are then applied to Z in one pass over
+// the columns: rotation k of a sweep needs only rotations k and k+1 of the sweep before it
+// done, so at column position p sweep s of the batch applies its rotation p - s.  Each
+// entry of Z gets the same operations in the same order as with one pass per sweep, with
+// a batch's worth fewer reads and writes of Z.
 // Z (ZCols): Z(i, k) is component i of eigenvector k; each lane owns the components
-// i = lane (mod 64).  rot: 2 (K - 1) doubles of LDS.
+// i = lane (mod 64).  rot: 4 kBwdMaxDepth doubles of LDS, the (c, s) pairs of the batch.
 template <typename ZA>
 __device__ bool tridiag_eig_wave(SGQ_L double* a, SGQ_L double* b, ZA Z, int K,
                                  SGQ_L double* rot) {
+  constexpr int kBatch = 4;   // most sweeps per pass over Z
   const int lane = threadIdx.x & (kWave - 1);
   for (int i = lane; i < K; i += kWave)
     for (int k = 0; k < K; ++k) Z(i, k) = (i == k) ? 1.0 : 0.0;
+  // sweeps per pass: as many chains of 2 (K - 1) values as rot holds
+  const int rs = 2 * (K > 1 ? K - 1 : 1);
+  const int S = min(kBatch, (4 * kBwdMaxDepth) / rs);
+  int ns = 0;                          // sweeps formed and not yet applied
+  int wl[kBatch], wm[kBatch];          // their rotation windows [l, m)
+#pragma unroll
+  for (int t = 0; t < kBatch; ++t) wl[t] = wm[t] = 0;
+  // applies the ns formed sweeps: column positions p = L .. M + 3, where sweep t applies
+  // its rotation p - t to columns (p - t, p - t + 1); v[j] holds column p - 3 + j
+  auto apply = [&]() {
+    int L = wl[0], M = wm[0];
+#pragma unroll
+    for (int t = 1; t < kBatch; ++t)
+      if (t < ns) {
+        L = min(L, wl[t]);
+        M = max(M, wm[t]);
+      }
+    for (int i = lane; i < K; i += kWave) {
+      double v[kBatch + 1];
+#pragma unroll
+      for (int j = 0; j < kBatch + 1; ++j) v[j] = 0.0;
+      v[kBatch - 1] = Z(i, L);
+      for (int p0 = L; p0 <= M + kBatch - 1; p0 += 8) {
+        // the new columns of eight positions are loaded together
+        double u[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) u[t] = p0 + t + 1 <= M ? Z(i, p0 + t + 1) : 0.0;
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+          const int p = p0 + t;
+          if (p <= M + kBatch - 1) {
+            v[kBatch] = u[t];
+#pragma unroll
+            for (int q = 0; q < kBatch; ++q) {
+              const int k = p - q;
+              if (q < ns && k >= wl[q] && k < wm[q]) {
+                const SGQ_L double* rq = rot + q * rs + 2 * (k - wl[q]);
+                const double c = rq[0], s = rq[1];
+                const double u0 = v[kBatch - 1 - q], u1 = v[kBatch - q];
+                v[kBatch - 1 - q] = c * u0 - s * u1;
+                v[kBatch - q] = s * u0 + c * u1;
+              }
+            }
+            const int done = p - (kBatch - 1);
+            if (done >= L && done <= M) Z(i, done) = v[0];
+#pragma unroll
+            for (int j = 0; j < kBatch; ++j) v[j] = v[j + 1];
+          }
+        }
+      }
+    }
+    // rot is rewritten by the next batch only after every lane has read it
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    ns = 0;
+  };
   const double eps = 2.220446049250313e-16;
   int m = K - 1;
   int sweeps = 0;
@@ -629,6 +688,7 @@ __device__ bool tridiag_eig_wave(SGQ_L double* a, SGQ_L double* b, ZA Z, int K,
     // root followed by a division is about four times as long a dependent sequence
     double ak1 = a[l + 1];
     double bk1 = l + 1 < m ? b[l + 1] : 0.0;
+    SGQ_L double* rw = rot + ns * rs;
     for (int k = l; k < m; ++k) {
       const double ak1n = k + 2 <= m ? a[k + 2] : 0.0;
       const double bk1n = k + 2 < m ? b[k + 2] : 0.0;
@@ -647,8 +707,8 @@ __device__ bool tridiag_eig_wave(SGQ_L double* a, SGQ_L double* b, ZA Z, int K,
         if (k > l) b[k - 1] = r;
         a[k] = nak;
         b[k] = nbk;
-        rot[2 * (k - l)] = c;
-        rot[2 * (k - l) + 1] = s;
+        rw[2 * (k - l)] = c;
+        rw[2 * (k - l) + 1] = s;
       }
       x = nbk;
       y = -s * bk1;      // the bulge
@@ -660,29 +720,15 @@ __device__ bool tridiag_eig_wave(SGQ_L double* a, SGQ_L double* b, ZA Z, int K,
     if (lane == 0) a[m] = ak;
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
-    // the rotations on the rows of Z: column k+1's old value is loaded before rotation k
-    // writes column k, and its new value is carried to rotation k+1
-    for (int i = lane; i < K; i += kWave) {
-      double u0 = Z(i, l);
-      for (int k0 = l; k0 < m; k0 += 8) {
-        double u1[8];
 #pragma unroll
-        for (int t = 0; t < 8; ++t) u1[t] = k0 + t < m ? Z(i, k0 + t + 1) : 0.0;
-#pragma unroll
-        for (int t = 0; t < 8; ++t) {
-          if (k0 + t < m) {
-            const double c = rot[2 * (k0 + t - l)], s = rot[2 * (k0 + t - l) + 1];
-            Z(i, k0 + t) = c * u0 - s * u1[t];
-            u0 = s * u0 + c * u1[t];
-          }
-        }
+    for (int t = 0; t < kBatch; ++t)
+      if (t == ns) {
+        wl[t] = l;
+        wm[t] = m;
       }
-      Z(i, m) = u0;
-    }
-    // rot is rewritten by the next sweep only after every lane has read it
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
+    if (++ns == S) apply();
   }
+  if (ns > 0) apply();
   return true;
 }
 
@@ -754,7 +800,7 @@ __device__ void daleckii_krein(const LaunchParams& P, SGQ_L const double* ta, SG
 // (hash[0] == hash[1]), and the backward kernel takes a node's result only when its own
 // K_eff agrees (tbar_k).  zscratch: 2 K_max^2 doubles per workgroup, the eigenvectors by
 // columns and then G.
-__global__ __launch_bounds__(kWave) void tbar_kernel(LaunchParams P, double* zscratch,
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(4))) void tbar_kernel(LaunchParams P, double* zscratch,
                                                       size_t zstride, double* tbar,
                                                       int32_t* tbar_k) {
   __shared__ double ta_s[kBwdMaxDepth], tb_s[kBwdMaxDepth], Fv_s[kBwdMaxDepth], Fd_s[kBwdMaxDepth];
