@@ -305,6 +305,32 @@ def test_wide_planes_take_the_512_lane_launch(monkeypatch):
         assert np.array_equal(a, b), name
 
 
+@pytest.mark.parametrize("case", ["cube51", "periodic"])
+def test_fp32_nodes_off_the_plane_march(case):
+    """FP32 nodes that no plane march takes, reversed with separate dot, update and operator
+    passes in the 256-lane launch: two 51^3 cubes (wider than the 512-lane march's 49-point
+    planes) on a 60^3 grid with 24 projector atoms, or two untruncated nodes of a 16^3
+    periodic grid with 4.  Every adjoint output within 1e-4 of the oracle gradient."""
+    import dataclasses
+    rng = np.random.default_rng(3)
+    N, h = (60, 0.5) if case == "cube51" else (16, 0.5)
+    na = 24 if case == "cube51" else 4
+    atoms = rng.uniform(0, N * h, size=(na, 3))
+    E = rng.uniform(-1, 1, size=(na, 4))
+    centers = ([lin(30, 30, 30, N), lin(5, 50, 12, N)] if case == "cube51"
+               else [lin(3, 4, 5, N), lin(10, 2, 7, N)])
+    P = custom_problem(N, h=h, atoms=atoms, proj_E=E, v_loc=synth.gaussian_vloc((N,) * 3, h, atoms),
+                       centers=centers, half_width=25 if case == "cube51" else -1,
+                       depth=16 if case == "cube51" else 14, mu=-0.3, kT=0.05)
+    P = dataclasses.replace(P, precision="f32")
+    rdV, rdE, rdR = O.band_energy_backward(P, kind=O.FREE)
+    announce(f"fp32 off the march: {case}")
+    dV, dR, dE = _gpu_grad(P, O.FREE, "f32")
+    errs = _rel(dV, rdV), _rel(dR, rdR), _rel(dE, rdE)
+    print("off-march grad errs", case, errs)
+    assert max(errs) < 1e-4
+
+
 def _gpu_grad_on(plan, P, inputs=None):
     """(dV, dR, dE) on host through an existing plan, on the given device inputs (the ones a
     forward saw, for its retained rows) or fresh copies."""
