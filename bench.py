@@ -33,7 +33,7 @@ HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ("sgq_common.h", "tridiag.h", "lanczos_device.h", "forward.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_lanczos_forward_64grid_8192nodes.txt")
 LEGS = ("copy", "fermi", "cluster", "fe", "plain", "c1", "c3", "c4", "c5")
-# host cores a one-GPU machine grants a job, whatever the machine has
+# host cores granted to a job per GPU on the target nodes, whatever nproc reports
 HOST_CORE_SHARE = 16
 
 
