@@ -179,12 +179,32 @@ __device__ __noinline__ void projector_gradients(const SGQ_G double* proj_E,
 // values of its NA atoms and their seven partials (one per lane) together, so the step
 // waits on memory once per NA atoms; the totals and the step's terms pass through the
 // wave's 64 doubles of wsb (LDS).
+// The rows, coefficients and outputs of ubar_coefs.
+template <typename T>
+struct UbarArgs {
+  const SGQ_G double* proj_E;
+  const SGQ_G T* Q0;
+  const SGQ_G T* Wc;
+  double* dEp;
+  double* dRp;
+  double sc, ib, bb, ahat, h3;
+  int wbs, B, B3, last;
+};
+
 template <typename T, int BLOCK>
-__device__ __noinline__ void ubar_coefs(const SGQ_G double* proj_E, SGQ_L NodeState<T, BLOCK>& st,
-                                        ProjEval<T> pe, const SGQ_G T* Q0, const SGQ_G T* Wc,
-                                        int wbs, double sc, double ib, double bb, double ahat,
-                                        bool last, double h3, int B, int B3, SGQ_L T (*cq)[16],
-                                        double* dEp, double* dRp, SGQ_L double* wsb) {
+__device__ __noinline__ void ubar_coefs(SGQ_L NodeState<T, BLOCK>& st, ProjEval<T> pe,
+                                        SGQ_L T (*cq)[16], SGQ_L double* wsb, UbarArgs<T> U) {
+  // the arguments as one by-value aggregate: scalar arguments beyond the registers the
+  // calling convention passes them in changed the register allocation to one that saved
+  // four times as many registers through scratch on every call
+  const SGQ_G double* proj_E = U.proj_E;
+  const SGQ_G T* Q0 = U.Q0;
+  const SGQ_G T* Wc = U.Wc;
+  const int wbs = U.wbs, B = U.B, B3 = U.B3;
+  const double sc = U.sc, ib = U.ib, bb = U.bb, ahat = U.ahat, h3 = U.h3;
+  const bool last = U.last;
+  double* dEp = U.dEp;
+  double* dRp = U.dRp;
   constexpr int NW = BLOCK / kWave;
   constexpr int UNR = 6;    // 6 x 64 box points cover the 7^3 box of h = rc/3
   constexpr int NA = 3;     // atoms whose box values are requested together
@@ -365,33 +385,51 @@ __device__ __forceinline__ X to_sgpr(X v) {
 // qbar_j . q_{j-2}, q_j . q_{j-1}, q_j . q_{j-2}) into st.red.  Per step this reads nine rows
 // and writes three, against ten reads and seven writes for separate dot, update and
 // operator passes.  Plane order, ring lengths and the LDS plane as in stencil_march.
+// What reverse_march needs of the caller besides the node state: the rows of the step and
+// its index (the coefficients are read from the node state and the adjoint scalars in LDS).
+template <typename T>
+struct RevArgs {
+  const SGQ_G T* Q0;
+  const SGQ_G T* Wq;    // the basis (row j at Wq + 64 j, block stride wbs)
+  const SGQ_G T* Uj;
+  SGQ_G T* Q1;
+  SGQ_G T* Q2;
+  SGQ_G T* Pq;
+  int j, keff, wbs;
+};
+
 template <typename T, int BLOCK, int PPT>
 __device__ __noinline__ void reverse_march(int gnx, int gny, int gnz, SGQ_L NodeState<T, BLOCK>& st,
                                            const SGQ_G T* __restrict__ V, T kin, ProjEval<T> pe,
-                                           int B, RevStep<T> Sv) {
+                                           int B, const SGQ_L double* sc3, RevArgs<T> A) {
+  // the step's coefficients and basis rows are formed here from the step index, the node
+  // state and the adjoint scalars (a by-value descriptor of all of them cost 160 bytes of
+  // each lane's scratch memory per step)
   RevStep<T> S;
-  S.Q0 = to_sgpr(Sv.Q0);
-  S.Wn = to_sgpr(Sv.Wn);
-  S.Wc = to_sgpr(Sv.Wc);
-  S.Wp = to_sgpr(Sv.Wp);
-  S.Wpp = to_sgpr(Sv.Wpp);
-  S.Uj = to_sgpr(Sv.Uj);
-  S.Q1 = to_sgpr(Sv.Q1);
-  S.Q2 = to_sgpr(Sv.Q2);
-  S.Pq = to_sgpr(Sv.Pq);
-  S.ib = to_sgpr(Sv.ib);
-  S.bb = to_sgpr(Sv.bb);
-  S.ahat = to_sgpr(Sv.ahat);
-  S.al = to_sgpr(Sv.al);
-  S.bprev = to_sgpr(Sv.bprev);
-  S.sn = to_sgpr(Sv.sn);
-  S.sc = to_sgpr(Sv.sc);
-  S.sp = to_sgpr(Sv.sp);
-  S.spp = to_sgpr(Sv.spp);
-  S.wbs = to_sgpr(Sv.wbs);
-  S.last = to_sgpr(Sv.last);
-  S.prev = to_sgpr(Sv.prev);
-  S.ldq1 = to_sgpr(Sv.ldq1);
+  const int jj = to_sgpr(A.j), ke = to_sgpr(A.keff);
+  const SGQ_G T* Wb = to_sgpr(A.Wq);
+  S.last = jj == ke - 1;
+  S.prev = jj > 0;
+  S.Q0 = to_sgpr(A.Q0);
+  S.Wn = Wb + 64 * (S.last ? jj : jj + 1);     // (row j+1 does not exist on the last step)
+  S.Wc = Wb + 64 * jj;
+  S.Wp = Wb + 64 * (jj >= 1 ? jj - 1 : 0);
+  S.Wpp = Wb + 64 * (jj >= 2 ? jj - 2 : 0);
+  S.Uj = to_sgpr(A.Uj);
+  S.Q1 = to_sgpr(A.Q1);
+  S.Q2 = to_sgpr(A.Q2);
+  S.Pq = to_sgpr(A.Pq);
+  S.ib = to_sgpr(sc3[0]);
+  S.bb = to_sgpr(sc3[1]);
+  S.ahat = to_sgpr(sc3[2]);
+  S.al = to_sgpr(st.alpha[jj]);
+  S.bprev = jj > 0 ? to_sgpr(st.beta[jj - 1]) : 0.0;
+  S.sn = (jj + 1 < ke) ? to_sgpr(st.scale[jj + 1]) : 0.0;
+  S.sc = to_sgpr(st.scale[jj]);
+  S.sp = jj >= 1 ? to_sgpr(st.scale[jj - 1]) : 0.0;
+  S.spp = jj >= 2 ? to_sgpr(st.scale[jj - 2]) : 0.0;
+  S.wbs = to_sgpr(A.wbs);
+  S.ldq1 = !S.last || st.natoms > st.ngrp;
   constexpr int NQ = 8;    // ring of ubar planes z-3 .. z+4 (z+4 arrives after plane z)
   constexpr int LEAD = 4;  // plane z+LEAD is loaded while plane z is computed
   const int sx = st.sx, sy = st.sy, sz = st.sz, sxy = sx * sy;
@@ -890,7 +928,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2, 2))) v
   for (;;) {
     if (tid == 0) st.node = atomicAdd(P.queue, 1);
     __syncthreads();
-    const int qi = st.node;
+    // node-level values are wave-uniform: in scalar registers they cost no vector registers
+    // to keep across the step calls (where vector registers are saved through scratch)
+    const int qi = to_sgpr(st.node);
     if (qi >= P.n_nodes) break;
     const int q = P.order[qi];
     node_setup<T, BLOCK>(P, st, q);
@@ -902,7 +942,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2, 2))) v
       __syncthreads();
       continue;
     }
-    const int n = st.n, natoms = st.natoms;
+    const int n = to_sgpr(st.n), natoms = to_sgpr(st.natoms);
     // the node's basis and u_j rows: retained by the forward call, or recomputed here
     SGQ_G T* __restrict__ Wq = W;
     SGQ_G T* __restrict__ Uq = Ubase;
@@ -926,7 +966,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2, 2))) v
       if (tid == 0) st.scale[0] = 1.0;
       __syncthreads();
     } else {
-      keff = run_lanczos<T, BLOCK, KG>(P, st, W, Ubase, npad, P.depth[q]);
+      keff = to_sgpr(run_lanczos<T, BLOCK, KG>(P, st, W, Ubase, npad, P.depth[q]));
     }
     // ---- eigenvectors of T and the Daleckii-Krein adjoint: from the pre-pass when it
     // solved this node's tridiagonal (the forward's, for these inputs and this K_eff), else
@@ -1011,8 +1051,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2, 2))) v
           S.prev = j > 0;
           S.ldq1 = !last || natoms > st.ngrp;
           if (natoms > 0) {
-            ubar_coefs<T, BLOCK>(proj_E, st, pe, S.Q0, S.Wc, wbs, S.sc, S.ib, S.bb, S.ahat, last,
-                                 h3, B, B3, cq, dEp, dRp, bs.part);
+            ubar_coefs<T, BLOCK>(st, pe, cq, bs.part,
+                                 UbarArgs<T>{proj_E, S.Q0, S.Wc, dEp, dRp, S.sc, S.ib, S.bb,
+                                             S.ahat, h3, wbs, B, B3, (int)last});
             __syncthreads();
             if (natoms > st.ngrp) {
               // the atoms outside the group are added to qbar_j before the march
@@ -1023,7 +1064,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2, 2))) v
               apply_scatter<T, BLOCK>(P, st, pe, S.Q1, B, B3, false);
             }
           }
-          reverse_march<T, BLOCK, 5>(P.nx, P.ny, P.nz, st, V, kin, pe, B, S);
+          reverse_march<T, BLOCK, 5>(P.nx, P.ny, P.nz, st, V, kin, pe, B, bs.sc,
+                                     RevArgs<T>{S.Q0, Wq, S.Uj, S.Q1, S.Q2, S.Pq, j, keff, wbs});
           __syncthreads();
           const int t0 = r0;
           r0 = r1;
