@@ -905,22 +905,24 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2, 2))) v
   SGQ_L NodeState<T, BLOCK>& st = *(SGQ_L NodeState<T, BLOCK>*)(&st_shared);
   SGQ_L BwdState& bs = *(SGQ_L BwdState*)(&bs_shared);
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
-  const size_t npad = P.npad;
-  const int kmax = P.kmax_out;
-  const int wbs = P.wbs;
-  SGQ_G T* __restrict__ W = (SGQ_G T*)P.W + (size_t)blockIdx.x * P.slot_stride;
-  SGQ_G T* __restrict__ Ubase = W + (size_t)kmax * npad;
+  // (the kernel-wide values in scalar registers, where the step calls do not make the
+  // kernel save them through scratch)
+  const size_t npad = to_sgpr(P.npad);
+  const int kmax = to_sgpr(P.kmax_out);
+  const int wbs = to_sgpr(P.wbs);
+  SGQ_G T* __restrict__ W = to_sgpr((SGQ_G T*)P.W + (size_t)blockIdx.x * P.slot_stride);
+  SGQ_G T* __restrict__ Ubase = to_sgpr(W + (size_t)kmax * npad);
   SGQ_G double* __restrict__ Z =
-      (SGQ_G double*)P.zbuf + (size_t)blockIdx.x * kBwdSlotDoubles;
+      to_sgpr((SGQ_G double*)P.zbuf + (size_t)blockIdx.x * kBwdSlotDoubles);
   SGQ_G T* __restrict__ R[3] = {Ubase + (size_t)kmax * npad, Ubase + (size_t)(kmax + 1) * npad,
                                 Ubase + (size_t)(kmax + 2) * npad};
-  const SGQ_G T* __restrict__ V = (const SGQ_G T*)P.v;
-  const ProjEval<T> pe = proj_eval<T>(P);
-  const SGQ_G double* proj_E = (const SGQ_G double*)P.proj_E;
-  const double h = P.h, h3 = h * h * h;
+  const SGQ_G T* __restrict__ V = to_sgpr((const SGQ_G T*)P.v);
+  const ProjEval<T> pe = to_sgpr(proj_eval<T>(P));
+  const SGQ_G double* proj_E = to_sgpr((const SGQ_G double*)P.proj_E);
+  const double h = to_sgpr(P.h), h3 = h * h * h;
   const T kin = (T)(-0.5 / (h * h));
-  const int B = 2 * P.box_m + 1, B3 = B * B * B;
-  const double gomega = *P.grad_omega;
+  const int B = to_sgpr(2 * P.box_m + 1), B3 = B * B * B;
+  const double gomega = to_sgpr(*P.grad_omega);
   constexpr int VW = 16 / (int)sizeof(T);                    // points per 16-byte access
   typedef T VT __attribute__((ext_vector_type(VW)));
   if (tid == 0) st.orth_tol = sizeof(T) == 4 ? 3.4526698300124393e-4 : 1.4901161193847656e-8;
@@ -993,8 +995,10 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2, 2))) v
                             Z + (size_t)keff * keff, keff, 2.0 * P.node_weight[q] * gomega,
                             bs.abar, bs.bbar);
     }
-    double* dEp = P.dE_part + (size_t)q * kMaxNodeAtoms * 4;
-    double* dRp = P.dR_part + (size_t)q * kMaxNodeAtoms * 3;
+    double* dEp = to_sgpr(P.dE_part + (size_t)q * kMaxNodeAtoms * 4);
+    double* dRp = to_sgpr(P.dR_part + (size_t)q * kMaxNodeAtoms * 3);
+    Wq = to_sgpr(Wq);
+    Uq = to_sgpr(Uq);
     // ---- reverse recurrence: one fused march per step where the node's stencil is the
     // FP32 plane march and its projector group is added inside it; otherwise separate
     // dot, update and operator passes
@@ -1028,15 +1032,17 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2, 2))) v
           }
           __syncthreads();
           RevStep<T> S;
-          S.Q0 = R[r0];
+          // (the qbar rows by their index: R[r] with r varying would be a select the
+          // compiler keeps in vector registers)
+          S.Q0 = to_sgpr(Ubase + (size_t)(kmax + r0) * npad);
           S.Wn = Wq + 64 * (last ? j : j + 1);     // (row j+1 does not exist on the last step)
           S.Wc = Wq + 64 * j;
           S.Wp = Wq + 64 * (j >= 1 ? j - 1 : 0);
           S.Wpp = Wq + 64 * (j >= 2 ? j - 2 : 0);
           S.Uj = Uq + (size_t)j * npad;
-          S.Q1 = R[r1];
-          S.Q2 = R[r2];
-          S.Pq = Pq;
+          S.Q1 = to_sgpr(Ubase + (size_t)(kmax + r1) * npad);
+          S.Q2 = to_sgpr(Ubase + (size_t)(kmax + r2) * npad);
+          S.Pq = to_sgpr(Pq);
           S.ib = bs.sc[0];
           S.bb = bs.sc[1];
           S.ahat = bs.sc[2];
