@@ -914,8 +914,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2, 2))) v
   SGQ_G T* __restrict__ Ubase = to_sgpr(W + (size_t)kmax * npad);
   SGQ_G double* __restrict__ Z =
       to_sgpr((SGQ_G double*)P.zbuf + (size_t)blockIdx.x * kBwdSlotDoubles);
-  SGQ_G T* __restrict__ R[3] = {Ubase + (size_t)kmax * npad, Ubase + (size_t)(kmax + 1) * npad,
-                                Ubase + (size_t)(kmax + 2) * npad};
+  // the three qbar rows follow the kmax u_j rows of the slot: row r at
+  // Ubase + (kmax + r) npad
   const SGQ_G T* __restrict__ V = to_sgpr((const SGQ_G T*)P.v);
   const ProjEval<T> pe = to_sgpr(proj_eval<T>(P));
   const SGQ_G double* proj_E = to_sgpr((const SGQ_G double*)P.proj_E);
@@ -1087,9 +1087,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2, 2))) v
       const SGQ_G T* Wn = Wq + 64 * (j + 1);
       const SGQ_G T* Wp = Wq + 64 * (j > 0 ? j - 1 : 0);
       SGQ_G T* Uj = Uq + (size_t)j * npad;      // u_j, replaced by ubar_j in pass B
-      SGQ_G T* Q0 = R[r0];
-      SGQ_G T* Q1 = R[r1];
-      SGQ_G T* Q2 = R[r2];
+      SGQ_G T* Q0 = to_sgpr(Ubase + (size_t)(kmax + r0) * npad);
+      SGQ_G T* Q1 = to_sgpr(Ubase + (size_t)(kmax + r1) * npad);
+      SGQ_G T* Q2 = to_sgpr(Ubase + (size_t)(kmax + r2) * npad);
       const double sc_ = st.scale[j];
       const double sn = (j + 1 < keff) ? st.scale[j + 1] : 0.0;
       const double sp = j > 0 ? st.scale[j - 1] : 0.0;
