@@ -42,6 +42,7 @@ struct sgq_fe_mesh {
   int32_t bucket = 4, nb[3] = {1, 1, 1};
   int4* d_esp = nullptr;       // (x, y, z, linear index) per ESP
   uint2* d_xyz = nullptr;      // (x | y << 16, z) per ESP
+  int32_t* d_lin = nullptr;    // linear fine-grid index per ESP
   int4* d_tet = nullptr;       // positively oriented vertex ids, caller's numbering
   int32_t* d_bstart = nullptr; // bucket CSR offsets
   int32_t* d_blist = nullptr;  // tetrahedron ids per bucket, ascending
@@ -126,17 +127,28 @@ __global__ __launch_bounds__(kFeBlock) void fe_locate_kernel(
   }
 }
 
-// fc_q = f_q - f0(r_q) for every field and ESP, stored ESP-major (the fields of one ESP
-// are adjacent, so the reconstruction fetches them with one load).
+// fc_q = f_q - f0(r_q) for every field, one ESP per lane: the ESP's fine-grid index is read
+// once for all F fields (from its own packed array), and its correctors are stored ESP-major
+// in one contiguous write (the fields of one ESP are adjacent, so the reconstruction fetches
+// them with one load).  f_q comes field-major, [F][n_esp].
+template <int F>
 __global__ __launch_bounds__(kFeBlock) void fe_corrector_kernel(
-    const int4* __restrict__ esp, int n_esp, int n_fields, int64_t npts,
+    const int32_t* __restrict__ lin, int n_esp, int64_t npts,
     const double* __restrict__ esp_values, const double* __restrict__ predictor,
     double* __restrict__ corr) {
-  const int64_t total = (int64_t)n_esp * n_fields;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const int f = (int)(i / n_esp), q = (int)(i % n_esp);
-    corr[(int64_t)q * n_fields + f] = esp_values[i] - predictor[f * npts + esp[q].w];
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n_esp; q += gridDim.x * blockDim.x) {
+    const int64_t p = lin[q];
+    double c[F];
+#pragma unroll
+    for (int f = 0; f < F; ++f) c[f] = esp_values[(int64_t)f * n_esp + q] - predictor[f * npts + p];
+    double* b = corr + (int64_t)q * F;
+    if constexpr (F == 2 || F == 4) {
+#pragma unroll
+      for (int h = 0; h < F / 2; ++h) reinterpret_cast<double2*>(b)[h] = make_double2(c[2 * h], c[2 * h + 1]);
+    } else {
+#pragma unroll
+      for (int f = 0; f < F; ++f) b[f] = c[f];
+    }
   }
 }
 
@@ -237,6 +249,7 @@ int fe_grid(int64_t work) {
 void free_mesh(sgq_fe_mesh* m) {
   (void)hipFree(m->d_esp);
   (void)hipFree(m->d_xyz);
+  (void)hipFree(m->d_lin);
   (void)hipFree(m->d_tet);
   (void)hipFree(m->d_bstart);
   (void)hipFree(m->d_blist);
@@ -289,6 +302,7 @@ extern "C" int sgq_fe_mesh_create(const int32_t n[3], const int64_t* esp_center,
   FE_HIP(hipGetDevice(&m->device));
   FE_HIP(hipMalloc(&m->d_esp, sizeof(int4) * n_esp));
   FE_HIP(hipMalloc(&m->d_xyz, sizeof(uint2) * n_esp));
+  FE_HIP(hipMalloc(&m->d_lin, sizeof(int32_t) * n_esp));
   FE_HIP(hipMalloc(&m->d_tet, sizeof(int4) * ntet));
   FE_HIP(hipMalloc(&m->d_bstart, sizeof(int32_t) * bstart.size()));
   FE_HIP(hipMalloc(&m->d_blist, sizeof(int32_t) * blist.size()));
@@ -296,11 +310,14 @@ extern "C" int sgq_fe_mesh_create(const int32_t n[3], const int64_t* esp_center,
   FE_HIP(hipMalloc(&m->d_corr, sizeof(double) * max_fields * (size_t)n_esp));
   FE_HIP(hipMemcpy(m->d_esp, geo.esp.data(), sizeof(int4) * n_esp, hipMemcpyHostToDevice));
   std::vector<uint2> packed(n_esp);
+  std::vector<int32_t> lin(n_esp);
   for (int32_t q = 0; q < n_esp; ++q) {
     const int32_t* e = geo.esp.data() + 4 * (size_t)q;
     packed[q] = make_uint2((uint32_t)e[0] | ((uint32_t)e[1] << 16), (uint32_t)e[2]);
+    lin[q] = e[3];
   }
   FE_HIP(hipMemcpy(m->d_xyz, packed.data(), sizeof(uint2) * n_esp, hipMemcpyHostToDevice));
+  FE_HIP(hipMemcpy(m->d_lin, lin.data(), sizeof(int32_t) * n_esp, hipMemcpyHostToDevice));
   FE_HIP(hipMemcpy(m->d_tet, geo.tet.data(), sizeof(int4) * ntet, hipMemcpyHostToDevice));
   FE_HIP(hipMemcpy(m->d_bstart, bstart.data(), sizeof(int32_t) * bstart.size(), hipMemcpyHostToDevice));
   FE_HIP(hipMemcpy(m->d_blist, blist.data(), sizeof(int32_t) * blist.size(), hipMemcpyHostToDevice));
@@ -350,14 +367,13 @@ extern "C" int sgq_fe_reconstruct(sgq_fe_mesh* mesh, int32_t n_fields, const dou
   hipStream_t s = (hipStream_t)stream;
   hipError_t e = hipSetDevice(mesh->device);
   if (e != hipSuccess) return report_error(SGQ_EHIP, hipGetErrorString(e));
-  const int64_t nc = (int64_t)n_fields * mesh->n_esp;
-  hipLaunchKernelGGL(sgq::fe_corrector_kernel, dim3(sgq::fe_grid(nc)), dim3(sgq::kFeBlock), 0, s,
-                     mesh->d_esp, mesh->n_esp, n_fields, mesh->npts, esp_values, predictor,
-                     mesh->d_corr);
-  const dim3 grid(sgq::fe_grid_full(mesh->npts)), block(sgq::kFeBlock);
+  const dim3 cgrid(sgq::fe_grid(mesh->n_esp)), grid(sgq::fe_grid_full(mesh->npts)),
+      block(sgq::kFeBlock);
   switch (n_fields) {
 #define FE_CASE(F)                                                                               \
   case F:                                                                                        \
+    hipLaunchKernelGGL(sgq::fe_corrector_kernel<F>, cgrid, block, 0, s, mesh->d_lin,             \
+                       mesh->n_esp, mesh->npts, esp_values, predictor, mesh->d_corr);            \
     hipLaunchKernelGGL(sgq::fe_reconstruct_kernel<F>, grid, block, 0, s, mesh->d_xyz, mesh->d_tet, \
                        mesh->d_loc, mesh->n[0], mesh->n[1], mesh->npts, mesh->d_corr, predictor,  \
                        out);                                                                      \
