@@ -30,9 +30,12 @@ struct NodeState {
   int sx, sy, sz, ox, oy, oz, periodic, n, start, natoms, abort;
   int atom[kMaxNodeAtoms];
   int abox[kMaxNodeAtoms][3];       // local coordinates of the projector box corner
-  int aphase[kMaxNodeAtoms];        // 0: scatter with the parallel group, 1: alone
-  int grp[kMaxNodeAtoms];           // the parallel group, in atom order
-  int ngrp;
+  int aphase[kMaxNodeAtoms];        // scatter layer (0: the parallel group)
+  int grp[kMaxNodeAtoms];           // the atoms by layer, in atom order within a layer
+  unsigned short lstart[kMaxNodeAtoms + 1];   // layer L is grp[lstart[L], lstart[L + 1])
+  int nlayer;                       // layers, the group included
+  int lchange;                      // a layer changed in the last relaxation round
+  int ngrp;                         // atoms of the group (layer 0)
   int wcount[NW];
   T afrac[kMaxNodeAtoms][4];        // g0 h - R of each node atom (x, y, z): box offsets
   T acoef[kMaxNodeAtoms][4];        // E h^3 (chi . q): weights of the projector scatter
@@ -188,6 +191,8 @@ __device__ __noinline__ void node_setup(const LaunchParams& P, SGQ_L NodeState<T
     }
     st.n = st.sx * st.sy * st.sz;
     st.natoms = 0;
+    st.ngrp = 0;
+    st.nlayer = 0;
     st.abort = 0;
     st.fuse = 0;
   }
@@ -246,33 +251,79 @@ __device__ __noinline__ void node_setup(const LaunchParams& P, SGQ_L NodeState<T
     __syncthreads();
     return;
   }
-  // Scatter groups: an atom whose box overlaps no earlier atom's box joins the
-  // parallel group; the others are added one at a time, in atom order.
+  // Scatter layers: an atom whose box overlaps no earlier atom's box joins the parallel
+  // group (layer 0); any other atom takes the layer one above the highest layer among the
+  // earlier atoms whose boxes overlap its own.  No two atoms of a layer overlap, so each
+  // layer is scattered in parallel, and at every point the layers add their terms in atom
+  // order, as scattering the atoms one at a time would.  Where the grid is narrower than a
+  // box, a box overlaps itself: every atom is then scattered alone, by one thread.
   const int B = 2 * m + 1;
-  bool alias = st.periodic && (P.nx < B || P.ny < B || P.nz < B);
+  const bool alias = st.periodic && (P.nx < B || P.ny < B || P.nz < B);
+  auto overlap = [&](int a, int b) {
+    for (int ax = 0; ax < 3; ++ax) {
+      int d = st.abox[a][ax] - st.abox[b][ax];
+      if (st.periodic) {
+        int nax = nn[ax];
+        d = wrap_index(d, nax);
+        d = d > nax / 2 ? nax - d : d;
+      }
+      if (abs(d) > 2 * m) return false;
+    }
+    return true;
+  };
   for (int a = tid; a < st.natoms; a += BLOCK) {
     int ph = alias ? 1 : 0;
-    for (int b = 0; b < a && ph == 0; ++b) {
-      bool ov = true;
-      for (int ax = 0; ax < 3; ++ax) {
-        int d = st.abox[a][ax] - st.abox[b][ax];
-        if (st.periodic) {
-          int nax = nn[ax];
-          d = wrap_index(d, nax);
-          d = d > nax / 2 ? nax - d : d;
-        }
-        if (abs(d) > 2 * m) ov = false;
-      }
-      if (ov) ph = 1;
-    }
+    for (int b = 0; b < a && ph == 0; ++b)
+      if (overlap(a, b)) ph = 1;
     st.aphase[a] = ph;
   }
   __syncthreads();
+  if (!alias) {
+    // rounds of L(a) = 1 + max L(b) over the overlapping earlier atoms b, each from the
+    // layers of the round before; the layers only grow, and a round that changes none has
+    // reached the (unique) solution
+    constexpr int IT = (kMaxNodeAtoms + BLOCK - 1) / BLOCK;
+    for (;;) {
+      int nl[IT];
+#pragma unroll
+      for (int i = 0; i < IT; ++i) {
+        const int a = tid + i * BLOCK;
+        int L = 0;
+        if (a < st.natoms && st.aphase[a]) {
+          L = 1;
+          for (int b = 0; b < a; ++b)
+            if (st.aphase[b] >= L && overlap(a, b)) L = st.aphase[b] + 1;
+        }
+        nl[i] = L;
+      }
+      __syncthreads();
+      if (tid == 0) st.lchange = 0;
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < IT; ++i) {
+        const int a = tid + i * BLOCK;
+        if (a < st.natoms && nl[i] != st.aphase[a]) {
+          st.aphase[a] = nl[i];
+          st.lchange = 1;
+        }
+      }
+      __syncthreads();
+      if (!st.lchange) break;
+    }
+  }
   if (threadIdx.x == 0) {
-    int c = 0;
-    for (int a = 0; a < st.natoms; ++a)
-      if (!st.aphase[a]) st.grp[c++] = a;
-    st.ngrp = c;
+    // counting sort of the atoms by layer, stable in atom order
+    int nlay = 0;
+    for (int a = 0; a < st.natoms; ++a) nlay = max(nlay, st.aphase[a] + 1);
+    for (int L = 0; L <= nlay; ++L) st.lstart[L] = 0;
+    for (int a = 0; a < st.natoms; ++a) ++st.lstart[st.aphase[a] + 1];
+    for (int L = 0; L < nlay; ++L) st.lstart[L + 1] += st.lstart[L];
+    for (int a = 0; a < st.natoms; ++a) st.grp[st.lstart[st.aphase[a]]++] = a;
+    // lstart[L] now ends layer L: shift to the starts
+    for (int L = nlay - 1; L >= 1; --L) st.lstart[L] = st.lstart[L - 1];
+    st.lstart[0] = 0;
+    st.nlayer = nlay;
+    st.ngrp = nlay > 0 ? st.lstart[1] : 0;
   }
   __syncthreads();
   if constexpr (NodeState<T, BLOCK>::kFuse) {
@@ -572,63 +623,36 @@ __device__ __noinline__ void projector_dots(const SGQ_G double* proj_E,
   }
 }
 
-// u += sum_l chi_l E_l h^3 (chi_l . q) over the box of atom a: `lanes` threads starting
-// at `first` cover its box points (lanes == 1: one point at a time, for grids narrower
-// than the box where box points alias).
+// u += sum_l chi_l E_l h^3 (chi_l . q) over the box of atom a, one point at a time by the
+// calling thread (grids narrower than the box, where box points alias).
 template <typename T, int BLOCK>
 __device__ __noinline__ void scatter_atom(SGQ_L NodeState<T, BLOCK>& st, ProjEval<T> pe,
-                                          SGQ_G T* U, int a, int B, int B3, int first,
-                                          int lanes) {
+                                          SGQ_G T* U, int a, int B, int B3) {
   const T coef[4] = {st.acoef[a][0], st.acoef[a][1], st.acoef[a][2], st.acoef[a][3]};
-  if (lanes == 1) {
-    for (int b = 0; b < B3; ++b) {
-      const int bx = b % B, by = (b / B) % B, bz = b / (B * B);
-      int lp = box_point(st, a, bx, by, bz);
-      if (lp < 0) continue;
-      T c[4];
-      chi_at(pe, st.afrac[a], bx, by, bz, c);
-      U[lp] += c[0] * coef[0] + c[1] * coef[1] + c[2] * coef[2] + c[3] * coef[3];
-    }
-    return;
-  }
-  constexpr int UNR = 6;
-  for (int b0 = first; b0 < B3; b0 += UNR * lanes) {
-    int lp[UNR], bc[UNR][3];
-    T old[UNR];
-#pragma unroll
-    for (int u = 0; u < UNR; ++u) {
-      const int b = b0 + u * lanes;
-      bc[u][0] = b % B;
-      bc[u][1] = (b / B) % B;
-      bc[u][2] = b / (B * B);
-      lp[u] = b < B3 ? box_point(st, a, bc[u][0], bc[u][1], bc[u][2]) : -1;
-      old[u] = U[lp[u] >= 0 ? lp[u] : 0];
-    }
-#pragma unroll
-    for (int u = 0; u < UNR; ++u) {
-      if (lp[u] >= 0) {
-        T c[4];
-        chi_at(pe, st.afrac[a], bc[u][0], bc[u][1], bc[u][2], c);
-        U[lp[u]] = old[u] + (c[0] * coef[0] + c[1] * coef[1] + c[2] * coef[2] + c[3] * coef[3]);
-      }
-    }
+  for (int b = 0; b < B3; ++b) {
+    const int bx = b % B, by = (b / B) % B, bz = b / (B * B);
+    int lp = box_point(st, a, bx, by, bz);
+    if (lp < 0) continue;
+    T c[4];
+    chi_at(pe, st.afrac[a], bx, by, bz, c);
+    U[lp] += c[0] * coef[0] + c[1] * coef[1] + c[2] * coef[2] + c[3] * coef[3];
   }
 }
 
-// The parallel scatter group: atoms whose boxes overlap no earlier atom's box, so their
+// One scatter layer, the atoms st.grp[first, end): their boxes are disjoint, so their
 // updates never touch the same point.  A wave takes NA of them per round with all the
 // loads of the round issued before any update.
 template <typename T, int BLOCK>
 __device__ __noinline__ void scatter_group(SGQ_L NodeState<T, BLOCK>& st, ProjEval<T> pe,
-                                           SGQ_G T* U, int B, int B3) {
+                                           SGQ_G T* U, int B, int B3, int first, int end) {
   constexpr int NW = BLOCK / kWave;
   constexpr int NA = sizeof(T) == 4 ? 3 : 1;
   constexpr int UNR = 6;    // 6 x 64 box points cover the 7^3 box of h = rc/3
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-  // atoms of the group (st.grp, in atom order) dealt round-robin to the waves
-  const int ngrp = st.ngrp;
-  const int cnt = ngrp > wave ? (ngrp - wave + NW - 1) / NW : 0;
-  auto mine = [&](int i) { return st.grp[wave + NW * i]; };
+  // the layer's atoms (in atom order) dealt round-robin to the waves
+  const int na = end - first;
+  const int cnt = na > wave ? (na - wave + NW - 1) / NW : 0;
+  auto mine = [&](int i) { return st.grp[first + wave + NW * i]; };
   for (int i0 = 0; i0 < cnt; i0 += NA) {
     for (int b0 = 0; b0 < B3; b0 += UNR * kWave) {
       int bc[UNR][3];
@@ -933,25 +957,26 @@ __device__ __forceinline__ double apply_local(const LaunchParams& P, SGQ_L NodeS
 }
 
 // u += V_nl v with the weights st.acoef: the parallel group (unless the march added it,
-// `group` false) and then the remaining atoms one at a time, in atom order.
+// `group` false), then the other scatter layers in order, each in parallel.
 template <typename T, int BLOCK>
 __device__ __forceinline__ void apply_scatter(const LaunchParams& P, SGQ_L NodeState<T, BLOCK>& st,
                                               ProjEval<T> pe, SGQ_G T* U, int B, int B3,
                                               bool group = true) {
-  const int tid = threadIdx.x;
   if (st.natoms == 0) return;
   if (group) {
-    scatter_group<T, BLOCK>(st, pe, U, B, B3);
+    scatter_group<T, BLOCK>(st, pe, U, B, B3, 0, st.ngrp);
     __syncthreads();
   }
-  const bool alias = st.periodic && (P.nx < B || P.ny < B || P.nz < B);
-  for (int a = 0; a < st.natoms; ++a) {
-    if (!st.aphase[a]) continue;
-    if (alias) {
-      if (tid == 0) scatter_atom<T, BLOCK>(st, pe, U, a, B, B3, 0, 1);
-    } else {
-      scatter_atom<T, BLOCK>(st, pe, U, a, B, B3, tid, BLOCK);
+  if (st.periodic && (P.nx < B || P.ny < B || P.nz < B)) {
+    for (int a = 0; a < st.natoms; ++a) {
+      if (!st.aphase[a]) continue;
+      if (threadIdx.x == 0) scatter_atom<T, BLOCK>(st, pe, U, a, B, B3);
+      __syncthreads();
     }
+    return;
+  }
+  for (int L = 1; L < st.nlayer; ++L) {
+    scatter_group<T, BLOCK>(st, pe, U, B, B3, st.lstart[L], st.lstart[L + 1]);
     __syncthreads();
   }
 }
