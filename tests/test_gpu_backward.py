@@ -388,3 +388,37 @@ def test_every_reverse_path_in_one_plan():
     errs = _rel(fwd[0], rdV), _rel(fwd[1], rdR), _rel(fwd[2], rdE)
     print("mixed-path grad errs after a forward", errs)
     assert max(errs) < 1e-4
+
+
+@pytest.mark.parametrize("precision,tol", [("f32", 1e-4), ("f64", 1e-6)])
+def test_chained_projector_boxes(precision, tol):
+    """Projector atoms whose boxes overlap in long chains, so the scatter of the atoms
+    outside the parallel group runs in many layers: 24 atoms one grid point apart on a line
+    (each box overlaps the six before it, one layer per atom) and a 3 x 3 x 3 cluster 1.5
+    grid points apart (27 boxes that all overlap), both inside the cubes of two nodes on a
+    32^3 grid.  Density, rule depth and every adjoint output against the oracle."""
+    import dataclasses
+    from gpu_util import gpu_rho
+    N, h = 32, 0.5
+    rng = np.random.default_rng(9)
+    line = [[(4 + i) * h + 0.1, 16 * h + 0.13, 16 * h - 0.07] for i in range(24)]
+    cluster = [[(8 + 1.5 * a) * h + 0.05, (8 + 1.5 * b) * h, (24 + 1.5 * c) * h - 0.1]
+               for a in range(3) for b in range(3) for c in range(3)]
+    atoms = np.array(line + cluster)
+    E = rng.uniform(-0.5, 0.5, size=(atoms.shape[0], 4))
+    P = custom_problem(N, h=h, atoms=atoms, proj_E=E, v_loc=smooth_random_potential(N, 5, 0.3),
+                       centers=[lin(16, 16, 16, N), lin(10, 10, 22, N)], half_width=8,
+                       depth=16, mu=0.0, kT=0.1)
+    P = dataclasses.replace(P, precision=precision)
+    ref_rho, ref_k = O.rho_quadrature(P)
+    rdV, rdE, rdR = O.band_energy_backward(P, kind=O.FREE)
+    announce(f"chained projector boxes {precision}: density")
+    rho, ke, status = gpu_rho(P)
+    assert status == 0
+    assert np.array_equal(ke, ref_k)
+    assert O.normwise_rel_err(rho, ref_rho) < tol
+    announce(f"chained projector boxes {precision}: adjoint")
+    dV, dR, dE = _gpu_grad(P, O.FREE, precision)
+    errs = _rel(dV, rdV), _rel(dR, rdR), _rel(dE, rdE)
+    print("chained-box errs", precision, errs)
+    assert max(errs) < tol
