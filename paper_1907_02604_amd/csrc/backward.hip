@@ -163,6 +163,21 @@ __device__ __noinline__ void projector_gradients(const SGQ_G double* proj_E,
   }
 }
 
+// A wave-uniform value moved to scalar registers (arguments of a non-inlined call arrive
+// in vector registers, where the fields of RevStep would stay for the whole march).
+template <typename X>
+__device__ __forceinline__ X to_sgpr(X v) {
+  static_assert(sizeof(X) % 4 == 0, "whole dwords");
+  union {
+    X x;
+    int i[sizeof(X) / 4];
+  } u;
+  u.x = v;
+#pragma unroll
+  for (int k = 0; k < (int)(sizeof(X) / 4); ++k) u.i[k] = __builtin_amdgcn_readfirstlane(u.i[k]);
+  return u.x;
+}
+
 // Projector terms of step j of the fused reverse recurrence, for
 // ubar_j = ib qbar_{j+1} + bb q_{j+1} + ahat q_j.  For every node atom the sixteen box sums
 // m_r(v) = phi_r . v, phi = [chi_0..3 ; d chi_l / d d_a] (the functions of the projector
@@ -241,31 +256,37 @@ __device__ __noinline__ void ubar_coefs(SGQ_L NodeState<T, BLOCK>& st, ProjEval<
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
+    // every lane reads the totals (one broadcast LDS read each, all in flight together)
+    // and the atom's energies (one uniform address each), so that lane 0 below works from
+    // registers instead of a chain of dependent reads
+    const int J = to_sgpr(st.atom[a]);
+    double El[4], mq[16], mu[16];
+#pragma unroll
+    for (int l = 0; l < 4; ++l) El[l] = proj_E[4 * J + l];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      mq[r] = sc * ws[r];                                                        // m_r(q_j)
+      double v = ahat * mq[r];                                                   // m_r(ubar_j)
+      if (!last) v += ib * ws[16 + r] + bb * (double)cq[a][r];
+      mu[r] = v;
+    }
     if (lane == 0) {
-      const int J = st.atom[a];
-      auto mq = [&](int r) { return sc * ws[r]; };                              // m_r(q_j)
-      auto mu = [&](int r) {                                                    // m_r(ubar_j)
-        double v = ahat * mq(r);
-        if (!last) v += ib * ws[16 + r] + bb * (double)cq[a][r];
-        return v;
-      };
       double rb[3] = {0.0, 0.0, 0.0};
 #pragma unroll
       for (int l = 0; l < 4; ++l) {
-        const double El = proj_E[4 * J + l];
-        const double mql = mq(l), mul = mu(l);
-        st.acoef[a][l] = (T)(El * h3 * mul);
+        const double mql = mq[l], mul = mu[l];
+        st.acoef[a][l] = (T)(El[l] * h3 * mul);
         ws[32 + 7 * t + l] = h3 * mul * mql;
 #pragma unroll
         for (int ax = 0; ax < 3; ++ax) {
           const int ra = 4 + 3 * l + ax;
-          rb[ax] -= h3 * El * (mu(ra) * mql + mul * mq(ra));
+          rb[ax] -= h3 * El[l] * (mu[ra] * mql + mul * mq[ra]);
         }
       }
 #pragma unroll
       for (int ax = 0; ax < 3; ++ax) ws[32 + 7 * t + 4 + ax] = rb[ax];
 #pragma unroll
-      for (int r = 0; r < 16; ++r) cq[a][r] = (T)mq(r);
+      for (int r = 0; r < 16; ++r) cq[a][r] = (T)mq[r];
     }
     // ws[0, 32) is rewritten for the next atom only after lane 0 has read it
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -354,21 +375,6 @@ __device__ __forceinline__ T ld_off(const SGQ_G T* base, int i) {
 template <typename T>
 __device__ __forceinline__ void st_off(SGQ_G T* base, int i, T v) {
   *(SGQ_G T*)((SGQ_G char*)base + (unsigned)i * (unsigned)sizeof(T)) = v;
-}
-
-// A wave-uniform value moved to scalar registers (arguments of a non-inlined call arrive
-// in vector registers, where the fields of RevStep would stay for the whole march).
-template <typename X>
-__device__ __forceinline__ X to_sgpr(X v) {
-  static_assert(sizeof(X) % 4 == 0, "whole dwords");
-  union {
-    X x;
-    int i[sizeof(X) / 4];
-  } u;
-  u.x = v;
-#pragma unroll
-  for (int k = 0; k < (int)(sizeof(X) / 4); ++k) u.i[k] = __builtin_amdgcn_readfirstlane(u.i[k]);
-  return u.x;
 }
 
 // One reversed step of the recurrence as a single march through the z planes of a
