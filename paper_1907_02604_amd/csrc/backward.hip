@@ -246,14 +246,28 @@ __device__ __noinline__ void ubar_coefs(SGQ_L NodeState<T, BLOCK>& st, ProjEval<
   };
   // the sums of atom a (batch slot t) are complete: its weights, its step terms, the carry
   auto finish = [&](int a, int t, const T (&aw)[16], const T (&aq)[16]) {
+    // the 32 wave totals by a transposed reduction: at each offset o = 32 .. 2 a lane keeps
+    // half of its partial sums (the upper half when lane & o) and adds its partner's
+    // partial of the same ones, so total q ends in lanes 2q and 2q + 1 after 31 exchanges
+    // of one value, against 6 per total for a butterfly of each
+    T v[32];
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-      const T sw = wave_sum(aw[r]), sq = wave_sum(aq[r]);
-      if (lane == 0) {
-        ws[r] = (double)sw;
-        ws[16 + r] = (double)sq;
+      v[r] = aw[r];
+      v[16 + r] = aq[r];
+    }
+#pragma unroll
+    for (int h = 16, o = 32; h >= 1; h >>= 1, o >>= 1) {
+      const bool up = (lane & o) != 0;
+#pragma unroll
+      for (int i = 0; i < h; ++i) {
+        const T give = up ? v[i] : v[i + h];
+        const T keep = up ? v[i + h] : v[i];
+        v[i] = keep + __shfl_xor(give, o, kWave);
       }
     }
+    v[0] += __shfl_xor(v[0], 1, kWave);
+    if ((lane & 1) == 0) ws[lane >> 1] = (double)v[0];   // ws[r]: q_j terms, ws[16 + r]: qbar
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
     // every lane reads the totals (one broadcast LDS read each, all in flight together)
