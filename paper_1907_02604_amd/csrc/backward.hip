@@ -248,8 +248,8 @@ __device__ __noinline__ void ubar_coefs(SGQ_L NodeState<T, BLOCK>& st, ProjEval<
   auto finish = [&](int a, int t, const T (&aw)[16], const T (&aq)[16]) {
     // the 32 wave totals by a transposed reduction: at each offset o = 32 .. 2 a lane keeps
     // half of its partial sums (the upper half when lane & o) and adds its partner's
-    // partial of the same ones, so total q ends in lanes 2q and 2q + 1 after 31 exchanges
-    // of one value, against 6 per total for a butterfly of each
+    // partial of the same ones; a last exchange at offset 1 leaves total q in lanes 2q and
+    // 2q + 1: 32 exchanges of one value, against 6 per total for a butterfly of each
     T v[32];
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
@@ -280,9 +280,9 @@ __device__ __noinline__ void ubar_coefs(SGQ_L NodeState<T, BLOCK>& st, ProjEval<
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       mq[r] = sc * ws[r];                                                        // m_r(q_j)
-      double v = ahat * mq[r];                                                   // m_r(ubar_j)
-      if (!last) v += ib * ws[16 + r] + bb * (double)cq[a][r];
-      mu[r] = v;
+      double m = ahat * mq[r];                                                   // m_r(ubar_j)
+      if (!last) m += ib * ws[16 + r] + bb * (double)cq[a][r];
+      mu[r] = m;
     }
     if (lane == 0) {
       double rb[3] = {0.0, 0.0, 0.0};
@@ -302,7 +302,7 @@ __device__ __noinline__ void ubar_coefs(SGQ_L NodeState<T, BLOCK>& st, ProjEval<
 #pragma unroll
       for (int r = 0; r < 16; ++r) cq[a][r] = (T)mq[r];
     }
-    // ws[0, 32) is rewritten for the next atom only after lane 0 has read it
+    // ws[0, 32) is rewritten for the next atom only after every lane has read it
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
   };
