@@ -901,7 +901,11 @@ __device__ __noinline__ double stencil_march(int gnx, int gny, int gnz,
   return apart;
 }
 
-// The same operator on the whole periodic grid (untruncated nodes).
+// The same operator on the whole periodic grid (untruncated nodes), UNR points per thread
+// with every load issued unconditionally (points past the end read point 0 and store
+// nothing), in the same order of operations per point.  A neighbour coordinate c +- d
+// (d <= 3) wraps with one conditional add or subtract on an axis longer than 3 points, and
+// by the full remainder on a shorter one.
 template <typename T, int BLOCK, bool ACC = false>
 __device__ __noinline__ double stencil_periodic(const SGQ_L NodeState<T, BLOCK>& st,
                                                 const SGQ_G T* __restrict__ V,
@@ -910,24 +914,43 @@ __device__ __noinline__ double stencil_periodic(const SGQ_L NodeState<T, BLOCK>&
   const int n = st.n, sx = st.sx, sy = st.sy, sz = st.sz, sxy = sx * sy;
   const float inv_sx = 1.0f / (float)sx, inv_sxy = 1.0f / (float)sxy;
   const T wd[4] = {(T)0, (T)kFd1, (T)kFd2, (T)kFd3};
+  const bool fx = sx > 3, fy = sy > 3, fz = sz > 3;
+  auto wrap = [](int v, int m, bool fast) {
+    return fast ? (v < 0 ? v + m : (v >= m ? v - m : v)) : wrap_index(v, m);
+  };
+  constexpr int UNR = sizeof(T) == 4 ? 4 : 2;
   double apart = 0.0;
-  for (int p = threadIdx.x; p < n; p += BLOCK) {
-    int x, y, z;
-    unflatten(p, sx, sxy, inv_sx, inv_sxy, x, y, z);
-    T wc = Wj[bidx(p, vbs)];
-    T lap = (T)0;
-    for (int d = 1; d <= 3; ++d) {
-      // neighbour minus centre, as in the cube forms
-      lap += wd[d] * ((Wj[bidx(wrap_index(x - d, sx) + sx * (y + sy * z), vbs)] - wc) +
-                      (Wj[bidx(wrap_index(x + d, sx) + sx * (y + sy * z), vbs)] - wc));
-      lap += wd[d] * ((Wj[bidx(x + sx * (wrap_index(y - d, sy) + sy * z), vbs)] - wc) +
-                      (Wj[bidx(x + sx * (wrap_index(y + d, sy) + sy * z), vbs)] - wc));
-      lap += wd[d] * ((Wj[bidx(x + sx * (y + sy * wrap_index(z - d, sz)), vbs)] - wc) +
-                      (Wj[bidx(x + sx * (y + sy * wrap_index(z + d, sz)), vbs)] - wc));
+  for (int base = threadIdx.x; base < n; base += UNR * BLOCK) {
+    T u[UNR], wc[UNR];
+#pragma unroll
+    for (int k = 0; k < UNR; ++k) {
+      const int p = base + k * BLOCK;
+      const int pc = p < n ? p : 0;
+      int x, y, z;
+      unflatten(pc, sx, sxy, inv_sx, inv_sxy, x, y, z);
+      const T c = Wj[bidx(pc, vbs)];
+      wc[k] = c;
+      T lap = (T)0;
+#pragma unroll
+      for (int d = 1; d <= 3; ++d) {
+        // neighbour minus centre, as in the cube forms
+        lap += wd[d] * ((Wj[bidx(wrap(x - d, sx, fx) + sx * (y + sy * z), vbs)] - c) +
+                        (Wj[bidx(wrap(x + d, sx, fx) + sx * (y + sy * z), vbs)] - c));
+        lap += wd[d] * ((Wj[bidx(x + sx * (wrap(y - d, sy, fy) + sy * z), vbs)] - c) +
+                        (Wj[bidx(x + sx * (wrap(y + d, sy, fy) + sy * z), vbs)] - c));
+        lap += wd[d] * ((Wj[bidx(x + sx * (y + sy * wrap(z - d, sz, fz)), vbs)] - c) +
+                        (Wj[bidx(x + sx * (y + sy * wrap(z + d, sz, fz)), vbs)] - c));
+      }
+      u[k] = sj * (kin * lap + V[pc] * c);
     }
-    T u = sj * (kin * lap + V[p] * wc);
-    if (ACC) U[p] += u; else U[p] = u;
-    apart += (double)(sj * wc) * (double)u;
+#pragma unroll
+    for (int k = 0; k < UNR; ++k) {
+      const int p = base + k * BLOCK;
+      if (p < n) {
+        if (ACC) U[p] += u[k]; else U[p] = u[k];
+        apart += (double)(sj * wc[k]) * (double)u[k];
+      }
+    }
   }
   return apart;
 }
