@@ -369,8 +369,10 @@ int sgq_plan_set_graph(sgq_plan* plan, int enable);
 /* Launch-shape autotuner.  Times the candidate shapes of the persistent forward kernel
  * (lanes per node: 128, 256 or 512; resident workgroups per CU: 1 to 3; FP64 plans use 256
  * lanes) on `sample_nodes` nodes drawn evenly from the plan's cost-sorted node list, with
- * the given inputs (same meaning as rho_quadrature), and keeps the fastest for the plan.
- * The choice is cached per problem shape (device, precision, cube size, depth, projector
+ * the given inputs (same meaning as rho_quadrature), and keeps the fastest for the plan:
+ * three timed rounds over all candidates after a warm-up round, each candidate's best
+ * round counting, and the default shape (256 lanes, two workgroups per CU) kept unless
+ * another is more than 1 % faster.  The choice is cached per problem shape (device, precision, cube size, depth, projector
  * box) for the process and, when the environment variable SGQ_TUNE_CACHE names a file,
  * appended to that file and read from it by later processes.  May grow the plan's
  * workspace (SGQ_ENOMEM if that fails).  Synchronous on `stream`.
