@@ -422,3 +422,35 @@ def test_chained_projector_boxes(precision, tol):
     errs = _rel(dV, rdV), _rel(dR, rdR), _rel(dE, rdE)
     print("chained-box errs", precision, errs)
     assert max(errs) < tol
+
+
+@pytest.mark.parametrize("precision,tol", [("f32", 1e-4), ("f64", 1e-6)])
+def test_projector_boxes_over_one_round(precision, tol):
+    """A grid spacing of 0.4 bohr makes the projector box 9^3 = 729 points, more than the
+    6 x 64 box points one round of the adjoint's box sums covers, so the sums take the path
+    that goes over each atom's box in several rounds.  Two 13^3 nodes centred on atoms of
+    a 24^3 grid with 10 projector atoms: density, rule depth and every adjoint output
+    against the oracle."""
+    import dataclasses
+    from gpu_util import gpu_rho
+    N, h = 24, 0.4
+    rng = np.random.default_rng(4)
+    atoms = rng.uniform(0, N * h, size=(10, 3))
+    E = rng.uniform(-0.6, 0.6, size=(10, 4))
+    g = np.rint(atoms[:2] / h).astype(int) % N
+    P = custom_problem(N, h=h, atoms=atoms, proj_E=E, v_loc=smooth_random_potential(N, 7, 0.3),
+                       centers=[lin(*g[0], N), lin(*g[1], N)], half_width=6, depth=12,
+                       mu=0.3, kT=0.1)
+    P = dataclasses.replace(P, precision=precision)
+    ref_rho, ref_k = O.rho_quadrature(P)
+    rdV, rdE, rdR = O.band_energy_backward(P, kind=O.FREE)
+    announce(f"projector boxes of 9^3 {precision}: density")
+    rho, ke, status = gpu_rho(P)
+    assert status == 0
+    assert np.array_equal(ke, ref_k)
+    assert O.normwise_rel_err(rho, ref_rho) < tol
+    announce(f"projector boxes of 9^3 {precision}: adjoint")
+    dV, dR, dE = _gpu_grad(P, O.FREE, precision)
+    errs = _rel(dV, rdV), _rel(dR, rdR), _rel(dE, rdE)
+    print("9^3-box errs", precision, errs)
+    assert max(errs) < tol
